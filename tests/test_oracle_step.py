@@ -1,0 +1,225 @@
+"""Pins of the oracle's fixed-grid two-layer step: lake at rest, per-layer mass
+with walls, the Stoker dam break (lower layer dry), linear wave speeds, mirror
+symmetry and the reduction to one dimension."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import oracle
+from paper_1803_01450_amd import inputs
+
+G = 9.81
+
+
+def dt_rule(q, dx, cfl=0.9):
+    h1, h2 = q[0], q[3]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = np.where(h1 > 0, np.maximum(np.abs(q[1]), np.abs(q[2])) / np.where(h1 > 0, h1, 1), 0)
+        u2 = np.where(h2 > 0, np.maximum(np.abs(q[4]), np.abs(q[5])) / np.where(h2 > 0, h2, 1), 0)
+    s = np.maximum(u, u2) + np.sqrt(G * (h1 + h2))
+    return cfl * dx / s.max()
+
+
+def lake(B, eta1=0.0, eta2=-200.0):
+    return inputs.state_from_surfaces(np.full(B.shape, eta1), np.full(B.shape, eta2), B)
+
+
+@pytest.mark.parametrize("variant", ["wet", "interface_dry", "land"])
+def test_lake_at_rest(variant):
+    """Flat surfaces over arbitrary bathymetry stay at rest: momenta <= 1e-9 m^2/s
+    and depth changes <= 1e-10 m after 100 steps (not exactly zero because the
+    surfaces are recomputed as B + h2 + h1 and round)."""
+    c = inputs.fixed_small()
+    B = c["B"].copy()
+    if variant == "interface_dry":
+        B = -150.0 + (B - B.min()) / (B.max() - B.min()) * 140.0    # -150 .. -10 under eta2 = -100
+        q = lake(B, 0.0, -100.0)
+        assert (q[3] == 0).any() and (q[3] > 0).any()
+    elif variant == "land":
+        B = -300.0 + (B - B.min()) / (B.max() - B.min()) * 350.0    # -300 .. +50
+        q = lake(B, 0.0, -100.0)
+        assert (q[0] == 0).any() and (q[3] > 0).any()
+    else:
+        q = lake(B)
+    dt = dt_rule(q, c["dx"])
+    qn, sm, cnt = oracle.fixed_steps(B, q, c["dx"], c["dx"], [dt] * 100, r=0.95)
+    for f in (1, 2, 4, 5):
+        assert np.abs(qn[f]).max() <= 1e-9, (variant, f, np.abs(qn[f]).max())
+    for f in (0, 3):
+        assert np.abs(qn[f] - q[f]).max() <= 1e-10
+    assert cnt[1] == 0 and cnt[2] == 0
+
+
+def _mass_run(B, q, dx, n):
+    m0 = [math.fsum(q[0].ravel()), math.fsum(q[3].ravel())]
+    dt = dt_rule(q, dx)
+    qn, sm, cnt = oracle.fixed_steps(B, q, dx, dx, [dt] * n, r=0.95)
+    m1 = [math.fsum(qn[0].ravel()), math.fsum(qn[3].ravel())]
+    return m0, m1, cnt, qn
+
+
+def test_mass_conservation_with_walls():
+    """Per-layer mass plus clipped mass is conserved to 1e-13 relative per 100
+    steps (walls let nothing through)."""
+    c = inputs.fixed_small()
+    m0, m1, cnt, qn = _mass_run(c["B"], c["q"], c["dx"], 100)
+    assert cnt[1] == 0
+    for k in range(2):
+        assert abs(m1[k] - m0[k]) <= 1e-13 * m0[k]
+
+
+def test_mass_conservation_wet_dry():
+    """Same accounting with shorelines: the pulse runs up land, thin layers are
+    clipped; M(t) + clipped(t) = M(0)."""
+    c = inputs.fixed_small()
+    B = -300.0 + (c["B"] - c["B"].min()) / (c["B"].max() - c["B"].min()) * 302.0
+    eta1 = inputs.gaussian(64, c["L"], (30e3, 50e3), 8e3, 3.0)
+    q = inputs.state_from_surfaces(eta1, np.full(B.shape, -100.0), B)
+    m0, m1, cnt, qn = _mass_run(B, q, c["dx"], 200)
+    assert cnt[1] > 0   # the test exercises clipping
+    assert abs((m1[0] + cnt[3]) - m0[0]) <= 1e-12 * m0[0]
+    assert abs((m1[1] + cnt[4]) - m0[1]) <= 1e-12 * m0[1]
+    # wet ordering holds everywhere
+    assert not np.any((qn[0] == 0) & (qn[3] > 0))
+    assert np.all(qn[0] >= 0) and np.all(qn[3] >= 0)
+
+
+def stoker_exact(x, t, x0, hL, hR):
+    cL = math.sqrt(G * hL)
+    f = lambda hm: 2 * (cL - math.sqrt(G * hm)) - (hm - hR) * math.sqrt(G * (hm + hR) / (2 * hm * hR))
+    hm = brentq(f, hR, hL)
+    um = 2 * (cL - math.sqrt(G * hm))
+    S = hm * um / (hm - hR)
+    xi = (x - x0) / t
+    h = np.where(xi < -cL, hL, 0.0)
+    fan = (xi >= -cL) & (xi <= um - math.sqrt(G * hm))
+    h = np.where(fan, (2 * cL - xi) ** 2 / (9 * G), h)
+    h = np.where((xi > um - math.sqrt(G * hm)) & (xi < S), hm, h)
+    h = np.where(xi >= S, hR, h)
+    return h, hm, um, S
+
+
+def _stoker_run(n):
+    L = 100e3
+    dx = L / n
+    x = (np.arange(n) + 0.5) * dx
+    B = np.zeros((1, n))
+    q = np.zeros((6, 1, n))
+    q[0, 0] = np.where(x < L / 2, 200.0, 100.0)
+    T = 800.0
+    dt0 = 0.9 * dx / (math.sqrt(G * 200.0) + 20.0)
+    nst = int(math.ceil(T / dt0))
+    dts = [T / nst] * nst
+    qn, sm, cnt = oracle.fixed_steps(B, q, dx, dx, dts, r=0.95)
+    h_ex, hm, um, S = stoker_exact(x, T, L / 2, 200.0, 100.0)
+    err = np.abs(qn[0, 0] - h_ex).sum() * dx / (L * 100.0)
+    return err, hm, um, S, qn
+
+
+def test_stoker_dam_break_lower_layer_dry():
+    """Single-layer branch (h2 = 0, flat bottom): the Stoker solution with
+    h_m = 145.38 m, u_m = 13.06 m/s, shock speed 41.83 m/s; L1 error <= 1% at
+    1000 cells and decreasing under refinement."""
+    e1, hm, um, S, qn = _stoker_run(1000)
+    assert abs(hm - 145.38) < 0.01 and abs(um - 13.06) < 0.01 and abs(S - 41.83) < 0.01
+    assert e1 <= 0.01
+    e0, *_ = _stoker_run(500)
+    assert e1 < e0
+    assert np.all(qn[3] == 0.0)
+
+
+def _mode_speed(which):
+    """Flat channel h1 = 200, h2 = 3800, r = 0.95, at rest; a small Gaussian
+    perturbation along the exact right-going linear eigenvector of the external or
+    internal mode (speed l, (dh1, dm1, dh2, dm2) = (1, l, a, a l), a = (l^2 - g h1)
+    / (g h1)); the speed of its centroid over a time interval."""
+    h1, h2, r = 200.0, 3800.0, 0.95
+    H = h1 + h2
+    disc = math.sqrt(H * H - 4 * (1 - r) * h1 * h2)
+    lam = math.sqrt(G * (H + disc) / 2) if which == "external" else math.sqrt(G * (H - disc) / 2)
+    al = (lam * lam - G * h1) / (G * h1)
+    n, L = 800, 400e3
+    dx = L / n
+    x = (np.arange(n) + 0.5) * dx
+    x0 = 100e3
+    amp = 1e-4 if which == "external" else 1e-2
+    pert = amp * np.exp(-((x - x0) ** 2) / (2 * (8e3) ** 2))
+    B = np.full((1, n), -4000.0)
+    q = np.zeros((6, 1, n))
+    q[0, 0] = h1 + pert
+    q[1, 0] = lam * pert
+    q[3, 0] = h2 + al * pert
+    q[4, 0] = al * lam * pert
+    T1, T2 = (200.0, 800.0) if which == "external" else (2000.0, 8000.0)
+    dt = 0.9 * dx / 200.0
+    n1 = int(round(T1 / dt)); n2 = int(round(T2 / dt))
+    qa, *_ = oracle.fixed_steps(B, q, dx, dx, [dt] * n1, r=r)
+    qb, *_ = oracle.fixed_steps(B, qa, dx, dx, [dt] * (n2 - n1), r=r)
+
+    def centroid(qq):
+        d = qq[0, 0] - h1
+        return (d * x).sum() / d.sum()
+    return (centroid(qb) - centroid(qa)) / (n2 * dt - n1 * dt), lam
+
+
+def test_linear_wave_speeds():
+    """Small pulses on the exact linear eigenvectors travel at the roots of
+    l^4 - g(h1+h2) l^2 + g^2 (1-r) h1 h2 (197.855 and 9.6653 m/s for h1 = 200,
+    h2 = 3800, r = 0.95) within 0.5%; the solver's speeds approximate them to
+    first order in (1-r), 0.12% here."""
+    for which in ("external", "internal"):
+        c, lam = _mode_speed(which)
+        assert abs(c - lam) / lam < 0.005, (which, c, lam)
+
+
+def test_mirror_symmetry_x():
+    """Mirroring the data in x (and negating the x momenta) mirrors the solution
+    to roundoff."""
+    c = inputs.fixed_small()
+    B, q, dx = c["B"], c["q"].copy(), c["dx"]
+    rng = np.random.default_rng(9)
+    q[1] = rng.uniform(-5, 5, q[1].shape) * (q[0] > 0)
+    q[2] = rng.uniform(-5, 5, q[2].shape) * (q[0] > 0)
+    dts = [5.0] * 10
+    a, *_ = oracle.fixed_steps(B, q, dx, dx, dts)
+    qm = q[:, :, ::-1].copy()
+    qm[1] *= -1; qm[4] *= -1
+    b, *_ = oracle.fixed_steps(B[:, ::-1], qm, dx, dx, dts)
+    b = b[:, :, ::-1].copy()
+    b[1] *= -1; b[4] *= -1
+    for f in range(6):
+        sc = max(np.abs(a[f]).max(), 1.0)
+        assert np.abs(a[f] - b[f]).max() <= 1e-11 * sc, f
+
+
+def test_reduction_to_1d_is_bitwise():
+    """Data uniform in y: the y-sweep is the identity and every row equals the
+    one-row run bit for bit."""
+    c = inputs.fixed_small()
+    row_B = c["B"][20]
+    row_q = c["q"][:, 20]
+    rng = np.random.default_rng(4)
+    row_q = row_q.copy()
+    row_q[1] = rng.uniform(-3, 3, 64)
+    B2 = np.tile(row_B, (8, 1))
+    q2 = np.repeat(row_q[:, None, :], 8, axis=1)
+    dts = [6.0] * 20
+    a, *_ = oracle.fixed_steps(B2, q2, c["dx"], c["dx"], dts)
+    b, *_ = oracle.fixed_steps(row_B[None], row_q[:, None, :], c["dx"], c["dx"], dts)
+    for j in range(8):
+        assert np.array_equal(a[:, j], b[:, 0])
+    assert np.all(a[2] == 0) and np.all(a[5] == 0)
+
+
+def test_window_step_matches_full_step():
+    """The sampled-window entry equals the full-level step on every window,
+    including windows touching walls and corners (bitwise)."""
+    c = inputs.fixed_small()
+    B, q, dx = c["B"], c["q"], c["dx"]
+    full, *_ = oracle.fixed_steps(B, q, dx, dx, [7.0])
+    for box in [(0, 0, 16, 16), (48, 0, 16, 16), (20, 30, 9, 7), (0, 50, 64, 14), (63, 63, 1, 1)]:
+        w, _ = oracle.step_window(B, q, dx, dx, box, 7.0)
+        i, j, nx, ny = box
+        assert np.array_equal(w, full[:, j:j + ny, i:i + nx]), box
