@@ -1,0 +1,173 @@
+/*
+ * mlswe.h -- C ABI of the MI355X two-layer shallow-water AMR hot path.
+ *
+ * Paper: A. Schwarzschild, K. Mandli, "An Implementation of Adaptive Mesh
+ * Refinement for Shallow Water Equations" (arXiv 1803.01450).
+ *
+ * Conventions for every entry point:
+ *  - Returns 0 on success or a negative MLSWE_E* code; mlswe_last_error(ctx)
+ *    then holds a message.  No C++ exception crosses this boundary.
+ *  - Out-parameters are written only on success.
+ *  - State arrays are structure-of-arrays FP64, field-major, rows with x
+ *    fastest: q[f][j][i] for the fields f = h1, h1*u1, h1*v1, h2, h2*u2, h2*v2
+ *    (layer 1 on top), over a whole level's index space (nx_l x ny_l).
+ *  - `where` says whether a pointer is host memory (MLSWE_HOST) or device memory
+ *    of the context's GPU (MLSWE_DEVICE).  Pointers are borrowed for the call
+ *    only; device pointers are read or written in the order of the context's
+ *    stream.  The library owns all of its internal device memory.
+ *  - A context is used by one host thread at a time.
+ *  - Time-stepping calls are asynchronous on the context's stream; calls that
+ *    return host data (get_*, flag, counters, step smax) synchronise it.
+ */
+#ifndef MLSWE_H
+#define MLSWE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLSWE_VERSION 1
+
+enum {
+  MLSWE_OK = 0,
+  MLSWE_EINVAL = -1,  /* bad argument (shape, box, level, ratio, pointer) */
+  MLSWE_ENOMEM = -2,  /* device allocation failed or exceeds the configured cap */
+  MLSWE_EDEVICE = -3, /* no usable GPU, or a HIP call failed */
+  MLSWE_ECFL = -4,    /* observed Courant number above cfl_max in a substep */
+  MLSWE_ENAN = -5,    /* non-finite state detected */
+  MLSWE_ESTATE = -6   /* call order violated (e.g. stepping before set_state) */
+};
+
+enum { MLSWE_HOST = 0, MLSWE_DEVICE = 1 };
+enum { MLSWE_PLAIN = 0, MLSWE_BATCHED = 1 };
+
+typedef struct mlswe_ctx mlswe_ctx;
+
+typedef struct mlswe_config {
+  double g;           /* gravity (9.81) */
+  double hdry;        /* dry tolerance: a layer is wet where its depth >= hdry */
+  double kmin;        /* floor of the internal-wave hyperbolicity factor */
+  double cfl_desired; /* Courant number aimed at by the dt rule (0.9) */
+  double cfl_max;     /* Courant number above which a substep fails (1.0) */
+  int y_rows;         /* rows per y-sweep wave on large patches (0 = 128) */
+  int x_rows;         /* rows per x-sweep wave (0 = 16) */
+  int64_t max_device_bytes; /* cap on the library's device memory (0 = none) */
+} mlswe_config;
+
+typedef struct mlswe_counters {
+  int64_t cell_updates[8]; /* interior cells stepped, per level, summed over substeps */
+  int64_t hyp;             /* edges whose internal-wave factor was clamped */
+  int64_t nclip;           /* cells whose nonzero depth fell below hdry */
+  int64_t repair;          /* wet-ordering repairs (top layer dry over a wet bottom layer) */
+  double clip1, clip2;     /* mass removed from layers 1 and 2 by clipping */
+  double t;                /* simulated time of the problem */
+  int status;              /* sticky device status bits (1: Courant above cfl_max) */
+} mlswe_counters;
+
+/* Library version (MLSWE_VERSION). */
+int mlswe_version(void);
+
+/* Message of the last error on ctx (never NULL; empty string if none). */
+const char* mlswe_last_error(const mlswe_ctx* ctx);
+
+/* Creates a context on the current HIP device using stream `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  cfg may be NULL for defaults.
+ * Errors: MLSWE_EDEVICE if no GPU is usable, MLSWE_EINVAL for bad settings. */
+int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out);
+
+/* Frees every device allocation of ctx and ctx itself. */
+int mlswe_destroy(mlswe_ctx* ctx);
+
+/* Defines a new problem (index returned in *p_out): level 0 of nx0 x ny0 cells
+ * of size dx0 x dy0 with reflecting walls, nlevels levels whose spatial ratios
+ * ratios[0..nlevels-2] give dx_{l+1} = dx_l / r_l and dy_{l+1} = dy_l / r_l
+ * (Sec. 2, Eqs. 1-2), time ratio equal to the space ratio (Sec. 2), density
+ * ratio r = rho1 / rho2 in (0, 1).  Level 0 starts as one patch over the
+ * domain.  Allocates the problem's level arrays (two state buffers, an
+ * intermediate buffer, bathymetry and coverage per level).
+ * Errors: MLSWE_EINVAL (sizes below 2 cells -- the two mirrored ghost cells of
+ * a wall need two cells --, ratios not in 2..16 or not dividing 16),
+ * MLSWE_ENOMEM. */
+int mlswe_problem_define(mlswe_ctx* ctx, int* p_out, double r, int nx0, int ny0, double dx0,
+                         double dy0, int nlevels, const int* ratios);
+
+/* Bathymetry samples at the cell centres of the finest level (ny_f x nx_f);
+ * coarser levels hold block means, so refining the bathymetry (Sec. 2.1) is a
+ * lookup.  Errors: MLSWE_EINVAL. */
+int mlswe_set_bathymetry(mlswe_ctx* ctx, int p, const double* B_finest, int where);
+
+/* Replaces the patch set of a level: n boxes {ilo, jlo, nx, ny} in the level's
+ * index space, non-overlapping; on levels > 0 aligned to the level's ratio and
+ * covered by the coarser level.  Level 0 must be covered completely.  New cells
+ * of a level > 0 keep the value of an old patch that covered them, all others
+ * are refined from the coarser level (surfaces interpolated bottom layer
+ * first with minmod-limited slopes, depths recovered through the effective
+ * bathymetry, wet ordering enforced: Sec. 2.1, Eqs. 3-10).
+ * Errors: MLSWE_EINVAL. */
+int mlswe_set_patches(mlswe_ctx* ctx, int p, int level, int n, const int32_t* boxes);
+
+/* Copies up to cap boxes of a level into boxes (4 ints each); *n_out = count. */
+int mlswe_get_patches(mlswe_ctx* ctx, int p, int level, int cap, int32_t* boxes, int* n_out);
+
+/* Level-wide state q[6][ny_l][nx_l] into / out of the level's current buffer.
+ * get_state writes NaN where no patch covers a cell. Errors: MLSWE_EINVAL. */
+int mlswe_set_state(mlswe_ctx* ctx, int p, int level, const double* q, int where);
+int mlswe_get_state(mlswe_ctx* ctx, int p, int level, double* q, int where);
+
+/* One substep of every patch of `level` of every problem: ghost cells (coarse
+ * data at time fraction theta of the coarser level's last step, refined;
+ * sibling values; walls), x-sweep, y-sweep, dry-state fix-ups, largest wave
+ * speeds.  dt: host array [n_problems] of substeps, or NULL to use the
+ * device-resident dt.  smax_out (nullable, host) receives [n_problems][2]
+ * largest x / y speeds and synchronises.  Errors: MLSWE_EINVAL, MLSWE_ESTATE,
+ * MLSWE_ECFL (checked only when smax_out is given). */
+int mlswe_step_level(mlswe_ctx* ctx, int level, const double* dt, double theta, double* smax_out);
+
+/* Averages the fine level onto the coarser one for all six fields (Sec. 2.2,
+ * Eq. 11, divided by r_x r_y in two dimensions), then applies the dry-state
+ * fix-up.  Errors: MLSWE_EINVAL. */
+int mlswe_coarsen(mlswe_ctx* ctx, int p, int fine_level);
+
+/* Refinement flags of a level (ny_l x nx_l bytes, host): cell flagged iff the top
+ * layer is wet in it and its four neighbours and the centred |grad eta1| exceeds
+ * tau, dilated by nbuf cells within the level's coverage.  Synchronises. */
+int mlswe_flag(mlswe_ctx* ctx, int p, int level, double tau, int nbuf, uint8_t* flags_out);
+
+/* Sets the patches of fine_level (> 0) and fills them: same as set_patches. */
+int mlswe_refine(mlswe_ctx* ctx, int p, int fine_level, int n, const int32_t* boxes);
+
+/* Flag, cluster (16x16 fine tiles, kept if their coarse footprint grown by two
+ * cells lies in the coarser coverage, merged row-major into rectangles of at
+ * most 4x4 tiles) and refine, for levels 0..L-2 in order.  tau[l] per level. */
+int mlswe_regrid(mlswe_ctx* ctx, int p, const double* tau, int nbuf);
+
+/* n_coarse_steps subcycled coarse steps of every problem: regrid every
+ * regrid_every steps (0 = never; tau is [n_problems][8]), dt from the previous
+ * step's largest speeds (first step: from the state), each level l > 0 takes
+ * r_{l-1} substeps per step of level l-1 and is then averaged onto it (Sec. 2).
+ * mode MLSWE_PLAIN launches the sweeps per patch; MLSWE_BATCHED launches one
+ * x-sweep and one y-sweep per level substep over the patches of all problems.
+ * dts_out (nullable, host [n_problems][n_coarse_steps]) receives the coarse
+ * steps.  Errors: MLSWE_EINVAL, MLSWE_ESTATE, MLSWE_ECFL. */
+int mlswe_advance(mlswe_ctx* ctx, int n_coarse_steps, int regrid_every, const double* tau, int nbuf,
+                  int mode, double* dts_out);
+
+/* Counters of problem p (synchronises). */
+int mlswe_get_counters(mlswe_ctx* ctx, int p, mlswe_counters* out);
+
+/* Waits for all work queued on the context's stream. */
+int mlswe_synchronize(mlswe_ctx* ctx);
+
+/* Kernel timing: when enabled, HIP events bracket every sweep launch on the
+ * context's stream; mlswe_kernel_times returns, per kernel class (0: x-sweep,
+ * 1: y-sweep), the summed milliseconds and launch counts since enabling.
+ * Synchronises. */
+int mlswe_set_kernel_timing(mlswe_ctx* ctx, int enable);
+int mlswe_kernel_times(mlswe_ctx* ctx, double* ms_out /*[2]*/, int64_t* launches_out /*[2]*/);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLSWE_H */

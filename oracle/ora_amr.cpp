@@ -487,7 +487,8 @@ extern "C" {
 
 void* ora_create(double g, double r, double hdry, double kmin, double cfl, double cflmax, int nlev,
                  const int* ratios, int nx0, int ny0, double dx0, double dy0) {
-  if (nlev < 1 || nlev > 8 || nx0 <= 0 || ny0 <= 0) return nullptr;
+  // two reflecting ghost cells need at least two cells across the domain
+  if (nlev < 1 || nlev > 8 || nx0 < 2 || ny0 < 2) return nullptr;
   Hier* H = new Hier;
   H->P = make_params(g, r, hdry, kmin);
   H->cfl = cfl; H->cflmax = cflmax;

@@ -390,10 +390,11 @@ double sweep_line(const Params& P, int n, const T* line, const T* Bl, T nu, T* o
   for (int k = 0; k < n; ++k) {
     const T* q = line + 6 * (k + 2);
     T* o = out + 6 * k;
+    // Q - nu (A+dQ_left + A-dQ_right + F_right - F_left), grouped per edge
     for (int c = 0; c < 6; ++c) {
-      T fl = ap[6 * k + c] + am[6 * (k + 1) + c];
-      T cr = F[6 * (k + 1) + c] - F[6 * k + c];
-      o[c] = q[c] - nu * (fl + cr);
+      T gl = ap[6 * k + c] - F[6 * k + c];
+      T gr = am[6 * (k + 1) + c] + F[6 * (k + 1) + c];
+      o[c] = q[c] - nu * (gl + gr);
     }
     fixup(P, o, interior, C);
   }

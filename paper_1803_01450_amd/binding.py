@@ -1,0 +1,246 @@
+"""Python binding of the C ABI in include/mlswe.h (argument marshalling only).
+
+Every step of the computation runs in the HIP library ``libmlswe.so``; this
+module only converts arrays and codes.  It refuses to run without the library:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmlswe.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ECFL, ENAN, ESTATE = 0, -1, -2, -3, -4, -5, -6
+HOST, DEVICE = 0, 1
+PLAIN, BATCHED = 0, 1
+MAXLEV = 8
+
+ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECFL: "ECFL", ENAN: "ENAN", ESTATE: "ESTATE"}
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("hdry", ctypes.c_double), ("kmin", ctypes.c_double),
+                ("cfl_desired", ctypes.c_double), ("cfl_max", ctypes.c_double),
+                ("y_rows", ctypes.c_int), ("x_rows", ctypes.c_int),
+                ("max_device_bytes", ctypes.c_int64)]
+
+
+class CountersC(ctypes.Structure):
+    _fields_ = [("cell_updates", ctypes.c_int64 * 8), ("hyp", ctypes.c_int64), ("nclip", ctypes.c_int64),
+                ("repair", ctypes.c_int64), ("clip1", ctypes.c_double), ("clip2", ctypes.c_double),
+                ("t", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class MlsweError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRNAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError("libmlswe.so is not built (run __graft_entry__.build()); "
+                               "there is no fallback path")
+        L = ctypes.CDLL(LIBPATH)
+        P, I, D, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        IP = ctypes.POINTER(ctypes.c_int)
+        DP = ctypes.POINTER(ctypes.c_double)
+        I32P = ctypes.POINTER(ctypes.c_int32)
+        sig = {
+            "mlswe_version": (I, []),
+            "mlswe_last_error": (ctypes.c_char_p, [P]),
+            "mlswe_create": (I, [ctypes.POINTER(Config), V, ctypes.POINTER(P)]),
+            "mlswe_destroy": (I, [P]),
+            "mlswe_problem_define": (I, [P, IP, D, I, I, D, D, I, IP]),
+            "mlswe_set_bathymetry": (I, [P, I, V, I]),
+            "mlswe_set_patches": (I, [P, I, I, I, I32P]),
+            "mlswe_get_patches": (I, [P, I, I, I, I32P, IP]),
+            "mlswe_set_state": (I, [P, I, I, V, I]),
+            "mlswe_get_state": (I, [P, I, I, V, I]),
+            "mlswe_step_level": (I, [P, I, DP, D, DP]),
+            "mlswe_coarsen": (I, [P, I, I]),
+            "mlswe_flag": (I, [P, I, I, D, I, ctypes.POINTER(ctypes.c_uint8)]),
+            "mlswe_refine": (I, [P, I, I, I, I32P]),
+            "mlswe_regrid": (I, [P, I, DP, I]),
+            "mlswe_advance": (I, [P, I, I, DP, I, I, DP]),
+            "mlswe_get_counters": (I, [P, I, ctypes.POINTER(CountersC)]),
+            "mlswe_synchronize": (I, [P]),
+            "mlswe_set_kernel_timing": (I, [P, I]),
+            "mlswe_kernel_times": (I, [P, DP, ctypes.POINTER(ctypes.c_int64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    """(pointer, where) of a numpy array or a torch tensor (device pointers of
+    CUDA/HIP tensors are passed as device memory)."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p), HOST
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if a.is_cuda:
+            return ctypes.c_void_p(a.data_ptr()), DEVICE
+        return ctypes.c_void_p(a.data_ptr()), HOST
+    raise TypeError("expected a numpy array or a torch tensor")
+
+
+class Solver:
+    """One library context (one GPU stream) holding any number of problems."""
+
+    def __init__(self, g=9.81, hdry=1e-3, kmin=1e-6, cfl=0.9, cfl_max=1.0, y_rows=0, x_rows=0,
+                 max_device_bytes=0, stream=None):
+        self.L = lib()
+        cfg = Config(g, hdry, kmin, cfl, cfl_max, y_rows, x_rows, max_device_bytes)
+        h = ctypes.c_void_p()
+        rc = self.L.mlswe_create(ctypes.byref(cfg), stream, ctypes.byref(h))
+        if rc:
+            raise MlsweError(rc, "mlswe_create failed (no usable GPU?)")
+        self.h = h
+        self.shapes = []   # per problem: list of (nx, ny, dx, dy)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.mlswe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            raise MlsweError(rc, self.L.mlswe_last_error(self.h).decode())
+
+    # ------------------------------------------------------------ set-up
+    def define(self, nx0, ny0, dx0, dy0, r, ratios=()):
+        p = ctypes.c_int()
+        rat = (ctypes.c_int * max(1, len(ratios)))(*ratios) if ratios else None
+        self._check(self.L.mlswe_problem_define(self.h, ctypes.byref(p), r, nx0, ny0, dx0, dy0,
+                                                len(ratios) + 1, rat))
+        shp = [(nx0, ny0, dx0, dy0)]
+        for rr in ratios:
+            nx, ny, dx, dy = shp[-1]
+            shp.append((nx * rr, ny * rr, dx / rr, dy / rr))
+        self.shapes.append(shp)
+        return p.value
+
+    def set_bathymetry(self, p, Bf):
+        if isinstance(Bf, np.ndarray):
+            Bf = _f64(Bf)
+        ptr, where = _ptr(Bf)
+        self._check(self.L.mlswe_set_bathymetry(self.h, p, ptr, where))
+
+    def set_patches(self, p, level, boxes):
+        b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 4))
+        self._check(self.L.mlswe_set_patches(self.h, p, level, b.shape[0],
+                                             b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+
+    def refine(self, p, level, boxes):
+        b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 4))
+        self._check(self.L.mlswe_refine(self.h, p, level, b.shape[0],
+                                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+
+    def patches(self, p, level):
+        nx, ny = self.shapes[p][level][:2]
+        cap = (nx // 1) * (ny // 1) // 256 + 16
+        b = np.zeros((cap, 4), dtype=np.int32)
+        n = ctypes.c_int()
+        self._check(self.L.mlswe_get_patches(self.h, p, level, cap, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             ctypes.byref(n)))
+        return b[:n.value]
+
+    def set_state(self, p, level, q):
+        if isinstance(q, np.ndarray):
+            q = _f64(q)
+            nx, ny = self.shapes[p][level][:2]
+            assert q.shape == (6, ny, nx), q.shape
+        ptr, where = _ptr(q)
+        self._check(self.L.mlswe_set_state(self.h, p, level, ptr, where))
+
+    def state(self, p, level):
+        nx, ny = self.shapes[p][level][:2]
+        q = np.zeros((6, ny, nx))
+        self._check(self.L.mlswe_get_state(self.h, p, level, q.ctypes.data_as(ctypes.c_void_p), HOST))
+        return q
+
+    # ------------------------------------------------------------ operators
+    def step_level(self, level, dts=None, theta=0.0, want_smax=True):
+        n = len(self.shapes)
+        d = None
+        if dts is not None:
+            dd = _f64(np.broadcast_to(np.asarray(dts, dtype=np.float64), (n,)))
+            d = dd.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        sm = np.zeros((n, 2)) if want_smax else None
+        rc = self.L.mlswe_step_level(self.h, level, d, theta,
+                                     sm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_smax else None)
+        self._check(rc)
+        return sm
+
+    def coarsen(self, p, fine_level):
+        self._check(self.L.mlswe_coarsen(self.h, p, fine_level))
+
+    def flag(self, p, level, tau, nbuf=2):
+        nx, ny = self.shapes[p][level][:2]
+        f = np.zeros((ny, nx), dtype=np.uint8)
+        self._check(self.L.mlswe_flag(self.h, p, level, tau, nbuf, f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return f
+
+    def regrid(self, p, tau, nbuf=2):
+        t = _f64(list(tau) + [0.0] * (MAXLEV - len(tau)))
+        self._check(self.L.mlswe_regrid(self.h, p, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nbuf))
+
+    def advance(self, nsteps, regrid_every=0, tau=None, nbuf=2, mode=PLAIN, want_dts=False):
+        n = len(self.shapes)
+        t = None
+        if tau is not None:
+            tt = np.zeros((n, MAXLEV))
+            tau = np.asarray(tau, dtype=np.float64)
+            if tau.ndim == 1:
+                tau = np.broadcast_to(tau, (n, tau.shape[0]))
+            tt[:, :tau.shape[1]] = tau
+            t = tt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            self._tau_keep = tt
+        dts = np.zeros((n, nsteps)) if want_dts else None
+        rc = self.L.mlswe_advance(self.h, nsteps, regrid_every, t, nbuf, mode,
+                                  dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_dts else None)
+        self._check(rc)
+        return dts
+
+    def counters(self, p):
+        c = CountersC()
+        self._check(self.L.mlswe_get_counters(self.h, p, ctypes.byref(c)))
+        nl = len(self.shapes[p])
+        return dict(updates=[int(c.cell_updates[l]) for l in range(nl)], hyp=int(c.hyp), nclip=int(c.nclip),
+                    repair=int(c.repair), clip1=c.clip1, clip2=c.clip2, t=c.t, status=int(c.status))
+
+    def synchronize(self):
+        self._check(self.L.mlswe_synchronize(self.h))
+
+    def set_kernel_timing(self, on=True):
+        self._check(self.L.mlswe_set_kernel_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        ms = (ctypes.c_double * 2)()
+        n = (ctypes.c_int64 * 2)()
+        self._check(self.L.mlswe_kernel_times(self.h, ms, n))
+        return [ms[0], ms[1]], [int(n[0]), int(n[1])]

@@ -1,0 +1,115 @@
+// Launch descriptors shared by the HIP kernels and the host library.
+#pragma once
+#include "mlswe_device.hpp"
+
+namespace mlswe {
+
+constexpr int XOFF = 8;         // column offset of interior column 0 within a row
+constexpr int XTILE_COLS = 60;  // interior columns per x-sweep wave (64 lanes - 4 halo)
+constexpr int STATUS_CFL = 1;
+constexpr int STATUS_NAN = 2;
+
+struct Counters {
+  unsigned long long hyp, nclip, repair;
+  double clip1, clip2;
+  unsigned long long pad[3];
+};
+
+// Device-resident time-step control of one (problem, level).
+struct LevelCtl {
+  double dt;                        // substep of this level
+  unsigned long long step_smax[2];  // largest speeds (bit patterns) of the current substep
+  unsigned long long acc_smax[2];   // largest speeds over the current coarse step
+  unsigned long long last_smax[2];  // largest speeds of the last finished substep
+  double t;                         // simulated time (level 0 entry of a problem)
+  int status;
+  int pad;
+};
+
+// One patch of one level of one problem as seen by the sweep kernels.
+struct PatchDev {
+  const double* q;   // input state (field 0 plane; field f at + f * plane)
+  double* qo;        // output state
+  double* qs;        // x-swept intermediate state
+  const double* B;
+  LevelCtl* ctl;
+  Counters* cnt;
+  long long pitch, plane;
+  int ilo, jlo, nx, ny;
+  double dx, dy;
+  PhysParams P;
+};
+
+struct XTile { int patch, i0, ncols, j0, nrows; };
+struct YTile { int patch, i0, ncols, j0, nrows, last; };
+
+// Ghost fill / regrid refine of one fine patch.
+struct FillPatch {
+  double* q;                  // fine level buffer written
+  const double* B;            // fine bathymetry
+  const unsigned char* mask;  // fine coverage
+  const double* qco;          // coarse state at the start of its step
+  const double* qcn;          // coarse state at the end of its step
+  const double* Bc;
+  const double* theta;        // time fraction (device)
+  Counters* cnt;
+  long long pitch, plane, cpitch, cplane;
+  int nx, ny, ncx, ncy;
+  int ilo, jlo, bnx, bny;
+  int r;
+  int coarse_none;            // level 0: walls only
+  PhysParams P;
+};
+
+struct CoarsenPatch {
+  const double* qf;
+  double* qc;
+  long long fpitch, fplane, cpitch, cplane;
+  int ilo, jlo, bnx, bny, r;
+  PhysParams P;
+};
+
+struct FlagLevel {
+  const double* q;            // current state (field 0 = h1)
+  const double* B;
+  const unsigned char* mask;
+  unsigned char* raw;         // nx * ny scratch
+  unsigned char* out;         // nx * ny flags
+  long long pitch, plane;
+  int nx, ny, nbuf;
+  double dx, dy, tau, hdry;
+};
+
+struct LevelInfo { int ctl; double dx, dy; };
+
+struct SpeedLevel {
+  const double* q;
+  const unsigned char* mask;
+  LevelCtl* ctl;
+  long long pitch, plane;
+  int nx, ny;
+  double g, hdry;
+};
+
+struct ProbDt {
+  int ctl0, nlev;
+  int ratio[8];
+  int active[8];
+  double dx[8], dy[8];
+  double* dt_out;
+};
+
+__global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles);
+__global__ void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles);
+__global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass);
+__global__ void k_refine_new(const FillPatch* __restrict__ fills, const unsigned char* __restrict__ old_mask);
+__global__ void k_coarsen(const CoarsenPatch* __restrict__ cps);
+__global__ void k_flag_raw(FlagLevel F);
+__global__ void k_flag_dilate(FlagLevel F);
+__global__ void k_after_substep(LevelCtl* ctls, const LevelInfo* infos, int n, double cflmax);
+__global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
+__global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial);
+__global__ void k_set_theta(double* th, double v);
+__global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob);
+
+}  // namespace mlswe

@@ -1,0 +1,1106 @@
+// Host side of the MI355X two-layer shallow-water AMR library: contexts,
+// problems, dense per-level device arrays, launch descriptors, clustering,
+// regridding and the subcycled (Berger-Oliger) advance, behind the C ABI of
+// include/mlswe.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mlswe.h"
+#include "mlswe_kernels.hpp"
+
+using namespace mlswe;
+
+namespace {
+
+constexpr int MAXLEV = 8;
+constexpr int TILE = 16;  // clustering tile (fine cells per side)
+
+struct Box { int ilo, jlo, nx, ny; };
+
+struct LevelH {
+  int nx = 0, ny = 0;
+  double dx = 0, dy = 0;
+  long long pitch = 0, plane = 0;
+  double* q[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* qs = nullptr;
+  double* B = nullptr;
+  unsigned char* mask = nullptr;
+  unsigned char* mask_old = nullptr;
+  unsigned char* fraw = nullptr;
+  unsigned char* fout = nullptr;
+  std::vector<unsigned char> mask_h;
+  std::vector<Box> boxes;
+};
+
+struct ProblemH {
+  PhysParams P;
+  int nlev = 1;
+  int ratio[MAXLEV] = {0};
+  LevelH L[MAXLEV];
+  int ctl0 = 0;  // index of level 0's LevelCtl
+  int cnt = 0;   // index of the problem's counters
+  double t = 0.0;
+  long long updates[MAXLEV] = {0};
+  bool bathy = false;
+  bool state = false;
+  bool have_dt = false;
+};
+
+// Launch data of one level index across all problems (rebuilt on patch change).
+struct LevelLaunch {
+  bool dirty = true;
+  int nptch = 0;
+  std::vector<int> patch_prob;               // problem of each patch
+  std::vector<std::pair<int, int>> xr, yr;   // per patch: tile ranges
+  PatchDev* pd[2] = {nullptr, nullptr};      // by buffer parity of the level
+  XTile* xt = nullptr;
+  YTile* yt = nullptr;
+  int nxt = 0, nyt = 0;
+  FillPatch* fp[4] = {nullptr, nullptr, nullptr, nullptr};   // [fine parity * 2 + coarse parity]
+  CoarsenPatch* cp[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<int> fill_first;               // per problem: first fill entry (or -1) and count
+  std::vector<int> fill_count;
+  LevelInfo* li = nullptr;                   // ctl / dx / dy of every problem having the level
+  int nli = 0;
+  std::vector<int> li_first;
+  int cap_pd = 0, cap_xt = 0, cap_yt = 0, cap_fp = 0, cap_li = 0;
+};
+
+}  // namespace
+
+struct mlswe_ctx {
+  mlswe_config cfg;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<ProblemH> probs;
+  LevelCtl* ctl = nullptr;
+  int ctl_cap = 0;
+  Counters* cnt = nullptr;
+  int cnt_cap = 0;
+  double* theta = nullptr;  // [MAXLEV] time fraction used by the ghost fill of each level
+  ProbDt* pdt = nullptr;
+  int pdt_cap = 0;
+  bool pdt_dirty = true;
+  SpeedLevel* spd = nullptr;
+  int spd_cap = 0;
+  LevelLaunch launch[MAXLEV];
+  std::string err;
+  long long bytes = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+  double kms[2] = {0, 0};
+  long long klaunch[2] = {0, 0};
+  double* dt_stage = nullptr;
+  int dt_stage_cap = 0;
+};
+
+namespace {
+
+int fail(mlswe_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(c, call)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return fail((c), MLSWE_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+int dalloc(mlswe_ctx* c, void** p, size_t bytes) {
+  if (c->cfg.max_device_bytes > 0 && c->bytes + (long long)bytes > c->cfg.max_device_bytes)
+    return fail(c, MLSWE_ENOMEM, "device memory cap of %lld bytes exceeded", (long long)c->cfg.max_device_bytes);
+  hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+  if (e != hipSuccess) return fail(c, MLSWE_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  c->bytes += (long long)bytes;
+  return MLSWE_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+long long idx(const LevelH& L, int i, int j) { return (long long)(j + 2) * L.pitch + (i + XOFF); }
+
+bool valid_prob(mlswe_ctx* c, int p) { return p >= 0 && p < (int)c->probs.size(); }
+
+// grow-only device array
+template <class T>
+int ensure(mlswe_ctx* c, T** p, int* cap, int n) {
+  if (n <= *cap && *p) return MLSWE_OK;
+  int nc = std::max(n, std::max(16, *cap * 2));
+  dfree(*p);
+  *p = nullptr;
+  int rc = dalloc(c, (void**)p, sizeof(T) * (size_t)nc);
+  if (rc) return rc;
+  *cap = nc;
+  return MLSWE_OK;
+}
+
+// ------------------------------------------------------------ bathymetry
+void mirror_frame_host(const LevelH& L, std::vector<double>& a) {
+  for (int j = -2; j < L.ny + 2; ++j)
+    for (int i = -2; i < L.nx + 2; ++i) {
+      if (i >= 0 && j >= 0 && i < L.nx && j < L.ny) continue;
+      int si = i < 0 ? -1 - i : (i >= L.nx ? 2 * L.nx - 1 - i : i);
+      int sj = j < 0 ? -1 - j : (j >= L.ny ? 2 * L.ny - 1 - j : j);
+      a[idx(L, i, j)] = a[idx(L, si, sj)];
+    }
+}
+
+// ------------------------------------------------------------ clustering
+// 16x16 fine tiles marked by a flagged coarse cell, kept if their coarse
+// footprint grown by two coarse cells (clipped at the domain) is covered by the
+// coarse level, merged greedily row-major into rectangles of at most 4x4 tiles.
+std::vector<Box> cluster_tiles(const LevelH& C, int r, const std::vector<unsigned char>& flags) {
+  const int fnx = C.nx * r, fny = C.ny * r;
+  const int tx = (fnx + TILE - 1) / TILE, ty = (fny + TILE - 1) / TILE;
+  std::vector<char> keep((size_t)tx * ty, 0), taken((size_t)tx * ty, 0);
+  for (int J = 0; J < ty; ++J)
+    for (int I = 0; I < tx; ++I) {
+      const int ci0 = (TILE * I) / r, cj0 = (TILE * J) / r;
+      const int ci1 = std::min(C.nx, (TILE * (I + 1) + r - 1) / r);
+      const int cj1 = std::min(C.ny, (TILE * (J + 1) + r - 1) / r);
+      bool any = false;
+      for (int j = cj0; j < cj1 && !any; ++j)
+        for (int i = ci0; i < ci1; ++i)
+          if (flags[(size_t)j * C.nx + i]) { any = true; break; }
+      if (!any) continue;
+      bool inside = true;
+      const int a0 = std::max(0, ci0 - 2), a1 = std::min(C.nx, ci1 + 2);
+      const int b0 = std::max(0, cj0 - 2), b1 = std::min(C.ny, cj1 + 2);
+      for (int j = b0; j < b1 && inside; ++j)
+        for (int i = a0; i < a1; ++i)
+          if (!C.mask_h[idx(C, i, j)]) { inside = false; break; }
+      keep[(size_t)J * tx + I] = inside;
+    }
+  auto free_tile = [&](int I, int J) { return keep[(size_t)J * tx + I] && !taken[(size_t)J * tx + I]; };
+  std::vector<Box> out;
+  for (int J = 0; J < ty; ++J)
+    for (int I = 0; I < tx; ++I) {
+      if (!free_tile(I, J)) continue;
+      int w = 1;
+      while (w < 4 && I + w < tx && free_tile(I + w, J)) ++w;
+      int h = 1;
+      for (; h < 4 && J + h < ty; ++h) {
+        bool full = true;
+        for (int a = 0; a < w; ++a) full = full && free_tile(I + a, J + h);
+        if (!full) break;
+      }
+      for (int b = 0; b < h; ++b)
+        for (int a = 0; a < w; ++a) taken[(size_t)(J + b) * tx + I + a] = 1;
+      Box bx;
+      bx.ilo = TILE * I;
+      bx.jlo = TILE * J;
+      bx.nx = std::min(fnx, TILE * (I + w)) - bx.ilo;
+      bx.ny = std::min(fny, TILE * (J + h)) - bx.jlo;
+      out.push_back(bx);
+    }
+  return out;
+}
+
+// ------------------------------------------------------------ launch data
+int build_launch(mlswe_ctx* c, int l) {
+  LevelLaunch& LL = c->launch[l];
+  if (!LL.dirty) return MLSWE_OK;
+  const int xrows = c->cfg.x_rows > 0 ? c->cfg.x_rows : 16;
+  const int yrows = c->cfg.y_rows > 0 ? c->cfg.y_rows : 128;
+  std::vector<PatchDev> pd[2];
+  std::vector<XTile> xt;
+  std::vector<YTile> yt;
+  std::vector<FillPatch> fp[4];
+  std::vector<CoarsenPatch> cp[4];
+  std::vector<LevelInfo> li;
+  LL.patch_prob.clear(); LL.xr.clear(); LL.yr.clear();
+  LL.fill_first.assign(c->probs.size(), -1);
+  LL.fill_count.assign(c->probs.size(), 0);
+  LL.li_first.assign(c->probs.size(), -1);
+  for (size_t pi = 0; pi < c->probs.size(); ++pi) {
+    ProblemH& P = c->probs[pi];
+    if (l >= P.nlev) continue;
+    LevelH& L = P.L[l];
+    LL.li_first[pi] = (int)li.size();
+    li.push_back(LevelInfo{P.ctl0 + l, L.dx, L.dy});
+    if (L.boxes.empty()) continue;
+    LL.fill_first[pi] = (int)fp[0].size();
+    LL.fill_count[pi] = (int)L.boxes.size();
+    for (const Box& b : L.boxes) {
+      const int id = (int)pd[0].size();
+      for (int par = 0; par < 2; ++par) {
+        PatchDev d;
+        d.q = L.q[par]; d.qo = L.q[1 - par]; d.qs = L.qs; d.B = L.B;
+        d.ctl = c->ctl + P.ctl0 + l; d.cnt = c->cnt + P.cnt;
+        d.pitch = L.pitch; d.plane = L.plane;
+        d.ilo = b.ilo; d.jlo = b.jlo; d.nx = b.nx; d.ny = b.ny;
+        d.dx = L.dx; d.dy = L.dy; d.P = P.P;
+        pd[par].push_back(d);
+      }
+      LL.patch_prob.push_back((int)pi);
+      const int x0 = (int)xt.size();
+      for (int i0 = b.ilo; i0 < b.ilo + b.nx; i0 += XTILE_COLS) {
+        const int nc = std::min(XTILE_COLS, b.ilo + b.nx - i0);
+        for (int j0 = b.jlo - 2; j0 < b.jlo + b.ny + 2; j0 += xrows)
+          xt.push_back(XTile{id, i0, nc, j0, std::min(xrows, b.jlo + b.ny + 2 - j0)});
+      }
+      const int y0 = (int)yt.size();
+      for (int i0 = b.ilo; i0 < b.ilo + b.nx; i0 += 64) {
+        const int nc = std::min(64, b.ilo + b.nx - i0);
+        for (int j0 = b.jlo; j0 < b.jlo + b.ny; j0 += yrows) {
+          const int nr = std::min(yrows, b.jlo + b.ny - j0);
+          yt.push_back(YTile{id, i0, nc, j0, nr, (j0 + nr == b.jlo + b.ny) ? 1 : 0});
+        }
+      }
+      LL.xr.push_back({x0, (int)xt.size() - x0});
+      LL.yr.push_back({y0, (int)yt.size() - y0});
+      for (int fpar = 0; fpar < 2; ++fpar)
+        for (int cpar = 0; cpar < 2; ++cpar) {
+          FillPatch f;
+          std::memset(&f, 0, sizeof f);
+          f.q = L.q[fpar]; f.B = L.B; f.mask = L.mask;
+          f.theta = c->theta + l;
+          f.cnt = c->cnt + P.cnt;
+          f.pitch = L.pitch; f.plane = L.plane;
+          f.nx = L.nx; f.ny = L.ny;
+          f.ilo = b.ilo; f.jlo = b.jlo; f.bnx = b.nx; f.bny = b.ny;
+          f.P = P.P;
+          CoarsenPatch cc;
+          std::memset(&cc, 0, sizeof cc);
+          if (l > 0) {
+            const LevelH& Cl = P.L[l - 1];
+            f.qco = Cl.q[1 - cpar]; f.qcn = Cl.q[cpar]; f.Bc = Cl.B;
+            f.cpitch = Cl.pitch; f.cplane = Cl.plane; f.ncx = Cl.nx; f.ncy = Cl.ny;
+            f.r = P.ratio[l - 1];
+            f.coarse_none = 0;
+            cc.qf = L.q[fpar]; cc.qc = Cl.q[cpar];
+            cc.fpitch = L.pitch; cc.fplane = L.plane; cc.cpitch = Cl.pitch; cc.cplane = Cl.plane;
+            cc.ilo = b.ilo; cc.jlo = b.jlo; cc.bnx = b.nx; cc.bny = b.ny; cc.r = P.ratio[l - 1];
+            cc.P = P.P;
+          } else {
+            f.coarse_none = 1;
+            f.r = 1;
+          }
+          fp[fpar * 2 + cpar].push_back(f);
+          cp[fpar * 2 + cpar].push_back(cc);
+        }
+    }
+  }
+  LL.nptch = (int)pd[0].size();
+  LL.nxt = (int)xt.size();
+  LL.nyt = (int)yt.size();
+  LL.nli = (int)li.size();
+  int rc;
+  int cap_pd1 = LL.cap_pd;
+  if ((rc = ensure(c, &LL.pd[0], &LL.cap_pd, LL.nptch))) return rc;
+  if ((rc = ensure(c, &LL.pd[1], &cap_pd1, LL.nptch))) return rc;
+  if ((rc = ensure(c, &LL.xt, &LL.cap_xt, LL.nxt))) return rc;
+  if ((rc = ensure(c, &LL.yt, &LL.cap_yt, LL.nyt))) return rc;
+  int capf[4] = {LL.cap_fp, LL.cap_fp, LL.cap_fp, LL.cap_fp};
+  int capc[4] = {LL.cap_fp, LL.cap_fp, LL.cap_fp, LL.cap_fp};
+  for (int k = 0; k < 4; ++k) {
+    if ((rc = ensure(c, &LL.fp[k], &capf[k], LL.nptch))) return rc;
+    if ((rc = ensure(c, &LL.cp[k], &capc[k], LL.nptch))) return rc;
+  }
+  LL.cap_fp = capf[0];
+  if ((rc = ensure(c, &LL.li, &LL.cap_li, LL.nli))) return rc;
+  if (LL.nptch) {
+    HIPCHK(c, hipMemcpyAsync(LL.pd[0], pd[0].data(), sizeof(PatchDev) * LL.nptch, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(LL.pd[1], pd[1].data(), sizeof(PatchDev) * LL.nptch, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(LL.xt, xt.data(), sizeof(XTile) * LL.nxt, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(LL.yt, yt.data(), sizeof(YTile) * LL.nyt, hipMemcpyHostToDevice, c->stream));
+    for (int k = 0; k < 4; ++k) {
+      HIPCHK(c, hipMemcpyAsync(LL.fp[k], fp[k].data(), sizeof(FillPatch) * LL.nptch, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(LL.cp[k], cp[k].data(), sizeof(CoarsenPatch) * LL.nptch, hipMemcpyHostToDevice, c->stream));
+    }
+  }
+  if (LL.nli)
+    HIPCHK(c, hipMemcpyAsync(LL.li, li.data(), sizeof(LevelInfo) * LL.nli, hipMemcpyHostToDevice, c->stream));
+  // host vectors must outlive the asynchronous copies
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  LL.dirty = false;
+  return MLSWE_OK;
+}
+
+void mark_dirty(mlswe_ctx* c, int l) {
+  if (l >= 0 && l < MAXLEV) c->launch[l].dirty = true;
+  if (l + 1 < MAXLEV) c->launch[l + 1].dirty = true;  // fill/coarsen descriptors of the finer level
+  c->pdt_dirty = true;
+}
+
+int build_pdt(mlswe_ctx* c) {
+  if (!c->pdt_dirty) return MLSWE_OK;
+  std::vector<ProbDt> v(c->probs.size());
+  for (size_t i = 0; i < c->probs.size(); ++i) {
+    const ProblemH& P = c->probs[i];
+    ProbDt d;
+    std::memset(&d, 0, sizeof d);
+    d.ctl0 = P.ctl0; d.nlev = P.nlev;
+    for (int l = 0; l < P.nlev; ++l) {
+      d.ratio[l] = P.ratio[l];
+      d.active[l] = P.L[l].boxes.empty() ? 0 : 1;
+      d.dx[l] = P.L[l].dx; d.dy[l] = P.L[l].dy;
+    }
+    d.dt_out = nullptr;
+    v[i] = d;
+  }
+  int rc = ensure(c, &c->pdt, &c->pdt_cap, (int)v.size());
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->pdt, v.data(), sizeof(ProbDt) * v.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->pdt_dirty = false;
+  return MLSWE_OK;
+}
+
+// ------------------------------------------------------------ timing
+int ev_begin(mlswe_ctx* c, hipEvent_t* e) {
+  if (c->ev_pool.empty()) {
+    hipEvent_t a;
+    HIPCHK(c, hipEventCreate(&a));
+    c->ev_pool.push_back(a);
+  }
+  *e = c->ev_pool.back();
+  c->ev_pool.pop_back();
+  HIPCHK(c, hipEventRecord(*e, c->stream));
+  return MLSWE_OK;
+}
+
+int collect_events(mlswe_ctx* c) {
+  if (c->ev_used.empty()) return MLSWE_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& u : c->ev_used) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, u.second.first, u.second.second));
+    c->kms[u.first] += ms;
+    c->klaunch[u.first] += 1;
+    c->ev_pool.push_back(u.second.first);
+    c->ev_pool.push_back(u.second.second);
+  }
+  c->ev_used.clear();
+  return MLSWE_OK;
+}
+
+// ------------------------------------------------------------ launches
+int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, int nyt) {
+  LevelLaunch& LL = c->launch[l];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc;
+  if (nxt > 0) {
+    if (c->timing && (rc = ev_begin(c, &e0))) return rc;
+    hipLaunchKernelGGL(k_sweep_x, dim3((nxt + 3) / 4), dim3(256), 0, c->stream, LL.pd[parity], LL.xt + xt0, nxt);
+    HIPCHK(c, hipGetLastError());
+    if (c->timing) {
+      if ((rc = ev_begin(c, &e1))) return rc;
+      c->ev_used.push_back({0, {e0, e1}});
+    }
+  }
+  if (nyt > 0) {
+    if (c->timing && (rc = ev_begin(c, &e0))) return rc;
+    hipLaunchKernelGGL(k_sweep_y, dim3((nyt + 3) / 4), dim3(256), 0, c->stream, LL.pd[parity], LL.yt + yt0, nyt);
+    HIPCHK(c, hipGetLastError());
+    if (c->timing) {
+      if ((rc = ev_begin(c, &e1))) return rc;
+      c->ev_used.push_back({1, {e0, e1}});
+    }
+  }
+  if (c->ev_used.size() > 4096) return collect_events(c);
+  return MLSWE_OK;
+}
+
+// Ghost fill of level l for the problems in [p0, p1) (all with the level).
+int launch_fill(mlswe_ctx* c, int l, int p0, int p1, double theta) {
+  LevelLaunch& LL = c->launch[l];
+  const ProblemH& P0 = c->probs[p0];
+  const int fpar = P0.L[l].cur;
+  const int cpar = l > 0 ? P0.L[l - 1].cur : 0;
+  int first = -1, count = 0, maxring = 0;
+  for (int p = p0; p < p1; ++p) {
+    if (LL.fill_first[p] < 0) continue;
+    if (first < 0) first = LL.fill_first[p];
+    count = LL.fill_first[p] + LL.fill_count[p] - first;
+    for (const Box& b : c->probs[p].L[l].boxes) maxring = std::max(maxring, 4 * (b.nx + 4) + 4 * b.ny);
+  }
+  if (count == 0) return MLSWE_OK;
+  const FillPatch* f = LL.fp[fpar * 2 + cpar] + first;
+  if (l > 0) {
+    hipLaunchKernelGGL(k_set_theta, dim3(1), dim3(1), 0, c->stream, c->theta + l, theta);
+    hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 0);
+    HIPCHK(c, hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 1);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
+int launch_after(mlswe_ctx* c, int l, int p0, int p1) {
+  LevelLaunch& LL = c->launch[l];
+  int first = -1, n = 0;
+  for (int p = p0; p < p1; ++p) {
+    if (LL.li_first[p] < 0) continue;
+    if (first < 0) first = LL.li_first[p];
+    n = LL.li_first[p] + 1 - first;
+  }
+  if (n == 0) return MLSWE_OK;
+  hipLaunchKernelGGL(k_after_substep, dim3((n + 63) / 64), dim3(64), 0, c->stream, c->ctl, LL.li + first, n,
+                     c->cfg.cfl_max);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
+// One substep of level l for problems [p0, p1): fill, sweeps, buffer flip.
+int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
+  int rc;
+  if ((rc = build_launch(c, l))) return rc;
+  if (l > 0 && (rc = build_launch(c, l - 1))) return rc;
+  LevelLaunch& LL = c->launch[l];
+  if ((rc = launch_fill(c, l, p0, p1, theta))) return rc;
+  const int parity = c->probs[p0].L[l].cur;
+  for (int p = p0; p < p1; ++p)
+    if (l < c->probs[p].nlev && c->probs[p].L[l].cur != parity)
+      return fail(c, MLSWE_ESTATE, "problems out of step on level %d", l);
+  // patches of [p0, p1) are contiguous in the launch data
+  int a = -1, b = -1;
+  for (int k = 0; k < LL.nptch; ++k)
+    if (LL.patch_prob[k] >= p0 && LL.patch_prob[k] < p1) {
+      if (a < 0) a = k;
+      b = k;
+    }
+  if (a >= 0) {
+    if (batched) {
+      const int xt0 = LL.xr[a].first, nxt = LL.xr[b].first + LL.xr[b].second - xt0;
+      const int yt0 = LL.yr[a].first, nyt = LL.yr[b].first + LL.yr[b].second - yt0;
+      if ((rc = launch_sweeps(c, l, parity, xt0, nxt, yt0, nyt))) return rc;
+    } else {
+      // plain: x then y of every patch, one launch each
+      for (int k = a; k <= b; ++k)
+        if ((rc = launch_sweeps(c, l, parity, LL.xr[k].first, LL.xr[k].second, LL.yr[k].first, LL.yr[k].second)))
+          return rc;
+    }
+  }
+  for (int p = p0; p < p1; ++p) {
+    ProblemH& P = c->probs[p];
+    if (l >= P.nlev) continue;
+    LevelH& L = P.L[l];
+    L.cur = 1 - L.cur;
+    for (const Box& bx : L.boxes) P.updates[l] += (long long)bx.nx * bx.ny;
+  }
+  return launch_after(c, l, p0, p1);
+}
+
+int coarsen_level(mlswe_ctx* c, int lf, int p0, int p1) {
+  int rc;
+  if ((rc = build_launch(c, lf))) return rc;
+  LevelLaunch& LL = c->launch[lf];
+  int first = -1, count = 0, maxc = 0;
+  for (int p = p0; p < p1; ++p) {
+    if (LL.fill_first[p] < 0) continue;
+    if (first < 0) first = LL.fill_first[p];
+    count = LL.fill_first[p] + LL.fill_count[p] - first;
+    const int r = c->probs[p].ratio[lf - 1];
+    for (const Box& b : c->probs[p].L[lf].boxes) maxc = std::max(maxc, (b.nx / r) * (b.ny / r));
+  }
+  if (count == 0) return MLSWE_OK;
+  const int fpar = c->probs[p0].L[lf].cur, cpar = c->probs[p0].L[lf - 1].cur;
+  hipLaunchKernelGGL(k_coarsen, dim3((maxc + 255) / 256, count), dim3(256), 0, c->stream,
+                     LL.cp[fpar * 2 + cpar] + first);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
+bool level_active(const mlswe_ctx* c, int l, int p0, int p1) {
+  for (int p = p0; p < p1; ++p)
+    if (l < c->probs[p].nlev && !c->probs[p].L[l].boxes.empty()) return true;
+  return false;
+}
+
+int adv(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
+  int rc;
+  if ((rc = substep(c, l, p0, p1, theta, batched))) return rc;
+  const ProblemH& P0 = c->probs[p0];
+  if (l + 1 < P0.nlev && level_active(c, l + 1, p0, p1)) {
+    const int r = P0.ratio[l];
+    for (int k = 0; k < r; ++k)
+      if ((rc = adv(c, l + 1, p0, p1, double(k) / double(r), batched))) return rc;
+    if ((rc = coarsen_level(c, l + 1, p0, p1))) return rc;
+  }
+  return MLSWE_OK;
+}
+
+int next_dt(mlswe_ctx* c, int p0, int p1, bool initial) {
+  int rc;
+  if ((rc = build_pdt(c))) return rc;
+  if (initial) {
+    std::vector<SpeedLevel> sl;
+    for (int p = p0; p < p1; ++p) {
+      ProblemH& P = c->probs[p];
+      for (int l = 0; l < P.nlev; ++l) {
+        if (P.L[l].boxes.empty()) continue;
+        LevelH& L = P.L[l];
+        SpeedLevel s;
+        s.q = L.q[L.cur]; s.mask = L.mask; s.ctl = c->ctl + P.ctl0 + l;
+        s.pitch = L.pitch; s.plane = L.plane; s.nx = L.nx; s.ny = L.ny;
+        s.g = P.P.g; s.hdry = P.P.hdry;
+        sl.push_back(s);
+      }
+    }
+    if ((rc = ensure(c, &c->spd, &c->spd_cap, (int)sl.size()))) return rc;
+    hipLaunchKernelGGL(k_reset_acc, dim3((p1 - p0 + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, p1 - p0);
+    HIPCHK(c, hipMemcpyAsync(c->spd, sl.data(), sizeof(SpeedLevel) * sl.size(), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_initial_speed, dim3(64, (unsigned)sl.size()), dim3(256), 0, c->stream, c->spd);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  hipLaunchKernelGGL(k_next_dt, dim3((p1 - p0 + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, p1 - p0,
+                     c->cfg.cfl_desired, initial ? 1 : 0);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
+int read_status(mlswe_ctx* c, int p0, int p1, int* status) {
+  *status = 0;
+  for (int p = p0; p < p1; ++p) {
+    const ProblemH& P = c->probs[p];
+    for (int l = 0; l < P.nlev; ++l) {
+      LevelCtl h;
+      HIPCHK(c, hipMemcpyAsync(&h, c->ctl + P.ctl0 + l, sizeof h, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      *status |= h.status;
+    }
+  }
+  return MLSWE_OK;
+}
+
+// ------------------------------------------------------------ patches
+int upload_mask(mlswe_ctx* c, LevelH& L) {
+  std::fill(L.mask_h.begin(), L.mask_h.end(), 0);
+  for (const Box& b : L.boxes)
+    for (int j = b.jlo; j < b.jlo + b.ny; ++j)
+      std::memset(&L.mask_h[idx(L, b.ilo, j)], 1, b.nx);
+  HIPCHK(c, hipMemcpyAsync(L.mask, L.mask_h.data(), L.mask_h.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MLSWE_OK;
+}
+
+int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
+  ProblemH& P = c->probs[p];
+  if (l < 0 || l >= P.nlev) return fail(c, MLSWE_EINVAL, "level %d out of range", l);
+  if (n < 0 || (n > 0 && !bx)) return fail(c, MLSWE_EINVAL, "bad patch list");
+  LevelH& L = P.L[l];
+  std::vector<Box> nb(n);
+  std::vector<unsigned char> cov((size_t)L.nx * L.ny, 0);
+  for (int k = 0; k < n; ++k) {
+    Box b{bx[4 * k], bx[4 * k + 1], bx[4 * k + 2], bx[4 * k + 3]};
+    if (b.nx <= 0 || b.ny <= 0 || b.ilo < 0 || b.jlo < 0 || b.ilo + b.nx > L.nx || b.jlo + b.ny > L.ny)
+      return fail(c, MLSWE_EINVAL, "patch %d outside level %d", k, l);
+    if (l > 0) {
+      const int r = P.ratio[l - 1];
+      if (b.ilo % r || b.jlo % r || b.nx % r || b.ny % r)
+        return fail(c, MLSWE_EINVAL, "patch %d not aligned to ratio %d", k, r);
+      const LevelH& C = P.L[l - 1];
+      for (int j = b.jlo / r; j < (b.jlo + b.ny) / r; ++j)
+        for (int i = b.ilo / r; i < (b.ilo + b.nx) / r; ++i)
+          if (!C.mask_h[idx(C, i, j)]) return fail(c, MLSWE_EINVAL, "patch %d not covered by level %d", k, l - 1);
+    }
+    for (int j = b.jlo; j < b.jlo + b.ny; ++j)
+      for (int i = b.ilo; i < b.ilo + b.nx; ++i) {
+        unsigned char& m = cov[(size_t)j * L.nx + i];
+        if (m) return fail(c, MLSWE_EINVAL, "patches overlap on level %d", l);
+        m = 1;
+      }
+    nb[k] = b;
+  }
+  if (l == 0) {
+    for (unsigned char m : cov)
+      if (!m) return fail(c, MLSWE_EINVAL, "level 0 patches must cover the domain");
+  }
+  // keep the old coverage for the fill of new cells
+  if (l > 0) {
+    HIPCHK(c, hipMemcpyAsync(L.mask_old, L.mask, L.mask_h.size(), hipMemcpyDeviceToDevice, c->stream));
+  }
+  L.boxes = nb;
+  int rc = upload_mask(c, L);
+  if (rc) return rc;
+  mark_dirty(c, l);
+  if (l > 0 && n > 0) {
+    std::vector<FillPatch> f;
+    int maxn = 0;
+    const LevelH& C = P.L[l - 1];
+    for (const Box& b : L.boxes) {
+      FillPatch x;
+      std::memset(&x, 0, sizeof x);
+      x.q = L.q[L.cur]; x.B = L.B; x.mask = L.mask;
+      x.qco = C.q[C.cur]; x.qcn = C.q[C.cur]; x.Bc = C.B;
+      x.cnt = c->cnt + P.cnt;
+      x.pitch = L.pitch; x.plane = L.plane; x.cpitch = C.pitch; x.cplane = C.plane;
+      x.nx = L.nx; x.ny = L.ny; x.ncx = C.nx; x.ncy = C.ny;
+      x.ilo = b.ilo; x.jlo = b.jlo; x.bnx = b.nx; x.bny = b.ny;
+      x.r = P.ratio[l - 1];
+      x.P = P.P;
+      f.push_back(x);
+      maxn = std::max(maxn, b.nx * b.ny);
+    }
+    FillPatch* fd = nullptr;
+    if ((rc = dalloc(c, (void**)&fd, sizeof(FillPatch) * f.size()))) return rc;
+    HIPCHK(c, hipMemcpyAsync(fd, f.data(), sizeof(FillPatch) * f.size(), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_refine_new, dim3((maxn + 255) / 256, (unsigned)f.size()), dim3(256), 0, c->stream, fd,
+                       L.mask_old);
+    hipError_t e = hipGetLastError();
+    hipError_t s = hipStreamSynchronize(c->stream);
+    dfree(fd);
+    c->bytes -= (long long)(sizeof(FillPatch) * f.size());
+    if (e != hipSuccess || s != hipSuccess)
+      return fail(c, MLSWE_EDEVICE, "refine launch: %s", hipGetErrorString(e != hipSuccess ? e : s));
+  }
+  return MLSWE_OK;
+}
+
+int flag_impl(mlswe_ctx* c, int p, int l, double tau, int nbuf, std::vector<unsigned char>& out) {
+  ProblemH& P = c->probs[p];
+  LevelH& L = P.L[l];
+  int rc;
+  if (!L.fraw) {
+    if ((rc = dalloc(c, (void**)&L.fraw, (size_t)L.nx * L.ny))) return rc;
+    if ((rc = dalloc(c, (void**)&L.fout, (size_t)L.nx * L.ny))) return rc;
+  }
+  FlagLevel F;
+  F.q = L.q[L.cur]; F.B = L.B; F.mask = L.mask; F.raw = L.fraw; F.out = L.fout;
+  F.pitch = L.pitch; F.plane = L.plane; F.nx = L.nx; F.ny = L.ny; F.nbuf = nbuf;
+  F.dx = L.dx; F.dy = L.dy; F.tau = tau; F.hdry = P.P.hdry;
+  hipLaunchKernelGGL(k_flag_raw, dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, c->stream, F);
+  hipLaunchKernelGGL(k_flag_dilate, dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, c->stream, F);
+  HIPCHK(c, hipGetLastError());
+  out.resize((size_t)L.nx * L.ny);
+  HIPCHK(c, hipMemcpyAsync(out.data(), L.fout, out.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MLSWE_OK;
+}
+
+int regrid_impl(mlswe_ctx* c, int p, const double* tau, int nbuf) {
+  ProblemH& P = c->probs[p];
+  for (int l = 0; l + 1 < P.nlev; ++l) {
+    std::vector<unsigned char> f;
+    int rc = flag_impl(c, p, l, tau[l], nbuf, f);
+    if (rc) return rc;
+    std::vector<Box> bx = cluster_tiles(P.L[l], P.ratio[l], f);
+    std::vector<int32_t> flat;
+    for (const Box& b : bx) { flat.push_back(b.ilo); flat.push_back(b.jlo); flat.push_back(b.nx); flat.push_back(b.ny); }
+    if ((rc = set_patches_impl(c, p, l + 1, (int)bx.size(), flat.data()))) return rc;
+  }
+  return MLSWE_OK;
+}
+
+int copy_state(mlswe_ctx* c, LevelH& L, int buf, const double* src, int where, bool to_dev, double* dst) {
+  const hipMemcpyKind kind = to_dev ? (where == MLSWE_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
+                                    : (where == MLSWE_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+  for (int f = 0; f < 6; ++f) {
+    double* lv = L.q[buf] + f * L.plane + idx(L, 0, 0);
+    const size_t hrow = (size_t)L.nx * sizeof(double);
+    if (to_dev)
+      HIPCHK(c, hipMemcpy2DAsync(lv, L.pitch * sizeof(double), src + (size_t)f * L.nx * L.ny, hrow, hrow, L.ny, kind,
+                                 c->stream));
+    else
+      HIPCHK(c, hipMemcpy2DAsync(dst + (size_t)f * L.nx * L.ny, hrow, lv, L.pitch * sizeof(double), hrow, L.ny, kind,
+                                 c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MLSWE_OK;
+}
+
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+int mlswe_version(void) { return MLSWE_VERSION; }
+
+const char* mlswe_last_error(const mlswe_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
+  if (!out) return MLSWE_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MLSWE_EDEVICE;
+  mlswe_ctx* c = new (std::nothrow) mlswe_ctx;
+  if (!c) return MLSWE_ENOMEM;
+  mlswe_config d;
+  std::memset(&d, 0, sizeof d);
+  d.g = 9.81; d.hdry = 1e-3; d.kmin = 1e-6; d.cfl_desired = 0.9; d.cfl_max = 1.0;
+  if (cfg) d = *cfg;
+  if (!(d.g > 0) || !(d.hdry > 0) || !(d.kmin > 0) || !(d.cfl_desired > 0) || !(d.cfl_max >= d.cfl_desired) ||
+      d.y_rows < 0 || d.x_rows < 0) {
+    delete c;
+    return MLSWE_EINVAL;
+  }
+  c->cfg = d;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return MLSWE_EDEVICE; }
+  int rc = dalloc(c, (void**)&c->theta, sizeof(double) * MAXLEV);
+  if (rc) { delete c; return rc; }
+  if (hipMemsetAsync(c->theta, 0, sizeof(double) * MAXLEV, c->stream) != hipSuccess) {
+    dfree(c->theta);
+    delete c;
+    return MLSWE_EDEVICE;
+  }
+  *out = c;
+  return MLSWE_OK;
+}
+
+int mlswe_destroy(mlswe_ctx* c) {
+  if (!c) return MLSWE_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  for (ProblemH& P : c->probs)
+    for (int l = 0; l < P.nlev; ++l) {
+      LevelH& L = P.L[l];
+      dfree(L.q[0]); dfree(L.q[1]); dfree(L.qs); dfree(L.B); dfree(L.mask); dfree(L.mask_old);
+      dfree(L.fraw); dfree(L.fout);
+    }
+  for (LevelLaunch& LL : c->launch) {
+    dfree(LL.pd[0]); dfree(LL.pd[1]); dfree(LL.xt); dfree(LL.yt); dfree(LL.li);
+    for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
+  }
+  dfree(c->ctl); dfree(c->cnt); dfree(c->theta); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& u : c->ev_used) { (void)hipEventDestroy(u.second.first); (void)hipEventDestroy(u.second.second); }
+  delete c;
+  return MLSWE_OK;
+}
+
+int mlswe_problem_define(mlswe_ctx* c, int* p_out, double r, int nx0, int ny0, double dx0, double dy0, int nlevels,
+                         const int* ratios) {
+  if (!c || !p_out) return MLSWE_EINVAL;
+  if (!(r > 0.0 && r < 1.0) || nx0 < 2 || ny0 < 2 || !(dx0 > 0) || !(dy0 > 0) || nlevels < 1 || nlevels > MAXLEV)
+    return fail(c, MLSWE_EINVAL, "bad problem geometry");
+  if (nlevels > 1 && !ratios) return fail(c, MLSWE_EINVAL, "ratios missing");
+  for (int l = 0; l + 1 < nlevels; ++l)
+    if (ratios[l] < 2 || ratios[l] > 16 || TILE % ratios[l])
+      return fail(c, MLSWE_EINVAL, "ratio %d must divide %d", ratios[l], TILE);
+  ProblemH P;
+  P.P.g = c->cfg.g; P.P.r = r; P.P.hdry = c->cfg.hdry; P.P.kmin = c->cfg.kmin;
+  P.P.gp = (1.0 - r) * c->cfg.g;
+  P.P.inv_gp = 1.0 / ((1.0 - r) * c->cfg.g);
+  P.nlev = nlevels;
+  long long nx = nx0, ny = ny0;
+  double dx = dx0, dy = dy0;
+  for (int l = 0; l < nlevels; ++l) {
+    if (l > 0) {
+      P.ratio[l - 1] = ratios[l - 1];
+      nx *= ratios[l - 1]; ny *= ratios[l - 1];
+      dx = dx / ratios[l - 1]; dy = dy / ratios[l - 1];
+    }
+    if (nx > (1 << 20) || ny > (1 << 20)) return fail(c, MLSWE_EINVAL, "level %d too large", l);
+    LevelH& L = P.L[l];
+    L.nx = (int)nx; L.ny = (int)ny; L.dx = dx; L.dy = dy;
+    L.pitch = ((XOFF + nx + 2) + 15) / 16 * 16;
+    L.plane = L.pitch * (ny + 4);
+    const size_t sb = sizeof(double) * 6 * (size_t)L.plane;
+    int rc;
+    if ((rc = dalloc(c, (void**)&L.q[0], sb)) || (rc = dalloc(c, (void**)&L.q[1], sb)) ||
+        (rc = dalloc(c, (void**)&L.qs, sb)) || (rc = dalloc(c, (void**)&L.B, sizeof(double) * (size_t)L.plane)) ||
+        (rc = dalloc(c, (void**)&L.mask, (size_t)L.plane)) || (rc = dalloc(c, (void**)&L.mask_old, (size_t)L.plane))) {
+      for (int k = 0; k <= l; ++k) {
+        dfree(P.L[k].q[0]); dfree(P.L[k].q[1]); dfree(P.L[k].qs); dfree(P.L[k].B); dfree(P.L[k].mask);
+        dfree(P.L[k].mask_old);
+      }
+      return rc;
+    }
+    HIPCHK(c, hipMemsetAsync(L.q[0], 0, sb, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.q[1], 0, sb, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.qs, 0, sb, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.B, 0, sizeof(double) * (size_t)L.plane, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.mask, 0, (size_t)L.plane, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.mask_old, 0, (size_t)L.plane, c->stream));
+    L.mask_h.assign((size_t)L.plane, 0);
+  }
+  const int pidx = (int)c->probs.size();
+  // device control blocks: grow and copy
+  int nctl = 0;
+  for (const ProblemH& Q : c->probs) nctl += Q.nlev;
+  P.ctl0 = nctl;
+  P.cnt = pidx;
+  if (nctl + nlevels > c->ctl_cap || pidx + 1 > c->cnt_cap) {
+    int ncap = std::max(2 * (nctl + nlevels), 64);
+    int ccap = std::max(2 * (pidx + 1), 64);
+    LevelCtl* nc = nullptr;
+    Counters* ncn = nullptr;
+    int rc;
+    if ((rc = dalloc(c, (void**)&nc, sizeof(LevelCtl) * ncap))) return rc;
+    if ((rc = dalloc(c, (void**)&ncn, sizeof(Counters) * ccap))) return rc;
+    HIPCHK(c, hipMemsetAsync(nc, 0, sizeof(LevelCtl) * ncap, c->stream));
+    HIPCHK(c, hipMemsetAsync(ncn, 0, sizeof(Counters) * ccap, c->stream));
+    if (c->ctl) HIPCHK(c, hipMemcpyAsync(nc, c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToDevice, c->stream));
+    if (c->cnt) HIPCHK(c, hipMemcpyAsync(ncn, c->cnt, sizeof(Counters) * pidx, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c->ctl); dfree(c->cnt);
+    c->ctl = nc; c->cnt = ncn; c->ctl_cap = ncap; c->cnt_cap = ccap;
+    for (int l = 0; l < MAXLEV; ++l) c->launch[l].dirty = true;  // descriptors hold ctl pointers
+  }
+  P.L[0].boxes.push_back(Box{0, 0, nx0, ny0});
+  c->probs.push_back(P);
+  int rc = upload_mask(c, c->probs.back().L[0]);
+  if (rc) return rc;
+  for (int l = 0; l < MAXLEV; ++l) c->launch[l].dirty = true;
+  c->pdt_dirty = true;
+  *p_out = pidx;
+  return MLSWE_OK;
+}
+
+int mlswe_set_bathymetry(mlswe_ctx* c, int p, const double* Bf, int where) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || !Bf) return fail(c, MLSWE_EINVAL, "bad problem or pointer");
+  ProblemH& P = c->probs[p];
+  const LevelH& F = P.L[P.nlev - 1];
+  std::vector<double> fine((size_t)F.nx * F.ny);
+  if (where == MLSWE_DEVICE) {
+    HIPCHK(c, hipMemcpy(fine.data(), Bf, sizeof(double) * fine.size(), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(fine.data(), Bf, sizeof(double) * fine.size());
+  }
+  std::vector<double> prev;
+  for (int l = P.nlev - 1; l >= 0; --l) {
+    LevelH& L = P.L[l];
+    std::vector<double> a((size_t)L.plane, 0.0);
+    if (l == P.nlev - 1) {
+      for (int j = 0; j < L.ny; ++j)
+        for (int i = 0; i < L.nx; ++i) a[idx(L, i, j)] = fine[(size_t)j * L.nx + i];
+    } else {
+      const LevelH& Fl = P.L[l + 1];
+      const int r = P.ratio[l];
+      const double inv = 1.0 / double(r * r);
+      for (int J = 0; J < L.ny; ++J)
+        for (int I = 0; I < L.nx; ++I) {
+          double s = 0.0;
+          for (int b = 0; b < r; ++b)
+            for (int a2 = 0; a2 < r; ++a2) s = s + prev[idx(Fl, r * I + a2, r * J + b)];
+          a[idx(L, I, J)] = s * inv;
+        }
+    }
+    mirror_frame_host(L, a);
+    HIPCHK(c, hipMemcpyAsync(L.B, a.data(), sizeof(double) * a.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    prev.swap(a);
+  }
+  P.bathy = true;
+  return MLSWE_OK;
+}
+
+int mlswe_set_patches(mlswe_ctx* c, int p, int level, int n, const int32_t* boxes) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p)) return fail(c, MLSWE_EINVAL, "bad problem %d", p);
+  if (!c->probs[p].bathy) return fail(c, MLSWE_ESTATE, "set the bathymetry first");
+  return set_patches_impl(c, p, level, n, boxes);
+}
+
+int mlswe_refine(mlswe_ctx* c, int p, int fine_level, int n, const int32_t* boxes) {
+  if (!c) return MLSWE_EINVAL;
+  if (fine_level < 1) return fail(c, MLSWE_EINVAL, "refine needs a level > 0");
+  return mlswe_set_patches(c, p, fine_level, n, boxes);
+}
+
+int mlswe_get_patches(mlswe_ctx* c, int p, int level, int cap, int32_t* boxes, int* n_out) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || level < 0 || level >= c->probs[p].nlev || !n_out) return fail(c, MLSWE_EINVAL, "bad args");
+  const std::vector<Box>& B = c->probs[p].L[level].boxes;
+  if ((int)B.size() > cap || (!boxes && !B.empty())) return fail(c, MLSWE_EINVAL, "capacity %d < %zu", cap, B.size());
+  for (size_t k = 0; k < B.size(); ++k) {
+    boxes[4 * k] = B[k].ilo; boxes[4 * k + 1] = B[k].jlo; boxes[4 * k + 2] = B[k].nx; boxes[4 * k + 3] = B[k].ny;
+  }
+  *n_out = (int)B.size();
+  return MLSWE_OK;
+}
+
+int mlswe_set_state(mlswe_ctx* c, int p, int level, const double* q, int where) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || !q || level < 0 || level >= c->probs[p].nlev) return fail(c, MLSWE_EINVAL, "bad args");
+  ProblemH& P = c->probs[p];
+  LevelH& L = P.L[level];
+  int rc = copy_state(c, L, L.cur, q, where, true, nullptr);
+  if (rc) return rc;
+  P.state = true;
+  return MLSWE_OK;
+}
+
+int mlswe_get_state(mlswe_ctx* c, int p, int level, double* q, int where) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || !q || level < 0 || level >= c->probs[p].nlev) return fail(c, MLSWE_EINVAL, "bad args");
+  LevelH& L = c->probs[p].L[level];
+  if (where == MLSWE_DEVICE) return fail(c, MLSWE_EINVAL, "get_state supports host destinations");
+  int rc = copy_state(c, L, L.cur, nullptr, where, false, q);
+  if (rc) return rc;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  for (int j = 0; j < L.ny; ++j)
+    for (int i = 0; i < L.nx; ++i)
+      if (!L.mask_h[idx(L, i, j)])
+        for (int f = 0; f < 6; ++f) q[((size_t)f * L.ny + j) * L.nx + i] = nan;
+  return MLSWE_OK;
+}
+
+int mlswe_step_level(mlswe_ctx* c, int level, const double* dt, double theta, double* smax_out) {
+  if (!c) return MLSWE_EINVAL;
+  if (c->probs.empty()) return fail(c, MLSWE_ESTATE, "no problem defined");
+  const int np = (int)c->probs.size();
+  for (int p = 0; p < np; ++p) {
+    const ProblemH& P = c->probs[p];
+    if (!P.bathy || !P.state) return fail(c, MLSWE_ESTATE, "problem %d lacks bathymetry or state", p);
+    if (level < 0 || level >= P.nlev) return fail(c, MLSWE_EINVAL, "level %d missing in problem %d", level, p);
+  }
+  int rc;
+  if (dt) {
+    for (int p = 0; p < np; ++p) {
+      if (!(dt[p] > 0.0) || !std::isfinite(dt[p])) return fail(c, MLSWE_EINVAL, "dt[%d] must be positive", p);
+      HIPCHK(c, hipMemcpyAsync(&c->ctl[c->probs[p].ctl0 + level].dt, &dt[p], sizeof(double), hipMemcpyHostToDevice,
+                               c->stream));
+    }
+  }
+  if ((rc = substep(c, level, 0, np, theta, true))) return rc;
+  if (smax_out) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int status = 0;
+    for (int p = 0; p < np; ++p) {
+      LevelCtl h;
+      HIPCHK(c, hipMemcpy(&h, c->ctl + c->probs[p].ctl0 + level, sizeof h, hipMemcpyDeviceToHost));
+      smax_out[2 * p] = __builtin_bit_cast(double, (long long)h.last_smax[0]);
+      smax_out[2 * p + 1] = __builtin_bit_cast(double, (long long)h.last_smax[1]);
+      status |= h.status;
+    }
+    if (status & STATUS_CFL) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
+  }
+  return MLSWE_OK;
+}
+
+int mlswe_coarsen(mlswe_ctx* c, int p, int fine_level) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || fine_level < 1 || fine_level >= c->probs[p].nlev) return fail(c, MLSWE_EINVAL, "bad level");
+  int rc = coarsen_level(c, fine_level, p, p + 1);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MLSWE_OK;
+}
+
+int mlswe_flag(mlswe_ctx* c, int p, int level, double tau, int nbuf, uint8_t* flags_out) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || level < 0 || level >= c->probs[p].nlev || !flags_out || nbuf < 0)
+    return fail(c, MLSWE_EINVAL, "bad args");
+  std::vector<unsigned char> f;
+  int rc = flag_impl(c, p, level, tau, nbuf, f);
+  if (rc) return rc;
+  std::memcpy(flags_out, f.data(), f.size());
+  return MLSWE_OK;
+}
+
+int mlswe_regrid(mlswe_ctx* c, int p, const double* tau, int nbuf) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || !tau || nbuf < 0) return fail(c, MLSWE_EINVAL, "bad args");
+  return regrid_impl(c, p, tau, nbuf);
+}
+
+int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau, int nbuf, int mode, double* dts_out) {
+  if (!c) return MLSWE_EINVAL;
+  const int np = (int)c->probs.size();
+  if (np == 0) return fail(c, MLSWE_ESTATE, "no problem defined");
+  if (nsteps < 0 || regrid_every < 0 || (regrid_every > 0 && !tau) || nbuf < 0 ||
+      (mode != MLSWE_PLAIN && mode != MLSWE_BATCHED))
+    return fail(c, MLSWE_EINVAL, "bad advance arguments");
+  for (int p = 0; p < np; ++p)
+    if (!c->probs[p].bathy || !c->probs[p].state) return fail(c, MLSWE_ESTATE, "problem %d not initialised", p);
+  if (mode == MLSWE_BATCHED)
+    for (int p = 1; p < np; ++p) {
+      if (c->probs[p].nlev != c->probs[0].nlev) return fail(c, MLSWE_EINVAL, "batched problems need equal levels");
+      for (int l = 0; l + 1 < c->probs[p].nlev; ++l)
+        if (c->probs[p].ratio[l] != c->probs[0].ratio[l]) return fail(c, MLSWE_EINVAL, "batched ratios differ");
+    }
+  // groups of problems advanced together: all (batched) or one at a time (plain)
+  const int ngroups = mode == MLSWE_BATCHED ? 1 : np;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const int p0 = mode == MLSWE_BATCHED ? 0 : gi, p1 = mode == MLSWE_BATCHED ? np : gi + 1;
+    const bool batched = mode == MLSWE_BATCHED;
+    for (int n = 0; n < nsteps; ++n) {
+      int rc;
+      if (regrid_every > 0 && n % regrid_every == 0)
+        for (int p = p0; p < p1; ++p)
+          if ((rc = regrid_impl(c, p, tau + (size_t)p * MAXLEV, nbuf))) return rc;
+      if ((rc = build_pdt(c))) return rc;
+      bool initial = !c->probs[p0].have_dt;
+      if ((rc = next_dt(c, p0, p1, initial))) return rc;
+      for (int p = p0; p < p1; ++p) c->probs[p].have_dt = true;
+      if ((rc = adv(c, 0, p0, p1, 0.0, batched))) return rc;
+      if (dts_out || c->timing) {
+        if ((rc = collect_events(c))) return rc;
+      }
+      if (dts_out) {
+        for (int p = p0; p < p1; ++p) {
+          LevelCtl h;
+          HIPCHK(c, hipMemcpy(&h, c->ctl + c->probs[p].ctl0, sizeof h, hipMemcpyDeviceToHost));
+          dts_out[(size_t)p * nsteps + n] = h.dt;
+        }
+      }
+    }
+    int status = 0;
+    int rc = read_status(c, p0, p1, &status);
+    if (rc) return rc;
+    if (status & STATUS_CFL) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
+  }
+  return MLSWE_OK;
+}
+
+int mlswe_get_counters(mlswe_ctx* c, int p, mlswe_counters* out) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || !out) return fail(c, MLSWE_EINVAL, "bad args");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  Counters h;
+  HIPCHK(c, hipMemcpy(&h, c->cnt + c->probs[p].cnt, sizeof h, hipMemcpyDeviceToHost));
+  mlswe_counters o;
+  std::memset(&o, 0, sizeof o);
+  const ProblemH& P = c->probs[p];
+  for (int l = 0; l < P.nlev; ++l) o.cell_updates[l] = P.updates[l];
+  o.hyp = (int64_t)h.hyp; o.nclip = (int64_t)h.nclip; o.repair = (int64_t)h.repair;
+  o.clip1 = h.clip1; o.clip2 = h.clip2;
+  LevelCtl lc;
+  HIPCHK(c, hipMemcpy(&lc, c->ctl + P.ctl0, sizeof lc, hipMemcpyDeviceToHost));
+  o.t = lc.t;
+  int status = 0;
+  int rc = read_status(c, p, p + 1, &status);
+  if (rc) return rc;
+  o.status = status;
+  *out = o;
+  return MLSWE_OK;
+}
+
+int mlswe_synchronize(mlswe_ctx* c) {
+  if (!c) return MLSWE_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MLSWE_OK;
+}
+
+int mlswe_set_kernel_timing(mlswe_ctx* c, int enable) {
+  if (!c) return MLSWE_EINVAL;
+  int rc = collect_events(c);
+  if (rc) return rc;
+  c->timing = enable != 0;
+  c->kms[0] = c->kms[1] = 0.0;
+  c->klaunch[0] = c->klaunch[1] = 0;
+  return MLSWE_OK;
+}
+
+int mlswe_kernel_times(mlswe_ctx* c, double* ms_out, int64_t* launches_out) {
+  if (!c || !ms_out || !launches_out) return MLSWE_EINVAL;
+  int rc = collect_events(c);
+  if (rc) return rc;
+  ms_out[0] = c->kms[0]; ms_out[1] = c->kms[1];
+  launches_out[0] = c->klaunch[0]; launches_out[1] = c->klaunch[1];
+  return MLSWE_OK;
+}
+
+}  // extern "C"

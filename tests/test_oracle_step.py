@@ -223,3 +223,11 @@ def test_window_step_matches_full_step():
         w, _ = oracle.step_window(B, q, dx, dx, box, 7.0)
         i, j, nx, ny = box
         assert np.array_equal(w, full[:, j:j + ny, i:i + nx]), box
+
+
+def test_degenerate_domain_rejected():
+    """A reflecting wall mirrors two cells, so a level needs two cells across."""
+    import pytest as _pt
+    for nx, ny in [(1, 4), (4, 1)]:
+        with _pt.raises(ValueError):
+            oracle.Hierarchy(nx, ny, 1.0, 1.0)
