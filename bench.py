@@ -44,6 +44,30 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_sha():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1803_01450_amd", "csrc")
+    src = open(os.path.join(d, "mlswe_kernels.hip"), "rb").read() + open(os.path.join(d, "mlswe_device.hpp"), "rb").read()
+    return hashlib.sha256(src).hexdigest()
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "sweeps_roofline_grid_4096_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    sha, val = None, None
+    for line in open(path):
+        if line.startswith("kernel_source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch k_%s:" % kernel):
+            val = float(line.split(":", 1)[1])
+    if sha != kernel_source_sha() or val is None:
+        return None
+    return val
+
+
 def copy_probe(mib):
     import torch
     n = mib * (1 << 20) // 8
@@ -127,8 +151,9 @@ def main():
                         gbs=byts / avg / 1e9 if avg > 0 else 0.0))
     dom = max(per, key=lambda d: d["avg_ms"])
     achieved = dom["gbs"]
+    traffic = profiled_traffic(dom["kernel"]) if n == 4096 else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": None,
+            "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic,
             "kernel": dom["kernel"], "avg_ms": round(dom["avg_ms"], 4),
             "bytes_per_launch": dom["bytes"], "all_kernels": per}
 
