@@ -112,7 +112,9 @@ int mlswe_set_patches(mlswe_ctx* ctx, int p, int level, int n, const int32_t* bo
 int mlswe_get_patches(mlswe_ctx* ctx, int p, int level, int cap, int32_t* boxes, int* n_out);
 
 /* Level-wide state q[6][ny_l][nx_l] into / out of the level's current buffer.
- * get_state writes NaN where no patch covers a cell. Errors: MLSWE_EINVAL. */
+ * get_state writes NaN where no patch covers a cell (for a device destination
+ * the copy is queued on the context's stream; for a host one it synchronises).
+ * Errors: MLSWE_EINVAL. */
 int mlswe_set_state(mlswe_ctx* ctx, int p, int level, const double* q, int where);
 int mlswe_get_state(mlswe_ctx* ctx, int p, int level, double* q, int where);
 
@@ -166,6 +168,47 @@ int mlswe_synchronize(mlswe_ctx* ctx);
  * Synchronises. */
 int mlswe_set_kernel_timing(mlswe_ctx* ctx, int enable);
 int mlswe_kernel_times(mlswe_ctx* ctx, double* ms_out /*[2]*/, int64_t* launches_out /*[2]*/);
+
+/* ---------------------------------------------------------------- adjoint
+ * Differentiation of a fixed-grid run with a frozen dt sequence, for problems
+ * with one level whose states keep both layers wet (the solve's reverse is the
+ * transpose of its coupled branch; a dry layer anywhere makes the call fail with
+ * MLSWE_ESTATE).  All arrays are device pointers of the context's GPU in the
+ * layout of mlswe_set_state; the caller owns them. */
+
+/* n steps of problem p's level 0 with the given substeps (host array [n]),
+ * without any host round trip. */
+int mlswe_run_fixed(mlswe_ctx* ctx, int p, int n, const double* dts);
+
+/* lam_n = (dQ_{n+1}/dQ_n)^T lam_np1 and B_bar += (dQ_{n+1}/dB)^T lam_np1 for the
+ * step Q_{n+1} = S(Q_n; B, dt) of problem p (walls, x-sweep, y-sweep; the
+ * dry-state fix-ups are the identity on wet states).  q_n, lam_np1, lam_n:
+ * [6][ny][nx]; B_bar: [ny][nx]. */
+int mlswe_adjoint_step(mlswe_ctx* ctx, int p, const double* q_n, const double* lam_np1, double* lam_n,
+                       double* B_bar, double dt);
+
+/* Initial state q [6][ny][nx] from the top surface eta1_0 [ny][nx], the
+ * problem's bathymetry and a flat interface eta2_0: h2 = eta2_0 - B,
+ * h1 = eta1_0 - eta2_0, at rest, thin layers dry.  And its adjoint:
+ * eta1_bar = dh1 part of lam0 (written), B_bar -= dh2 part of lam0 (accumulated). */
+int mlswe_param_map(mlswe_ctx* ctx, int p, const double* eta1_0, double eta2_0, double* q_out);
+int mlswe_param_map_adjoint(mlswe_ctx* ctx, int p, const double* eta1_0, double eta2_0, const double* lam0,
+                            double* eta1_bar, double* B_bar);
+
+/* Gauge misfit: *loss += sum over the gn x gn cells at (i0, j0) of
+ * (eta1 - target)^2 with eta1 = B + h2 + h1, from q [6][ny][nx] or, if q is
+ * NULL, from the problem's current level-0 state.  If lam is not NULL its h1
+ * and h2 parts get 2 (eta1 - target) added (and B_bar too if not NULL). */
+int mlswe_gauge_misfit(mlswe_ctx* ctx, int p, const double* q, int i0, int j0, int gn, const double* target,
+                       double* loss, double* lam, double* B_bar);
+
+/* Branch signature for derivative checks: with enable = 1 the sweeps add, per
+ * problem, a position-hashed code of every limiter branch and wave direction
+ * to a 64-bit sum (enable = 0 stops, -1 leaves the setting); with sig_out not
+ * NULL the sum of problem p is returned and cleared.  Two runs with equal sums
+ * took the same branches (with overwhelming probability), so a finite
+ * difference between them sees a smooth map.  Synchronises when reading. */
+int mlswe_branch_signature(mlswe_ctx* ctx, int enable, int p, uint64_t* sig_out);
 
 #ifdef __cplusplus
 }

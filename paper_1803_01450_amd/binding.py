@@ -77,6 +77,12 @@ def lib():
             "mlswe_synchronize": (I, [P]),
             "mlswe_set_kernel_timing": (I, [P, I]),
             "mlswe_kernel_times": (I, [P, DP, ctypes.POINTER(ctypes.c_int64)]),
+            "mlswe_run_fixed": (I, [P, I, I, DP]),
+            "mlswe_adjoint_step": (I, [P, I, V, V, V, V, D]),
+            "mlswe_param_map": (I, [P, I, V, D, V]),
+            "mlswe_param_map_adjoint": (I, [P, I, V, D, V, V, V]),
+            "mlswe_gauge_misfit": (I, [P, I, V, I, I, I, V, V, V, V]),
+            "mlswe_branch_signature": (I, [P, I, I, ctypes.POINTER(ctypes.c_uint64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -232,6 +238,17 @@ class Solver:
         nl = len(self.shapes[p])
         return dict(updates=[int(c.cell_updates[l]) for l in range(nl)], hyp=int(c.hyp), nclip=int(c.nclip),
                     repair=int(c.repair), clip1=c.clip1, clip2=c.clip2, t=c.t, status=int(c.status))
+
+    def run_fixed(self, p, dts):
+        d = _f64(dts)
+        self._check(self.L.mlswe_run_fixed(self.h, p, d.shape[0], d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def branch_signature(self, p, enable=-1):
+        """Returns and clears problem p's branch signature; enable 1/0 switches
+        the accumulation on/off (-1 leaves it)."""
+        v = ctypes.c_uint64()
+        self._check(self.L.mlswe_branch_signature(self.h, enable, p, ctypes.byref(v)))
+        return v.value
 
     def synchronize(self):
         self._check(self.L.mlswe_synchronize(self.h))

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmlswe.so")
-SRCS = [os.path.join(HERE, "csrc", "mlswe_kernels.hip"), os.path.join(HERE, "csrc", "mlswe_lib.cpp")]
+SRCS = [os.path.join(HERE, "csrc", "mlswe_kernels.hip"), os.path.join(HERE, "csrc", "mlswe_adjoint.hip"),
+        os.path.join(HERE, "csrc", "mlswe_lib.cpp")]
 HDRS = [os.path.join(HERE, "csrc", "mlswe_kernels.hpp"), os.path.join(HERE, "csrc", "mlswe_device.hpp"),
         os.path.join(ROOT, "include", "mlswe.h")]
 ARCH = os.environ.get("MLSWE_ARCH", "gfx950")
@@ -26,7 +27,10 @@ FLAGS = [
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + ["-x", "hip", SRCS[0], "-x", "hip", SRCS[1], "-o", tmp]
+    cmd = [hipcc] + FLAGS
+    for src in SRCS:
+        cmd += ["-x", "hip", src]
+    cmd += ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

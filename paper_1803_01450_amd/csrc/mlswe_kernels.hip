@@ -72,6 +72,44 @@ __device__ __forceinline__ void flush_counts(Counters* cnt, LevelCtl* ctl, int a
   }
 }
 
+// Branch code of wave p's limiter and speed sign at an edge, weighted by a hash
+// of the edge position; sums of these over a run change (almost surely) when any
+// limiter branch or wave direction changes.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ unsigned long long branch_sig(const EdgeW& W, const double dd[6], const double dl[6],
+                                                         const double dr[6], int i, int j, int axis) {
+  unsigned long long acc = 0;
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    const double sv = W.s[p];
+    unsigned code = sv > 0.0 ? 1u : (sv < 0.0 ? 2u : 3u);
+    if (slot_mode(W, p) == 0 && sv != 0.0 && dd[p] != 0.0) {
+      const double th = (sv > 0.0 ? dl[p] : dr[p]) / dd[p];
+      const double a = 0.5 * (1.0 + th), b = 2.0 * th;
+      const double m1 = a < 2.0 ? a : 2.0;
+      const double m = m1 < b ? m1 : b;
+      unsigned br = (0.0 > m) ? 1u : (m1 < b ? (a < 2.0 ? 2u : 3u) : 4u);
+      code |= br << 2;
+    }
+    const unsigned long long key =
+        ((unsigned long long)(unsigned)i << 32) ^ ((unsigned long long)(unsigned)j << 4) ^ (unsigned)(axis * 8 + p);
+    acc += (unsigned long long)code * mix64(key);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ unsigned long long wave_usum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ double edge_smax(const EdgeW& W) {
   double m = 0.0;
 #pragma unroll
@@ -106,6 +144,7 @@ __global__ __launch_bounds__(256) void k_sweep_x(const PatchDev* __restrict__ pa
   const double nu = Pd.ctl->dt / Pd.dx;
   double smax = 0.0;
   int hyp = 0;
+  unsigned long long sig = 0;
   FixCount K = {0, 0, 0.0, 0.0};
 
   double nq[7];
@@ -151,6 +190,7 @@ __global__ __launch_bounds__(256) void k_sweep_x(const PatchDev* __restrict__ pa
     double coef[6], F[6], am[6], ap[6];
 #pragma unroll
     for (int p = 0; p < 6; ++p) coef[p] = corr_coef(W, p, dd[p], dl[p], dr[p], nu);
+    if (Pd.sig_on && own) sig += branch_sig(W, dd, dl, dr, c, j, 0);
     correction_flux(W, coef, F);
     fluctuations(W, am, ap);
     double gl[6], gr[6];
@@ -170,6 +210,10 @@ __global__ __launch_bounds__(256) void k_sweep_x(const PatchDev* __restrict__ pa
     }
   }
   flush_counts(Pd.cnt, Pd.ctl, 0, smax, hyp, K, lane);
+  if (Pd.sig_on) {
+    sig = wave_usum(sig);
+    if (lane == 0) atomicAdd(&Pd.cnt->sig, sig);
+  }
 }
 
 // ---------------------------------------------------------------- y-sweep
@@ -194,6 +238,7 @@ __global__ __launch_bounds__(256) void k_sweep_y(const PatchDev* __restrict__ pa
   const double nu = Pd.ctl->dt / Pd.dy;
   double smax = 0.0;
   int hyp = 0;
+  unsigned long long sig = 0;
   FixCount K = {0, 0, 0.0, 0.0};
 
   CellX Cp;
@@ -242,6 +287,7 @@ __global__ __launch_bounds__(256) void k_sweep_y(const PatchDev* __restrict__ pa
           double coef[6], F[6], am[6], ap[6];
 #pragma unroll
           for (int p = 0; p < 6; ++p) coef[p] = corr_coef(Wp, p, ddp[p], dlp[p], dlc[p], nu);
+          if (Pd.sig_on && act) sig += branch_sig(Wp, ddp, dlp, dlc, i, jj - 1, 1);
           correction_flux(Wp, coef, F);
           fluctuations(Wp, am, ap);
           if (k >= 4 && act) {
@@ -276,6 +322,10 @@ __global__ __launch_bounds__(256) void k_sweep_y(const PatchDev* __restrict__ pa
     Cp = Cc;
   }
   flush_counts(Pd.cnt, Pd.ctl, 1, smax, hyp, K, lane);
+  if (Pd.sig_on) {
+    sig = wave_usum(sig);
+    if (lane == 0) atomicAdd(&Pd.cnt->sig, sig);
+  }
 }
 
 // ---------------------------------------------------------------- ghost cells
@@ -552,5 +602,18 @@ __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int n
 }
 
 __global__ void k_set_theta(double* th, double v) { *th = v; }
+
+// Cells of a level-wide copy [6][ny][nx] that no patch covers read NaN.
+__global__ __launch_bounds__(256) void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask,
+                                                       long long pitch, int nx, int ny) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long pu = (long long)nx * ny;
+  if (t >= pu) return;
+  const int i = (int)(t % nx), j = (int)(t / nx);
+  if (mask[cidx(pitch, i, j)]) return;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) q[f * pu + t] = nan;
+}
 
 }  // namespace mlswe

@@ -12,7 +12,8 @@ constexpr int STATUS_NAN = 2;
 struct Counters {
   unsigned long long hyp, nclip, repair;
   double clip1, clip2;
-  unsigned long long pad[3];
+  unsigned long long sig;  // branch signature (sum of position-hashed limiter branches)
+  unsigned long long pad[2];
 };
 
 // Device-resident time-step control of one (problem, level).
@@ -38,6 +39,7 @@ struct PatchDev {
   int ilo, jlo, nx, ny;
   double dx, dy;
   PhysParams P;
+  int sig_on;        // accumulate the branch signature into cnt->sig
 };
 
 struct XTile { int patch, i0, ncols, j0, nrows; };
@@ -99,6 +101,60 @@ struct ProbDt {
   double* dt_out;
 };
 
+// Lines of one sweep for the adjoint: cell (line, k) at base + line * lstride
+// + k * kstride, field f at + f * plane.  orient 0: normal momentum hu (x-sweep),
+// 1: hv (y-sweep).  Cells -2..n+1 exist, cells 0..n-1 are updated.
+struct AdjView {
+  const double* q;
+  const double* B;
+  const double* lam;   // adjoint of the sweep's outputs (read at cells 0..n-1)
+  double* cL;          // 7 planes: contribution of edge e to its left cell, at e
+  double* cR;          // 7 planes: contribution of edge e to its right cell, at e
+  long long plane, lstride, kstride, base;
+  int nlines, n, orient;
+  double nu;
+  PhysParams P;
+  int* status;
+};
+
+struct AdjFold {
+  const double* lam_g;   // adjoint of the wall-filled state (level layout)
+  const double* Bbx;     // bathymetry adjoint from the x-sweep (level layout)
+  const double* Bby;     // from the y-sweep (level layout, interior columns)
+  double* lam_out;       // [6][ny][nx]
+  double* Bbar;          // [ny][nx], accumulated
+  long long pitch, plane;
+  int nx, ny;
+};
+
+struct ParamMap {
+  const double* eta1;  // [ny][nx]
+  const double* B;     // level array
+  double* q;           // [6][ny][nx]
+  long long pitch;
+  int nx, ny;
+  double eta2, hdry;
+};
+
+struct Gauge {
+  const double* q;       // state: level layout (qlevel = 1) or [6][ny][nx]
+  const double* B;       // level array
+  const double* target;  // [gn][gn]
+  double* loss;          // device scalar (accumulated) or null
+  double* lam;           // [6][ny][nx] accumulated source or null
+  double* B_bar;         // [ny][nx] accumulated or null
+  long long pitch, qplane;
+  int nx, ny, i0, j0, gn, qlevel;
+};
+
+__global__ void k_adj_edges(AdjView V);
+__global__ void k_adj_gather(AdjView V, double* lam_in, double* Bbar);
+__global__ void k_adj_fold(AdjFold F);
+__global__ void k_param_map(ParamMap M);
+__global__ void k_param_map_adj(ParamMap M, const double* __restrict__ lam0, double* eta1_bar, double* B_bar);
+__global__ void k_gauge(Gauge G);
+__global__ void k_set_dt(LevelCtl* ctl, const double* __restrict__ dts, int k);
+
 __global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles);
 __global__ void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles);
 __global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass);
@@ -110,6 +166,7 @@ __global__ void k_after_substep(LevelCtl* ctls, const LevelInfo* infos, int n, d
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
 __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial);
 __global__ void k_set_theta(double* th, double v);
+__global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);
 __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob);
 
 }  // namespace mlswe

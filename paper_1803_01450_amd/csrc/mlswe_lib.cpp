@@ -42,7 +42,22 @@ struct LevelH {
   std::vector<Box> boxes;
 };
 
+// Device buffers of the adjoint step (level layout), allocated on first use.
+struct AdjBuf {
+  double* lam1 = nullptr;  // adjoint of the step's output
+  double* lamS = nullptr;  // adjoint of the x-swept state
+  double* lamG = nullptr;  // adjoint of the wall-filled state
+  double* cL = nullptr;    // per-edge contributions (7 planes)
+  double* cR = nullptr;
+  double* Bbx = nullptr;
+  double* Bby = nullptr;
+  int* status = nullptr;
+  double* dts = nullptr;
+  int dts_cap = 0;
+};
+
 struct ProblemH {
+  AdjBuf adj;
   PhysParams P;
   int nlev = 1;
   int ratio[MAXLEV] = {0};
@@ -103,6 +118,7 @@ struct mlswe_ctx {
   long long klaunch[2] = {0, 0};
   double* dt_stage = nullptr;
   int dt_stage_cap = 0;
+  int sig_on = 0;
 };
 
 namespace {
@@ -249,6 +265,7 @@ int build_launch(mlswe_ctx* c, int l) {
         d.pitch = L.pitch; d.plane = L.plane;
         d.ilo = b.ilo; d.jlo = b.jlo; d.nx = b.nx; d.ny = b.ny;
         d.dx = L.dx; d.dy = L.dy; d.P = P.P;
+        d.sig_on = c->sig_on;
         pd[par].push_back(d);
       }
       LL.patch_prob.push_back((int)pi);
@@ -716,7 +733,9 @@ int copy_state(mlswe_ctx* c, LevelH& L, int buf, const double* src, int where, b
       HIPCHK(c, hipMemcpy2DAsync(dst + (size_t)f * L.nx * L.ny, hrow, lv, L.pitch * sizeof(double), hrow, L.ny, kind,
                                  c->stream));
   }
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // device-to-device copies stay ordered on the stream; host memory is released
+  // to the caller only once the copy is done
+  if (where != MLSWE_DEVICE) HIPCHK(c, hipStreamSynchronize(c->stream));
   return MLSWE_OK;
 }
 
@@ -761,6 +780,10 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
 int mlswe_destroy(mlswe_ctx* c) {
   if (!c) return MLSWE_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  for (ProblemH& P : c->probs) {
+    dfree(P.adj.lam1); dfree(P.adj.lamS); dfree(P.adj.lamG); dfree(P.adj.cL); dfree(P.adj.cR);
+    dfree(P.adj.Bbx); dfree(P.adj.Bby); dfree(P.adj.status); dfree(P.adj.dts);
+  }
   for (ProblemH& P : c->probs)
     for (int l = 0; l < P.nlev; ++l) {
       LevelH& L = P.L[l];
@@ -936,9 +959,15 @@ int mlswe_get_state(mlswe_ctx* c, int p, int level, double* q, int where) {
   if (!c) return MLSWE_EINVAL;
   if (!valid_prob(c, p) || !q || level < 0 || level >= c->probs[p].nlev) return fail(c, MLSWE_EINVAL, "bad args");
   LevelH& L = c->probs[p].L[level];
-  if (where == MLSWE_DEVICE) return fail(c, MLSWE_EINVAL, "get_state supports host destinations");
   int rc = copy_state(c, L, L.cur, nullptr, where, false, q);
   if (rc) return rc;
+  if (where == MLSWE_DEVICE) {
+    const long long pu = (long long)L.nx * L.ny;
+    hipLaunchKernelGGL(k_nan_uncovered, dim3((unsigned)((pu + 255) / 256)), dim3(256), 0, c->stream, q, L.mask,
+                       L.pitch, L.nx, L.ny);
+    HIPCHK(c, hipGetLastError());
+    return MLSWE_OK;
+  }
   const double nan = std::numeric_limits<double>::quiet_NaN();
   for (int j = 0; j < L.ny; ++j)
     for (int i = 0; i < L.nx; ++i)
@@ -1100,6 +1129,193 @@ int mlswe_kernel_times(mlswe_ctx* c, double* ms_out, int64_t* launches_out) {
   if (rc) return rc;
   ms_out[0] = c->kms[0]; ms_out[1] = c->kms[1];
   launches_out[0] = c->klaunch[0]; launches_out[1] = c->klaunch[1];
+  return MLSWE_OK;
+}
+
+// ------------------------------------------------------------ adjoint
+static int ensure_adj(mlswe_ctx* c, ProblemH& P) {
+  AdjBuf& A = P.adj;
+  if (A.lam1) return MLSWE_OK;
+  const LevelH& L = P.L[0];
+  const size_t pb = sizeof(double) * (size_t)L.plane;
+  int rc;
+  if ((rc = dalloc(c, (void**)&A.lam1, 6 * pb)) || (rc = dalloc(c, (void**)&A.lamS, 6 * pb)) ||
+      (rc = dalloc(c, (void**)&A.lamG, 6 * pb)) || (rc = dalloc(c, (void**)&A.cL, 7 * pb)) ||
+      (rc = dalloc(c, (void**)&A.cR, 7 * pb)) || (rc = dalloc(c, (void**)&A.Bbx, pb)) ||
+      (rc = dalloc(c, (void**)&A.Bby, pb)) || (rc = dalloc(c, (void**)&A.status, sizeof(int))))
+    return rc;
+  HIPCHK(c, hipMemsetAsync(A.lam1, 0, 6 * pb, c->stream));
+  HIPCHK(c, hipMemsetAsync(A.lamS, 0, 6 * pb, c->stream));
+  HIPCHK(c, hipMemsetAsync(A.lamG, 0, 6 * pb, c->stream));
+  HIPCHK(c, hipMemsetAsync(A.cL, 0, 7 * pb, c->stream));
+  HIPCHK(c, hipMemsetAsync(A.cR, 0, 7 * pb, c->stream));
+  HIPCHK(c, hipMemsetAsync(A.Bbx, 0, pb, c->stream));
+  HIPCHK(c, hipMemsetAsync(A.Bby, 0, pb, c->stream));
+  HIPCHK(c, hipMemsetAsync(A.status, 0, sizeof(int), c->stream));
+  return MLSWE_OK;
+}
+
+static int check_single(mlswe_ctx* c, int p) {
+  if (!valid_prob(c, p)) return fail(c, MLSWE_EINVAL, "bad problem %d", p);
+  const ProblemH& P = c->probs[p];
+  if (!P.bathy) return fail(c, MLSWE_ESTATE, "set the bathymetry first");
+  const LevelH& L = P.L[0];
+  if (L.boxes.size() != 1 || L.boxes[0].nx != L.nx || L.boxes[0].ny != L.ny)
+    return fail(c, MLSWE_EINVAL, "level 0 must be a single patch over the domain");
+  return MLSWE_OK;
+}
+
+static unsigned blocks(long long n) { return (unsigned)((n + 255) / 256); }
+
+extern "C" int mlswe_run_fixed(mlswe_ctx* c, int p, int n, const double* dts) {
+  if (!c) return MLSWE_EINVAL;
+  int rc = check_single(c, p);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && !dts)) return fail(c, MLSWE_EINVAL, "bad step list");
+  ProblemH& P = c->probs[p];
+  if (!P.state) return fail(c, MLSWE_ESTATE, "set the state first");
+  for (int k = 0; k < n; ++k)
+    if (!(dts[k] > 0.0) || !std::isfinite(dts[k])) return fail(c, MLSWE_EINVAL, "dt[%d] must be positive", k);
+  if (n > P.adj.dts_cap) {
+    dfree(P.adj.dts);
+    P.adj.dts = nullptr;
+    if ((rc = dalloc(c, (void**)&P.adj.dts, sizeof(double) * (size_t)n))) return rc;
+    P.adj.dts_cap = n;
+  }
+  if (n == 0) return MLSWE_OK;
+  HIPCHK(c, hipMemcpyAsync(P.adj.dts, dts, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, c->stream, c->ctl + P.ctl0, P.adj.dts, k);
+    if ((rc = substep(c, 0, p, p + 1, 0.0, false))) return rc;
+  }
+  return MLSWE_OK;
+}
+
+extern "C" int mlswe_adjoint_step(mlswe_ctx* c, int p, const double* q_n, const double* lam_np1, double* lam_n,
+                                  double* B_bar, double dt) {
+  if (!c) return MLSWE_EINVAL;
+  int rc = check_single(c, p);
+  if (rc) return rc;
+  if (!q_n || !lam_np1 || !lam_n || !B_bar || !(dt > 0.0)) return fail(c, MLSWE_EINVAL, "bad adjoint arguments");
+  ProblemH& P = c->probs[p];
+  LevelH& L = P.L[0];
+  if ((rc = ensure_adj(c, P))) return rc;
+  AdjBuf& A = P.adj;
+  // forward recomputation: state, walls, x-sweep
+  if ((rc = copy_state(c, L, L.cur, q_n, MLSWE_DEVICE, true, nullptr))) return rc;
+  HIPCHK(c, hipMemcpyAsync(&c->ctl[P.ctl0].dt, &dt, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if ((rc = build_launch(c, 0))) return rc;
+  if ((rc = launch_fill(c, 0, p, p + 1, 0.0))) return rc;
+  LevelLaunch& LL = c->launch[0];
+  int k0 = -1;
+  for (int k = 0; k < LL.nptch; ++k)
+    if (LL.patch_prob[k] == p) { k0 = k; break; }
+  if (k0 < 0) return fail(c, MLSWE_ESTATE, "problem %d has no patch", p);
+  if ((rc = launch_sweeps(c, 0, L.cur, LL.xr[k0].first, LL.xr[k0].second, 0, 0))) return rc;
+  // adjoint of the step's output into the level layout
+  for (int f = 0; f < 6; ++f)
+    HIPCHK(c, hipMemcpy2DAsync(A.lam1 + f * L.plane + idx(L, 0, 0), L.pitch * sizeof(double),
+                               lam_np1 + (size_t)f * L.nx * L.ny, (size_t)L.nx * sizeof(double),
+                               (size_t)L.nx * sizeof(double), L.ny, hipMemcpyDeviceToDevice, c->stream));
+  AdjView V;
+  std::memset(&V, 0, sizeof V);
+  V.B = L.B; V.cL = A.cL; V.cR = A.cR; V.plane = L.plane; V.P = P.P; V.status = A.status;
+  // y-sweep lines: columns, cells along rows
+  V.q = L.qs; V.lam = A.lam1;
+  V.lstride = 1; V.kstride = L.pitch; V.base = idx(L, 0, 0);
+  V.nlines = L.nx; V.n = L.ny; V.orient = 1; V.nu = dt / L.dy;
+  hipLaunchKernelGGL(k_adj_edges, dim3(blocks((long long)L.nx * (L.ny + 3))), dim3(256), 0, c->stream, V);
+  hipLaunchKernelGGL(k_adj_gather, dim3(blocks((long long)L.nx * (L.ny + 4))), dim3(256), 0, c->stream, V, A.lamS,
+                     A.Bby);
+  // x-sweep lines: rows -2..ny+1 of the wall-filled state, cells along x
+  V.q = L.q[L.cur]; V.lam = A.lamS;
+  V.lstride = L.pitch; V.kstride = 1; V.base = idx(L, 0, -2);
+  V.nlines = L.ny + 4; V.n = L.nx; V.orient = 0; V.nu = dt / L.dx;
+  hipLaunchKernelGGL(k_adj_edges, dim3(blocks((long long)(L.ny + 4) * (L.nx + 3))), dim3(256), 0, c->stream, V);
+  hipLaunchKernelGGL(k_adj_gather, dim3(blocks((long long)(L.ny + 4) * (L.nx + 4))), dim3(256), 0, c->stream, V,
+                     A.lamG, A.Bbx);
+  AdjFold F;
+  F.lam_g = A.lamG; F.Bbx = A.Bbx; F.Bby = A.Bby; F.lam_out = lam_n; F.Bbar = B_bar;
+  F.pitch = L.pitch; F.plane = L.plane; F.nx = L.nx; F.ny = L.ny;
+  hipLaunchKernelGGL(k_adj_fold, dim3(blocks((long long)L.nx * L.ny)), dim3(256), 0, c->stream, F);
+  HIPCHK(c, hipGetLastError());
+  // the recomputed x-sweep must not leave speeds behind for the next real step
+  HIPCHK(c, hipMemsetAsync(&c->ctl[P.ctl0].step_smax[0], 0, 2 * sizeof(unsigned long long), c->stream));
+  int st = 0;
+  HIPCHK(c, hipMemcpyAsync(&st, A.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (st) {
+    HIPCHK(c, hipMemsetAsync(A.status, 0, sizeof(int), c->stream));
+    return fail(c, MLSWE_ESTATE, "adjoint needs both layers wet at every edge");
+  }
+  return MLSWE_OK;
+}
+
+extern "C" int mlswe_branch_signature(mlswe_ctx* c, int enable, int p, uint64_t* sig_out) {
+  if (!c) return MLSWE_EINVAL;
+  if (enable >= 0 && (enable ? 1 : 0) != c->sig_on) {
+    c->sig_on = enable ? 1 : 0;
+    for (int l = 0; l < MAXLEV; ++l) c->launch[l].dirty = true;
+  }
+  if (sig_out) {
+    if (!valid_prob(c, p)) return fail(c, MLSWE_EINVAL, "bad problem %d", p);
+    Counters h;
+    HIPCHK(c, hipMemcpyAsync(&h, c->cnt + c->probs[p].cnt, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *sig_out = h.sig;
+    h.sig = 0;
+    HIPCHK(c, hipMemcpyAsync(c->cnt + c->probs[p].cnt, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return MLSWE_OK;
+}
+
+extern "C" int mlswe_param_map(mlswe_ctx* c, int p, const double* eta1_0, double eta2_0, double* q_out) {
+  if (!c) return MLSWE_EINVAL;
+  int rc = check_single(c, p);
+  if (rc) return rc;
+  if (!eta1_0 || !q_out) return fail(c, MLSWE_EINVAL, "null pointer");
+  const LevelH& L = c->probs[p].L[0];
+  ParamMap M;
+  M.eta1 = eta1_0; M.B = L.B; M.q = q_out; M.pitch = L.pitch; M.nx = L.nx; M.ny = L.ny;
+  M.eta2 = eta2_0; M.hdry = c->probs[p].P.hdry;
+  hipLaunchKernelGGL(k_param_map, dim3(blocks((long long)L.nx * L.ny)), dim3(256), 0, c->stream, M);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
+extern "C" int mlswe_param_map_adjoint(mlswe_ctx* c, int p, const double* eta1_0, double eta2_0, const double* lam0,
+                                       double* eta1_bar, double* B_bar) {
+  if (!c) return MLSWE_EINVAL;
+  int rc = check_single(c, p);
+  if (rc) return rc;
+  if (!eta1_0 || !lam0 || !eta1_bar || !B_bar) return fail(c, MLSWE_EINVAL, "null pointer");
+  const LevelH& L = c->probs[p].L[0];
+  ParamMap M;
+  M.eta1 = eta1_0; M.B = L.B; M.q = nullptr; M.pitch = L.pitch; M.nx = L.nx; M.ny = L.ny;
+  M.eta2 = eta2_0; M.hdry = c->probs[p].P.hdry;
+  hipLaunchKernelGGL(k_param_map_adj, dim3(blocks((long long)L.nx * L.ny)), dim3(256), 0, c->stream, M, lam0,
+                     eta1_bar, B_bar);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
+extern "C" int mlswe_gauge_misfit(mlswe_ctx* c, int p, const double* q, int i0, int j0, int gn, const double* target,
+                                  double* loss, double* lam, double* B_bar) {
+  if (!c) return MLSWE_EINVAL;
+  int rc = check_single(c, p);
+  if (rc) return rc;
+  const LevelH& L = c->probs[p].L[0];
+  if (!target || gn <= 0 || i0 < 0 || j0 < 0 || i0 + gn > L.nx || j0 + gn > L.ny)
+    return fail(c, MLSWE_EINVAL, "gauge region outside the domain");
+  Gauge G;
+  G.q = q ? q : L.q[L.cur]; G.qlevel = q ? 0 : 1;
+  G.qplane = q ? (long long)L.nx * L.ny : L.plane;
+  G.B = L.B; G.target = target; G.loss = loss; G.lam = lam; G.B_bar = B_bar;
+  G.pitch = L.pitch; G.nx = L.nx; G.ny = L.ny; G.i0 = i0; G.j0 = j0; G.gn = gn;
+  hipLaunchKernelGGL(k_gauge, dim3(1), dim3(256), 0, c->stream, G);
+  HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
 
