@@ -41,7 +41,7 @@ enum {
 };
 
 enum { MLSWE_HOST = 0, MLSWE_DEVICE = 1 };
-enum { MLSWE_PLAIN = 0, MLSWE_BATCHED = 1 };
+enum { MLSWE_PLAIN = 0, MLSWE_BATCHED = 1, MLSWE_GRAPH = 2 };
 
 typedef struct mlswe_ctx mlswe_ctx;
 
@@ -55,6 +55,17 @@ typedef struct mlswe_config {
   int x_rows;         /* rows per x-sweep wave (0 = 16) */
   int64_t max_device_bytes; /* cap on the library's device memory (0 = none) */
 } mlswe_config;
+
+/* Launch shape of the two sweep kernels.  rows: rows of a patch per x-sweep
+ * wave / per y-sweep wave (a y wave marches its rows with the last edge in
+ * registers).  sched: 0 one wave per tile, 1 persistent waves striding over
+ * the tile list, 2 persistent waves taking tiles from an atomic ticket.
+ * grid: persistent blocks of four waves per compute unit. */
+typedef struct mlswe_tuning {
+  int x_rows, y_rows;
+  int sched_x, sched_y;
+  int grid_x, grid_y;
+} mlswe_tuning;
 
 typedef struct mlswe_counters {
   int64_t cell_updates[8]; /* interior cells stepped, per level, summed over substeps */
@@ -150,11 +161,26 @@ int mlswe_regrid(mlswe_ctx* ctx, int p, const double* tau, int nbuf);
  * step's largest speeds (first step: from the state), each level l > 0 takes
  * r_{l-1} substeps per step of level l-1 and is then averaged onto it (Sec. 2).
  * mode MLSWE_PLAIN launches the sweeps per patch; MLSWE_BATCHED launches one
- * x-sweep and one y-sweep per level substep over the patches of all problems.
+ * x-sweep and one y-sweep per level substep over the patches of all problems;
+ * MLSWE_GRAPH does the same and replays each coarse step from a captured
+ * hipGraph (captured on first use, again after a regrid; the first step of a
+ * run, which derives dt from the state, runs uncaptured).
  * dts_out (nullable, host [n_problems][n_coarse_steps]) receives the coarse
  * steps.  Errors: MLSWE_EINVAL, MLSWE_ESTATE, MLSWE_ECFL. */
 int mlswe_advance(mlswe_ctx* ctx, int n_coarse_steps, int regrid_every, const double* tau, int nbuf,
                   int mode, double* dts_out);
+
+/* Reads / sets the sweeps' launch shape (setting rebuilds the launch data). */
+int mlswe_get_tuning(mlswe_ctx* ctx, mlswe_tuning* out);
+int mlswe_set_tuning(mlswe_ctx* ctx, const mlswe_tuning* t);
+
+/* Times candidate launch shapes of the x- and y-sweeps on the current patches
+ * of every problem (the states are left unchanged: the sweeps write only the
+ * intermediate and the spare buffer, and counters and speeds are restored),
+ * keeps the fastest, and records it in the text file cache_path under a key of
+ * the patch layout (nullable); a matching cache entry is applied without
+ * timing.  reps: launches per candidate (0 = 3).  Synchronises. */
+int mlswe_autotune(mlswe_ctx* ctx, const char* cache_path, int reps);
 
 /* Counters of problem p (synchronises). */
 int mlswe_get_counters(mlswe_ctx* ctx, int p, mlswe_counters* out);

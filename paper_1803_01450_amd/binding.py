@@ -16,7 +16,7 @@ LIBPATH = os.path.join(HERE, "libmlswe.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ECFL, ENAN, ESTATE = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
-PLAIN, BATCHED = 0, 1
+PLAIN, BATCHED, GRAPH = 0, 1, 2
 MAXLEV = 8
 
 ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECFL: "ECFL", ENAN: "ENAN", ESTATE: "ESTATE"}
@@ -33,6 +33,11 @@ class CountersC(ctypes.Structure):
     _fields_ = [("cell_updates", ctypes.c_int64 * 8), ("hyp", ctypes.c_int64), ("nclip", ctypes.c_int64),
                 ("repair", ctypes.c_int64), ("clip1", ctypes.c_double), ("clip2", ctypes.c_double),
                 ("t", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("x_rows", ctypes.c_int), ("y_rows", ctypes.c_int), ("sched_x", ctypes.c_int),
+                ("sched_y", ctypes.c_int), ("grid_x", ctypes.c_int), ("grid_y", ctypes.c_int)]
 
 
 class MlsweError(RuntimeError):
@@ -83,6 +88,9 @@ def lib():
             "mlswe_param_map_adjoint": (I, [P, I, V, D, V, V, V]),
             "mlswe_gauge_misfit": (I, [P, I, V, I, I, I, V, V, V, V]),
             "mlswe_branch_signature": (I, [P, I, I, ctypes.POINTER(ctypes.c_uint64)]),
+            "mlswe_get_tuning": (I, [P, ctypes.POINTER(Tuning)]),
+            "mlswe_set_tuning": (I, [P, ctypes.POINTER(Tuning)]),
+            "mlswe_autotune": (I, [P, ctypes.c_char_p, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -242,6 +250,22 @@ class Solver:
     def run_fixed(self, p, dts):
         d = _f64(dts)
         self._check(self.L.mlswe_run_fixed(self.h, p, d.shape[0], d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def tuning(self):
+        t = Tuning()
+        self._check(self.L.mlswe_get_tuning(self.h, ctypes.byref(t)))
+        return dict(x_rows=t.x_rows, y_rows=t.y_rows, sched_x=t.sched_x, sched_y=t.sched_y,
+                    grid_x=t.grid_x, grid_y=t.grid_y)
+
+    def set_tuning(self, **kw):
+        cur = self.tuning()
+        cur.update(kw)
+        t = Tuning(cur["x_rows"], cur["y_rows"], cur["sched_x"], cur["sched_y"], cur["grid_x"], cur["grid_y"])
+        self._check(self.L.mlswe_set_tuning(self.h, ctypes.byref(t)))
+
+    def autotune(self, cache_path=None, reps=3):
+        self._check(self.L.mlswe_autotune(self.h, cache_path.encode() if cache_path else None, reps))
+        return self.tuning()
 
     def branch_signature(self, p, enable=-1):
         """Returns and clears problem p's branch signature; enable 1/0 switches

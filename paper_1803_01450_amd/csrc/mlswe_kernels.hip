@@ -125,11 +125,8 @@ __device__ __forceinline__ double edge_smax(const EdgeW& W) {
 // lane l lies between columns i0 - 3 + l and i0 - 2 + l.  Lanes 2..ncols+1 own
 // the tile's interior cells.  Writes the x-swept, fixed-up state of the tile's
 // rows (interior and frame rows of the patch) into the intermediate buffer.
-__global__ __launch_bounds__(256) void k_sweep_x(const PatchDev* __restrict__ patches,
-                                                 const XTile* __restrict__ tiles, int ntiles) {
-  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wv >= ntiles) return;
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void sweep_x_tile(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles,
+                                             int wv, int lane) {
   const XTile T = tiles[wv];
   const PatchDev& Pd = patches[T.patch];
   const PhysParams P = Pd.P;
@@ -221,11 +218,8 @@ __global__ __launch_bounds__(256) void k_sweep_x(const PatchDev* __restrict__ pa
 // j0 - 2 .. j0 + nrows + 1 of the intermediate state, keeping the last edge's
 // waves in registers; row k is updated once the edges k, k + 1 and their
 // neighbours are known.
-__global__ __launch_bounds__(256) void k_sweep_y(const PatchDev* __restrict__ patches,
-                                                 const YTile* __restrict__ tiles, int ntiles) {
-  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wv >= ntiles) return;
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void sweep_y_tile(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles,
+                                             int wv, int lane) {
   const YTile T = tiles[wv];
   const PatchDev& Pd = patches[T.patch];
   const PhysParams P = Pd.P;
@@ -326,6 +320,51 @@ __global__ __launch_bounds__(256) void k_sweep_y(const PatchDev* __restrict__ pa
     sig = wave_usum(sig);
     if (lane == 0) atomicAdd(&Pd.cnt->sig, sig);
   }
+}
+
+// ---------------------------------------------------------------- sweep launches
+// sched 0: one wave per tile; 1: persistent waves over the tile list with a
+// static stride; 2: persistent waves taking tiles from an atomic ticket (every
+// wave leaves once the ticket passes the list, so the grid always drains).
+template <int AXIS>
+__device__ __forceinline__ void run_tiles(const PatchDev* __restrict__ patches, const void* __restrict__ tiles,
+                                          int ntiles, int sched, unsigned* ticket) {
+  const int lane = threadIdx.x & 63;
+  const int w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  auto one = [&](int wv) {
+    if (AXIS == 0) sweep_x_tile(patches, (const XTile*)tiles, wv, lane);
+    else sweep_y_tile(patches, (const YTile*)tiles, wv, lane);
+  };
+  if (sched == 0) {
+    if (w0 < ntiles) one(w0);
+    return;
+  }
+  if (sched == 1) {
+    for (int wv = w0; wv < ntiles; wv += gridDim.x * 4) one(wv);
+    return;
+  }
+  for (;;) {
+    int wv = 0;
+    if (lane == 0) wv = (int)atomicAdd(ticket, 1u);
+    wv = __shfl(wv, 0, 64);
+    if (wv >= ntiles) break;
+    one(wv);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles,
+                                                 int ntiles, int sched, unsigned* ticket) {
+  run_tiles<0>(patches, tiles, ntiles, sched, ticket);
+}
+
+__global__ __launch_bounds__(256) void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles,
+                                                 int ntiles, int sched, unsigned* ticket) {
+  run_tiles<1>(patches, tiles, ntiles, sched, ticket);
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0u;
 }
 
 // ---------------------------------------------------------------- ghost cells

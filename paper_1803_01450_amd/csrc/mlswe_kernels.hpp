@@ -155,8 +155,11 @@ __global__ void k_param_map_adj(ParamMap M, const double* __restrict__ lam0, dou
 __global__ void k_gauge(Gauge G);
 __global__ void k_set_dt(LevelCtl* ctl, const double* __restrict__ dts, int k);
 
-__global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles);
-__global__ void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles);
+__global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles, int sched,
+                          unsigned* ticket);
+__global__ void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles, int sched,
+                          unsigned* ticket);
+__global__ void k_zero_u32(unsigned* p, int n);
 __global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass);
 __global__ void k_refine_new(const FillPatch* __restrict__ fills, const unsigned char* __restrict__ old_mask);
 __global__ void k_coarsen(const CoarsenPatch* __restrict__ cps);

@@ -119,6 +119,23 @@ struct mlswe_ctx {
   double* dt_stage = nullptr;
   int dt_stage_cap = 0;
   int sig_on = 0;
+  // launch shape of the sweeps (autotuned or set)
+  mlswe_tuning tune;
+  int ncu = 256;
+  unsigned* tickets = nullptr;  // [2] atomic work tickets of the persistent sweeps
+  // graph replay of whole coarse steps
+  hipStream_t cap_stream = nullptr;
+  long long generation = 0;      // bumped whenever launch data may have changed
+  struct GraphRec {
+    unsigned key;
+    long long gen;
+    int p0, p1;
+    hipGraphExec_t exec;
+    std::vector<long long> upd;  // per problem, per level update increments
+    std::vector<int> flips;      // per problem, per level parity flips (0/1)
+  };
+  std::vector<GraphRec> graphs;
+  long long graph_launches = 0, graph_captures = 0;
 };
 
 namespace {
@@ -235,8 +252,8 @@ std::vector<Box> cluster_tiles(const LevelH& C, int r, const std::vector<unsigne
 int build_launch(mlswe_ctx* c, int l) {
   LevelLaunch& LL = c->launch[l];
   if (!LL.dirty) return MLSWE_OK;
-  const int xrows = c->cfg.x_rows > 0 ? c->cfg.x_rows : 16;
-  const int yrows = c->cfg.y_rows > 0 ? c->cfg.y_rows : 128;
+  const int xrows = c->tune.x_rows > 0 ? c->tune.x_rows : 16;
+  const int yrows = c->tune.y_rows > 0 ? c->tune.y_rows : 128;
   std::vector<PatchDev> pd[2];
   std::vector<XTile> xt;
   std::vector<YTile> yt;
@@ -354,6 +371,7 @@ int build_launch(mlswe_ctx* c, int l) {
 }
 
 void mark_dirty(mlswe_ctx* c, int l) {
+  c->generation++;
   if (l >= 0 && l < MAXLEV) c->launch[l].dirty = true;
   if (l + 1 < MAXLEV) c->launch[l + 1].dirty = true;  // fill/coarsen descriptors of the finer level
   c->pdt_dirty = true;
@@ -416,9 +434,19 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   LevelLaunch& LL = c->launch[l];
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc;
+  const int sx = c->tune.sched_x, sy = c->tune.sched_y;
+  auto grid_of = [&](int ntiles, int sched, int mult) {
+    const int need = (ntiles + 3) / 4;
+    if (sched == 0) return need;
+    const int g = std::max(1, mult) * c->ncu;
+    return std::min(need, g);
+  };
+  if ((sx == 2 && nxt > 0) || (sy == 2 && nyt > 0))
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->tickets, 2);
   if (nxt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
-    hipLaunchKernelGGL(k_sweep_x, dim3((nxt + 3) / 4), dim3(256), 0, c->stream, LL.pd[parity], LL.xt + xt0, nxt);
+    hipLaunchKernelGGL(k_sweep_x, dim3(grid_of(nxt, sx, c->tune.grid_x)), dim3(256), 0, c->stream, LL.pd[parity],
+                       LL.xt + xt0, nxt, sx, c->tickets);
     HIPCHK(c, hipGetLastError());
     if (c->timing) {
       if ((rc = ev_begin(c, &e1))) return rc;
@@ -427,7 +455,8 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   }
   if (nyt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
-    hipLaunchKernelGGL(k_sweep_y, dim3((nyt + 3) / 4), dim3(256), 0, c->stream, LL.pd[parity], LL.yt + yt0, nyt);
+    hipLaunchKernelGGL(k_sweep_y, dim3(grid_of(nyt, sy, c->tune.grid_y)), dim3(256), 0, c->stream, LL.pd[parity],
+                       LL.yt + yt0, nyt, sy, c->tickets + 1);
     HIPCHK(c, hipGetLastError());
     if (c->timing) {
       if ((rc = ev_begin(c, &e1))) return rc;
@@ -766,6 +795,15 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
   c->cfg = d;
   c->stream = (hipStream_t)hip_stream;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return MLSWE_EDEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->ncu = prop.multiProcessorCount;
+  std::memset(&c->tune, 0, sizeof c->tune);
+  c->tune.x_rows = d.x_rows > 0 ? d.x_rows : 16;
+  c->tune.y_rows = d.y_rows > 0 ? d.y_rows : 128;
+  c->tune.grid_x = 1;
+  c->tune.grid_y = 1;
+  if (dalloc(c, (void**)&c->tickets, 2 * sizeof(unsigned)) != MLSWE_OK) { delete c; return MLSWE_ENOMEM; }
   int rc = dalloc(c, (void**)&c->theta, sizeof(double) * MAXLEV);
   if (rc) { delete c; return rc; }
   if (hipMemsetAsync(c->theta, 0, sizeof(double) * MAXLEV, c->stream) != hipSuccess) {
@@ -795,6 +833,9 @@ int mlswe_destroy(mlswe_ctx* c) {
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
   }
   dfree(c->ctl); dfree(c->cnt); dfree(c->theta); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
+  dfree(c->tickets);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (auto& u : c->ev_used) { (void)hipEventDestroy(u.second.first); (void)hipEventDestroy(u.second.second); }
   delete c;
@@ -876,6 +917,7 @@ int mlswe_problem_define(mlswe_ctx* c, int* p_out, double r, int nx0, int ny0, d
   if (rc) return rc;
   for (int l = 0; l < MAXLEV; ++l) c->launch[l].dirty = true;
   c->pdt_dirty = true;
+  c->generation++;
   *p_out = pidx;
   return MLSWE_OK;
 }
@@ -1035,36 +1077,148 @@ int mlswe_regrid(mlswe_ctx* c, int p, const double* tau, int nbuf) {
   return regrid_impl(c, p, tau, nbuf);
 }
 
+}  // extern "C"
+
+namespace {
+
+int build_all(mlswe_ctx* c) {
+  int nl = 0;
+  for (const ProblemH& P : c->probs) nl = std::max(nl, P.nlev);
+  int rc;
+  for (int l = 0; l < nl; ++l)
+    if ((rc = build_launch(c, l))) return rc;
+  return build_pdt(c);
+}
+
+// One coarse step of problems [p0, p1): dt rule, then the subcycled recursion.
+int coarse_step(mlswe_ctx* c, int p0, int p1, bool batched) {
+  int rc;
+  const bool initial = !c->probs[p0].have_dt;
+  if ((rc = next_dt(c, p0, p1, initial))) return rc;
+  for (int p = p0; p < p1; ++p) c->probs[p].have_dt = true;
+  return adv(c, 0, p0, p1, 0.0, batched);
+}
+
+// A coarse step of all problems replayed from a captured hipGraph.  The graph of
+// a step depends only on the launch data and on the buffer parity of every
+// level at its start; it is captured on first use (the capture also advances the
+// host-side bookkeeping, and the graph is then launched once) and replayed while
+// the launch data is unchanged.
+int graph_step(mlswe_ctx* c, int p0, int p1) {
+  int rc;
+  const ProblemH& P0 = c->probs[p0];
+  unsigned key = 0;
+  for (int l = 0; l < P0.nlev; ++l) key |= (unsigned)P0.L[l].cur << l;
+  for (auto it = c->graphs.begin(); it != c->graphs.end();) {
+    if (it->gen != c->generation) {
+      (void)hipGraphExecDestroy(it->exec);
+      it = c->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  for (auto& g : c->graphs) {
+    if (g.key != key || g.p0 != p0 || g.p1 != p1) continue;
+    HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
+    c->graph_launches++;
+    size_t k = 0;
+    for (int p = p0; p < p1; ++p) {
+      ProblemH& P = c->probs[p];
+      for (int l = 0; l < P.nlev; ++l, ++k) {
+        P.updates[l] += g.upd[k];
+        if (g.flips[k]) P.L[l].cur = 1 - P.L[l].cur;
+      }
+    }
+    return MLSWE_OK;
+  }
+  if ((rc = build_all(c))) return rc;
+  std::vector<long long> upd0;
+  std::vector<int> cur0;
+  for (int p = p0; p < p1; ++p)
+    for (int l = 0; l < c->probs[p].nlev; ++l) {
+      upd0.push_back(c->probs[p].updates[l]);
+      cur0.push_back(c->probs[p].L[l].cur);
+    }
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t saved = c->stream;
+  const bool saved_timing = c->timing;
+  c->stream = c->cap_stream;
+  c->timing = false;
+  hipGraph_t graph = nullptr;
+  hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (eb == hipSuccess) rc = coarse_step(c, p0, p1, true);
+  hipError_t ee = eb == hipSuccess ? hipStreamEndCapture(c->cap_stream, &graph) : eb;
+  c->stream = saved;
+  c->timing = saved_timing;
+  auto restore = [&]() {
+    size_t k = 0;
+    for (int p = p0; p < p1; ++p)
+      for (int l = 0; l < c->probs[p].nlev; ++l, ++k) {
+        c->probs[p].updates[l] = upd0[k];
+        c->probs[p].L[l].cur = cur0[k];
+      }
+  };
+  if (rc || eb != hipSuccess || ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    restore();
+    return rc ? rc : fail(c, MLSWE_EDEVICE, "graph capture: %s", hipGetErrorString(eb != hipSuccess ? eb : ee));
+  }
+  mlswe_ctx::GraphRec g;
+  g.key = key; g.gen = c->generation; g.p0 = p0; g.p1 = p1;
+  hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    restore();
+    return fail(c, MLSWE_EDEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+  }
+  size_t k = 0;
+  for (int p = p0; p < p1; ++p)
+    for (int l = 0; l < c->probs[p].nlev; ++l, ++k) {
+      g.upd.push_back(c->probs[p].updates[l] - upd0[k]);
+      g.flips.push_back(c->probs[p].L[l].cur != cur0[k] ? 1 : 0);
+    }
+  HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
+  c->graphs.push_back(g);
+  c->graph_captures++;
+  c->graph_launches++;
+  return MLSWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau, int nbuf, int mode, double* dts_out) {
   if (!c) return MLSWE_EINVAL;
   const int np = (int)c->probs.size();
   if (np == 0) return fail(c, MLSWE_ESTATE, "no problem defined");
   if (nsteps < 0 || regrid_every < 0 || (regrid_every > 0 && !tau) || nbuf < 0 ||
-      (mode != MLSWE_PLAIN && mode != MLSWE_BATCHED))
+      (mode != MLSWE_PLAIN && mode != MLSWE_BATCHED && mode != MLSWE_GRAPH))
     return fail(c, MLSWE_EINVAL, "bad advance arguments");
   for (int p = 0; p < np; ++p)
     if (!c->probs[p].bathy || !c->probs[p].state) return fail(c, MLSWE_ESTATE, "problem %d not initialised", p);
-  if (mode == MLSWE_BATCHED)
+  const bool together = mode != MLSWE_PLAIN;
+  if (together)
     for (int p = 1; p < np; ++p) {
       if (c->probs[p].nlev != c->probs[0].nlev) return fail(c, MLSWE_EINVAL, "batched problems need equal levels");
       for (int l = 0; l + 1 < c->probs[p].nlev; ++l)
         if (c->probs[p].ratio[l] != c->probs[0].ratio[l]) return fail(c, MLSWE_EINVAL, "batched ratios differ");
     }
-  // groups of problems advanced together: all (batched) or one at a time (plain)
-  const int ngroups = mode == MLSWE_BATCHED ? 1 : np;
+  // groups of problems advanced together: all (batched, graph) or one at a time (plain)
+  const int ngroups = together ? 1 : np;
   for (int gi = 0; gi < ngroups; ++gi) {
-    const int p0 = mode == MLSWE_BATCHED ? 0 : gi, p1 = mode == MLSWE_BATCHED ? np : gi + 1;
-    const bool batched = mode == MLSWE_BATCHED;
+    const int p0 = together ? 0 : gi, p1 = together ? np : gi + 1;
     for (int n = 0; n < nsteps; ++n) {
       int rc;
       if (regrid_every > 0 && n % regrid_every == 0)
         for (int p = p0; p < p1; ++p)
           if ((rc = regrid_impl(c, p, tau + (size_t)p * MAXLEV, nbuf))) return rc;
       if ((rc = build_pdt(c))) return rc;
-      bool initial = !c->probs[p0].have_dt;
-      if ((rc = next_dt(c, p0, p1, initial))) return rc;
-      for (int p = p0; p < p1; ++p) c->probs[p].have_dt = true;
-      if ((rc = adv(c, 0, p0, p1, 0.0, batched))) return rc;
+      if (mode == MLSWE_GRAPH && c->probs[p0].have_dt && !c->timing)
+        rc = graph_step(c, p0, p1);
+      else
+        rc = coarse_step(c, p0, p1, together);
+      if (rc) return rc;
       if (dts_out || c->timing) {
         if ((rc = collect_events(c))) return rc;
       }
@@ -1256,6 +1410,7 @@ extern "C" int mlswe_branch_signature(mlswe_ctx* c, int enable, int p, uint64_t*
   if (!c) return MLSWE_EINVAL;
   if (enable >= 0 && (enable ? 1 : 0) != c->sig_on) {
     c->sig_on = enable ? 1 : 0;
+    c->generation++;
     for (int l = 0; l < MAXLEV; ++l) c->launch[l].dirty = true;
   }
   if (sig_out) {
@@ -1316,6 +1471,147 @@ extern "C" int mlswe_gauge_misfit(mlswe_ctx* c, int p, const double* q, int i0, 
   G.pitch = L.pitch; G.nx = L.nx; G.ny = L.ny; G.i0 = i0; G.j0 = j0; G.gn = gn;
   hipLaunchKernelGGL(k_gauge, dim3(1), dim3(256), 0, c->stream, G);
   HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
+
+// ------------------------------------------------------------ tuning
+extern "C" int mlswe_get_tuning(mlswe_ctx* c, mlswe_tuning* out) {
+  if (!c || !out) return MLSWE_EINVAL;
+  *out = c->tune;
+  return MLSWE_OK;
+}
+
+extern "C" int mlswe_set_tuning(mlswe_ctx* c, const mlswe_tuning* t) {
+  if (!c || !t) return MLSWE_EINVAL;
+  if (t->x_rows < 1 || t->x_rows > 4096 || t->y_rows < 1 || t->y_rows > 4096 || t->sched_x < 0 || t->sched_x > 2 ||
+      t->sched_y < 0 || t->sched_y > 2 || t->grid_x < 0 || t->grid_x > 64 || t->grid_y < 0 || t->grid_y > 64)
+    return fail(c, MLSWE_EINVAL, "bad tuning");
+  c->tune = *t;
+  c->generation++;
+  for (int l = 0; l < MAXLEV; ++l) c->launch[l].dirty = true;
+  return MLSWE_OK;
+}
+
+static std::string layout_key(const mlswe_ctx* c) {
+  std::string k = "np=" + std::to_string(c->probs.size());
+  int nl = 0;
+  for (const ProblemH& P : c->probs) nl = std::max(nl, P.nlev);
+  for (int l = 0; l < nl; ++l) {
+    long long cells = 0, npatch = 0;
+    for (const ProblemH& P : c->probs)
+      if (l < P.nlev)
+        for (const Box& b : P.L[l].boxes) { cells += (long long)b.nx * b.ny; ++npatch; }
+    k += ";L" + std::to_string(l) + "=" + std::to_string(npatch) + "/" + std::to_string(cells);
+  }
+  return k;
+}
+
+// Milliseconds of reps launches of one sweep (axis 0: x, 1: y) over the patches
+// of every level of every problem.
+static int time_sweeps(mlswe_ctx* c, int axis, int reps, double* ms) {
+  int rc;
+  if ((rc = build_all(c))) return rc;
+  hipEvent_t a, b;
+  HIPCHK(c, hipEventCreate(&a));
+  HIPCHK(c, hipEventCreate(&b));
+  int nl = 0;
+  for (const ProblemH& P : c->probs) nl = std::max(nl, P.nlev);
+  auto launch_all = [&]() -> int {
+    for (int l = 0; l < nl; ++l) {
+      LevelLaunch& LL = c->launch[l];
+      if (LL.nptch == 0) continue;
+      const int par = c->probs[LL.patch_prob[0]].L[l].cur;
+      int r2 = axis == 0 ? launch_sweeps(c, l, par, 0, LL.nxt, 0, 0) : launch_sweeps(c, l, par, 0, 0, 0, LL.nyt);
+      if (r2) return r2;
+    }
+    return MLSWE_OK;
+  };
+  if ((rc = launch_all())) return rc;  // warm-up
+  HIPCHK(c, hipEventRecord(a, c->stream));
+  for (int k = 0; k < reps; ++k)
+    if ((rc = launch_all())) return rc;
+  HIPCHK(c, hipEventRecord(b, c->stream));
+  HIPCHK(c, hipEventSynchronize(b));
+  float f = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&f, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = f / reps;
+  return MLSWE_OK;
+}
+
+extern "C" int mlswe_autotune(mlswe_ctx* c, const char* cache_path, int reps) {
+  if (!c) return MLSWE_EINVAL;
+  if (c->probs.empty()) return fail(c, MLSWE_ESTATE, "no problem defined");
+  for (const ProblemH& P : c->probs)
+    if (!P.bathy || !P.state) return fail(c, MLSWE_ESTATE, "problems must be initialised before tuning");
+  if (reps <= 0) reps = 3;
+  const std::string key = layout_key(c);
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "r");
+    if (f) {
+      char line[1024];
+      while (std::fgets(line, sizeof line, f)) {
+        char k[900];
+        mlswe_tuning t;
+        if (std::sscanf(line, "%899s %d %d %d %d %d %d", k, &t.x_rows, &t.y_rows, &t.sched_x, &t.sched_y, &t.grid_x,
+                        &t.grid_y) == 7 &&
+            key == k) {
+          std::fclose(f);
+          return mlswe_set_tuning(c, &t);
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  const bool saved_timing = c->timing;
+  c->timing = false;
+  int nctl = 0;
+  for (const ProblemH& P : c->probs) nctl += P.nlev;
+  const int ncnt = (int)c->probs.size();
+  std::vector<LevelCtl> ctl_save(nctl);
+  std::vector<Counters> cnt_save(ncnt);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(ctl_save.data(), c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(cnt_save.data(), c->cnt, sizeof(Counters) * ncnt, hipMemcpyDeviceToHost));
+  const int scheds[5][2] = {{0, 0}, {1, 1}, {1, 2}, {2, 1}, {2, 2}};
+  mlswe_tuning best = c->tune;
+  int rc = MLSWE_OK;
+  for (int axis = 0; axis < 2 && !rc; ++axis) {
+    const int rows_x[3] = {8, 16, 32};
+    const int rows_y[4] = {32, 64, 128, 256};
+    const int nrows = axis == 0 ? 3 : 4;
+    double best_ms = 1e300;
+    for (int ri = 0; ri < nrows && !rc; ++ri)
+      for (int si = 0; si < 5 && !rc; ++si) {
+        mlswe_tuning t = best;
+        if (axis == 0) { t.x_rows = rows_x[ri]; t.sched_x = scheds[si][0]; t.grid_x = scheds[si][1]; }
+        else { t.y_rows = rows_y[ri]; t.sched_y = scheds[si][0]; t.grid_y = scheds[si][1]; }
+        if ((rc = mlswe_set_tuning(c, &t))) break;
+        double ms = 0;
+        if ((rc = time_sweeps(c, axis, reps, &ms))) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          if (axis == 0) { best.x_rows = t.x_rows; best.sched_x = t.sched_x; best.grid_x = t.grid_x; }
+          else { best.y_rows = t.y_rows; best.sched_y = t.sched_y; best.grid_y = t.grid_y; }
+        }
+      }
+  }
+  c->timing = saved_timing;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->ctl, ctl_save.data(), sizeof(LevelCtl) * nctl, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->cnt, cnt_save.data(), sizeof(Counters) * ncnt, hipMemcpyHostToDevice));
+  if (rc) return rc;
+  if ((rc = mlswe_set_tuning(c, &best))) return rc;
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), best.x_rows, best.y_rows, best.sched_x, best.sched_y,
+                   best.grid_x, best.grid_y);
+      std::fclose(f);
+    }
+  }
   return MLSWE_OK;
 }
 
