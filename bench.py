@@ -41,7 +41,121 @@ def parse():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--y-rows", type=int, default=0)
     ap.add_argument("--x-rows", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-vs-plain, AMR and adjoint measurements")
+    ap.add_argument("--batch-problems", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--amr-steps", type=int, default=16)
+    ap.add_argument("--adjoint-steps", type=int, default=400)
     return ap.parse_args()
+
+
+def timed_advance(S, steps, every, tau, mode):
+    """Seconds of S.advance(...) bracketed by device synchronisation, and the
+    interior cell updates (all levels, all problems) it performed."""
+    import torch
+    before = sum(sum(S.counters(p)["updates"]) for p in range(len(S.shapes)))
+    S.synchronize(); torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.advance(steps, every, tau, mode=mode)
+    S.synchronize(); torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    after = sum(sum(S.counters(p)["updates"]) for p in range(len(S.shapes)))
+    return t1 - t0, after - before
+
+
+def bench_batch(nprob, steps, stream):
+    """The batch of uneven problems (48..512 cells a side, two levels, ratio 2,
+    regrid every 10 steps): plain per-problem launches against one launch per
+    level substep over all problems (eager and graph-replayed)."""
+    import numpy as np
+    from paper_1803_01450_amd import inputs
+    from paper_1803_01450_amd.binding import Solver, PLAIN, BATCHED, GRAPH
+    sizes = inputs.batch_sizes(nprob)
+    probs = [inputs.batch_problem(k, int(n)) for k, n in enumerate(sizes)]
+    tau = np.tile([2e-5, 0.0], (nprob, 1))
+    out = {}
+    for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH)):
+        print("bench: batch %d problems, %s" % (nprob, name), file=sys.stderr, flush=True)
+        S = Solver(stream=stream)
+        for c in probs:
+            p = S.define(c["n"], c["n"], c["dx"], c["dx"], c["r"], (2,))
+            S.set_bathymetry(p, np.kron(c["B"], np.ones((2, 2))))
+            S.set_state(p, 0, c["q"])
+        if name != "plain":
+            S.autotune(None, reps=1)
+        S.advance(2, 10, tau, mode=mode)   # initial dt, first regrid, graph capture
+        sec, upd = timed_advance(S, steps, 10, tau, mode)
+        out[name] = {"seconds": sec, "cell_updates": upd, "rate": upd / sec}
+        if name == "batched":
+            out["tuning"] = S.tuning()
+        S.close()
+    out["batched_vs_plain"] = out["batched"]["rate"] / out["plain"]["rate"]
+    out["graph_vs_plain"] = out["graph"]["rate"] / out["plain"]["rate"]
+    out["problems"] = nprob
+    out["level0_cells"] = int(sum(int(n) ** 2 for n in sizes))
+    out["coarse_steps"] = steps
+    return out
+
+
+def bench_amr(steps, stream):
+    """Three levels (ratios 2 and 4) over 400 km with shorelines, 16 level-0
+    patches of 64^2, regrid every 4 coarse steps."""
+    import numpy as np
+    from paper_1803_01450_amd import inputs
+    from paper_1803_01450_amd.binding import Solver, PLAIN, BATCHED, GRAPH
+    c = inputs.amr_shoreline()
+    tau = [[2e-6, 4e-6]]
+    out = {}
+    for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH)):
+        print("bench: AMR 3 levels, %s" % name, file=sys.stderr, flush=True)
+        S = Solver(stream=stream)
+        p = S.define(c["n0"], c["n0"], c["dx0"], c["dx0"], c["r"], c["ratios"])
+        S.set_bathymetry(p, c["Bf"])
+        S.set_patches(p, 0, c["level0_boxes"])
+        S.set_state(p, 0, c["q0"])
+        S.advance(2, 4, tau, mode=mode)
+        sec, upd = timed_advance(S, steps, 4, tau, mode)
+        out[name] = {"seconds": sec, "cell_updates": upd, "rate": upd / sec,
+                     "finest_patches": int(len(S.patches(p, 2)))}
+        S.close()
+    out["batched_vs_plain"] = out["batched"]["rate"] / out["plain"]["rate"]
+    out["graph_vs_plain"] = out["graph"]["rate"] / out["plain"]["rate"]
+    out["coarse_steps"] = steps
+    return out
+
+
+def bench_adjoint(nsteps, stream):
+    """1024^2 gauge-misfit run (dt frozen, checkpoints every 20 steps): forward
+    time against backward time (recomputation plus adjoint steps)."""
+    import numpy as np
+    import torch
+    from paper_1803_01450_amd import inputs
+    from paper_1803_01450_amd.binding import Solver
+    from paper_1803_01450_amd.adjoint import MisfitProblem
+    print("bench: adjoint 1024^2, %d steps" % nsteps, file=sys.stderr, flush=True)
+    c = inputs.adjoint_problem(n=1024)
+    dt = 0.9 * c["dx"] / np.sqrt(9.81 * 4000.0)
+    dts = np.full(nsteps, dt)
+    S = Solver(stream=stream)
+    p = S.define(1024, 1024, c["dx"], c["dx"], c["r"])
+    S.set_bathymetry(p, c["B"])
+    tgt = torch.from_numpy(np.ascontiguousarray(c["targets"][: nsteps // c["every"]])).cuda()
+    prob = MisfitProblem(S, p, c["eta2"], dts, c["every"], c["gauge"], tgt, ckpt=c["ckpt"])
+    e = torch.from_numpy(c["eta1"]).cuda()
+    B = torch.from_numpy(c["B"]).cuda()
+    prob.forward(e, B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, ck = prob.forward(e, B)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prob.backward(e, ck)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    S.close()
+    return {"forward_s": t1 - t0, "backward_s": t2 - t1, "adjoint_fwd": (t2 - t1) / (t1 - t0),
+            "steps": nsteps, "cells": 1024 * 1024, "loss": float(loss.item())}
 
 
 def kernel_source_sha():
@@ -177,6 +291,13 @@ def main():
         out["cpu_baseline"] = {"value": crate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
                                "sample": "%d steps of the full %dx%d grid (%.1f s)" % (args.cpu_steps, n, n, sec)}
     S.close()
+    if not args.no_extras:
+        st = stream.cuda_stream
+        out["batch"] = bench_batch(args.batch_problems, args.batch_steps, st)
+        out["amr"] = bench_amr(args.amr_steps, st)
+        out["adjoint"] = bench_adjoint(args.adjoint_steps, st)
+        out["batched_vs_plain"] = out["batch"]["batched_vs_plain"]
+        out["adjoint_fwd"] = out["adjoint"]["adjoint_fwd"]
     print(json.dumps(out))
 
 

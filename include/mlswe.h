@@ -54,6 +54,11 @@ typedef struct mlswe_config {
   int y_rows;         /* rows per y-sweep wave on large patches (0 = 128) */
   int x_rows;         /* rows per x-sweep wave (0 = 16) */
   int64_t max_device_bytes; /* cap on the library's device memory (0 = none) */
+  int max_retries;    /* a coarse step whose largest substep Courant number exceeds
+                         cfl_max is undone and retaken with dt scaled by
+                         cfl_desired / that number, at most this often; -1 = never
+                         (the step then fails with MLSWE_ECFL), 0 = the default 8 */
+  int pad_;
 } mlswe_config;
 
 /* Launch shape of the two sweep kernels.  rows: rows of a patch per x-sweep
@@ -75,6 +80,7 @@ typedef struct mlswe_counters {
   double clip1, clip2;     /* mass removed from layers 1 and 2 by clipping */
   double t;                /* simulated time of the problem */
   int status;              /* sticky device status bits (1: Courant above cfl_max) */
+  int64_t rejected;        /* coarse steps undone and retaken (Courant above cfl_max) */
 } mlswe_counters;
 
 /* Library version (MLSWE_VERSION). */

@@ -265,7 +265,7 @@ class Hierarchy:
         return lib().ora_next_dt(self.h)
 
     def counters(self):
-        c = np.zeros(14)
+        c = np.zeros(15)
         lib().ora_counters(self.h, _dp(c))
         return dict(hyp=int(c[0]), nclip=int(c[1]), repair=int(c[2]), clip1=c[3], clip2=c[4], t=c[5],
-                    updates=[int(x) for x in c[6:6 + self.nlev]])
+                    updates=[int(x) for x in c[6:6 + self.nlev]], rejected=int(c[14]))

@@ -45,6 +45,9 @@ struct Hier {
   int64_t updates[8] = {0};
   double t = 0.0;
   bool have_smax = false;
+  double cmax = 0.0;     // largest substep Courant number of the current coarse step
+  int retries = 8;       // rejected coarse steps are retaken at most this often
+  int64_t rejected = 0;  // coarse steps rejected so far
 };
 
 // ---------------------------------------------------------------- refine (Sec. 2.1)
@@ -254,6 +257,7 @@ static int step_level(Hier& H, int l, double dt, double th, double smax[2]) {
   L.smax[0] = std::max(L.smax[0], smax[0]);
   L.smax[1] = std::max(L.smax[1], smax[1]);
   double courant = dt * std::max(smax[0] / L.dx, smax[1] / L.dy);
+  if (courant > H.cmax || courant != courant) H.cmax = courant;
   if (!(courant <= H.cflmax)) return E_CFL;
   return OK;
 }
@@ -445,22 +449,28 @@ static double next_dt(const Hier& H) {
 
 // Subcycled recursion: fill and step level l, then r substeps of level l+1 (time
 // ratio equal to the space ratio), then average level l+1 back onto level l.
+// Subcycled recursion: fill and step level l, then r substeps of level l+1 (time
+// ratio equal to the space ratio), then average level l+1 back onto level l.
+// A substep above the Courant limit does not stop the step: the whole coarse
+// step is completed and judged by its largest substep Courant number.
 static int adv(Hier& H, int l, double dt, double th) {
   double s[2];
   int rc = step_level(H, l, dt, th, s);
-  if (rc) return rc;
+  if (rc && rc != E_CFL) return rc;
   if (l + 1 < H.nlev && !H.L[l + 1].boxes.empty()) {
     const int r = H.ratio[l];
     const double dtf = dt / double(r);
     for (int k = 0; k < r; ++k) {
       rc = adv(H, l + 1, dtf, double(k) / double(r));
-      if (rc) return rc;
+      if (rc && rc != E_CFL) return rc;
     }
     coarsen(H, l + 1);
   }
   return OK;
 }
 
+// Coarse steps with rejection: a step whose largest substep Courant number
+// exceeds cflmax is undone and retaken with dt scaled by cfl / (that number).
 static int advance(Hier& H, int nsteps, int regrid_every, const double* tau, int nbuf, double* dts) {
   for (int n = 0; n < nsteps; ++n) {
     if (regrid_every > 0 && n % regrid_every == 0) {
@@ -468,9 +478,25 @@ static int advance(Hier& H, int nsteps, int regrid_every, const double* tau, int
       if (rc) return rc;
     }
     double dt = next_dt(H);
-    for (int l = 0; l < H.nlev; ++l) { H.L[l].smax[0] = 0.0; H.L[l].smax[1] = 0.0; }
-    int rc = adv(H, 0, dt, 0.0);
-    if (rc) return rc;
+    std::vector<std::vector<double>> save(H.nlev);
+    std::vector<int> save_cur(H.nlev);
+    Counters save_c = H.C;
+    int64_t save_u[8];
+    std::copy(H.updates, H.updates + 8, save_u);
+    for (int l = 0; l < H.nlev; ++l) { save[l] = H.L[l].q[H.L[l].cur]; save_cur[l] = H.L[l].cur; }
+    for (int attempt = 0;; ++attempt) {
+      for (int l = 0; l < H.nlev; ++l) { H.L[l].smax[0] = 0.0; H.L[l].smax[1] = 0.0; }
+      H.cmax = 0.0;
+      int rc = adv(H, 0, dt, 0.0);
+      if (rc) return rc;
+      if (H.cmax <= H.cflmax) break;
+      if (attempt + 1 > H.retries || !(H.cmax == H.cmax)) return E_CFL;
+      for (int l = 0; l < H.nlev; ++l) { H.L[l].cur = save_cur[l]; H.L[l].q[save_cur[l]] = save[l]; }
+      H.C = save_c;
+      std::copy(save_u, save_u + 8, H.updates);
+      H.rejected++;
+      dt = dt * (H.cfl / H.cmax);
+    }
     H.have_smax = true;
     H.t += dt;
     if (dts) dts[n] = dt;
@@ -625,12 +651,13 @@ int ora_advance(void* h, int nsteps, int regrid_every, const double* tau, int nb
 
 double ora_next_dt(void* h) { return next_dt(*static_cast<Hier*>(h)); }
 
-// [hyp, nclip, repair, clip1, clip2, t, updates level 0..7]
+// [hyp, nclip, repair, clip1, clip2, t, updates level 0..7, rejected steps]
 void ora_counters(void* h, double* out) {
   Hier* H = static_cast<Hier*>(h);
   out[0] = double(H->C.hyp); out[1] = double(H->C.nclip); out[2] = double(H->C.repair);
   out[3] = H->C.clip1; out[4] = H->C.clip2; out[5] = H->t;
   for (int l = 0; l < 8; ++l) out[6 + l] = double(H->updates[l]);
+  out[14] = double(H->rejected);
 }
 
 // Refine one fine cell from explicit coarse data: q5 = 5 cells x 7 values

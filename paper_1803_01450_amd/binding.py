@@ -26,13 +26,13 @@ class Config(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("hdry", ctypes.c_double), ("kmin", ctypes.c_double),
                 ("cfl_desired", ctypes.c_double), ("cfl_max", ctypes.c_double),
                 ("y_rows", ctypes.c_int), ("x_rows", ctypes.c_int),
-                ("max_device_bytes", ctypes.c_int64)]
+                ("max_device_bytes", ctypes.c_int64), ("max_retries", ctypes.c_int), ("pad_", ctypes.c_int)]
 
 
 class CountersC(ctypes.Structure):
     _fields_ = [("cell_updates", ctypes.c_int64 * 8), ("hyp", ctypes.c_int64), ("nclip", ctypes.c_int64),
                 ("repair", ctypes.c_int64), ("clip1", ctypes.c_double), ("clip2", ctypes.c_double),
-                ("t", ctypes.c_double), ("status", ctypes.c_int)]
+                ("t", ctypes.c_double), ("status", ctypes.c_int), ("rejected", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):
@@ -120,9 +120,9 @@ class Solver:
     """One library context (one GPU stream) holding any number of problems."""
 
     def __init__(self, g=9.81, hdry=1e-3, kmin=1e-6, cfl=0.9, cfl_max=1.0, y_rows=0, x_rows=0,
-                 max_device_bytes=0, stream=None):
+                 max_device_bytes=0, stream=None, max_retries=0):
         self.L = lib()
-        cfg = Config(g, hdry, kmin, cfl, cfl_max, y_rows, x_rows, max_device_bytes)
+        cfg = Config(g, hdry, kmin, cfl, cfl_max, y_rows, x_rows, max_device_bytes, max_retries, 0)
         h = ctypes.c_void_p()
         rc = self.L.mlswe_create(ctypes.byref(cfg), stream, ctypes.byref(h))
         if rc:
@@ -245,7 +245,8 @@ class Solver:
         self._check(self.L.mlswe_get_counters(self.h, p, ctypes.byref(c)))
         nl = len(self.shapes[p])
         return dict(updates=[int(c.cell_updates[l]) for l in range(nl)], hyp=int(c.hyp), nclip=int(c.nclip),
-                    repair=int(c.repair), clip1=c.clip1, clip2=c.clip2, t=c.t, status=int(c.status))
+                    repair=int(c.repair), clip1=c.clip1, clip2=c.clip2, t=c.t, status=int(c.status),
+                    rejected=int(c.rejected))
 
     def run_fixed(self, p, dts):
         d = _f64(dts)

@@ -551,6 +551,7 @@ __global__ void k_after_substep(LevelCtl* ctls, const LevelInfo* infos, int n, d
   const double sy = __longlong_as_double((long long)C.step_smax[1]);
   const double ax = sx / infos[k].dx, ay = sy / infos[k].dy;
   const double courant = C.dt * (ax > ay ? ax : ay);
+  if (courant > C.cmax || courant != courant) C.cmax = courant;
   if (!(courant <= cflmax)) C.status |= STATUS_CFL;
   C.last_smax[0] = C.step_smax[0];
   C.last_smax[1] = C.step_smax[1];
@@ -626,9 +627,28 @@ __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int npr
     C.dt = dt;
     C.acc_smax[0] = 0ull;
     C.acc_smax[1] = 0ull;
+    C.cmax = 0.0;
   }
   ctls[D.ctl0].t += best;
   if (D.dt_out) D.dt_out[0] = best;
+}
+
+// Retake of a rejected coarse step: the given coarse dt, the levels' substeps,
+// cleared speeds and Courant maximum.
+__global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const double* __restrict__ dt0, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  const ProbDt& D = pd[p];
+  double dt = dt0[p];
+  for (int l = 0; l < D.nlev; ++l) {
+    LevelCtl& C = ctls[D.ctl0 + l];
+    if (l > 0) dt = dt / (double)D.ratio[l - 1];
+    C.dt = dt;
+    C.acc_smax[0] = 0ull;
+    C.acc_smax[1] = 0ull;
+    C.cmax = 0.0;
+  }
+  ctls[D.ctl0].t += dt0[p];
 }
 
 __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob) {

@@ -23,6 +23,7 @@ struct LevelCtl {
   unsigned long long acc_smax[2];   // largest speeds over the current coarse step
   unsigned long long last_smax[2];  // largest speeds of the last finished substep
   double t;                         // simulated time (level 0 entry of a problem)
+  double cmax;                      // largest substep Courant number of the coarse step
   int status;
   int pad;
 };
@@ -171,5 +172,6 @@ __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int npr
 __global__ void k_set_theta(double* th, double v);
 __global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);
 __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob);
+__global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const double* __restrict__ dt0, int nprob);
 
 }  // namespace mlswe

@@ -38,6 +38,7 @@ struct LevelH {
   unsigned char* mask_old = nullptr;
   unsigned char* fraw = nullptr;
   unsigned char* fout = nullptr;
+  double* bk = nullptr;  // copy of the current buffer for a rejected coarse step
   std::vector<unsigned char> mask_h;
   std::vector<Box> boxes;
 };
@@ -66,6 +67,7 @@ struct ProblemH {
   int cnt = 0;   // index of the problem's counters
   double t = 0.0;
   long long updates[MAXLEV] = {0};
+  long long rejected = 0;
   bool bathy = false;
   bool state = false;
   bool have_dt = false;
@@ -136,6 +138,11 @@ struct mlswe_ctx {
   };
   std::vector<GraphRec> graphs;
   long long graph_launches = 0, graph_captures = 0;
+  LevelCtl* ctl_bk = nullptr;
+  Counters* cnt_bk = nullptr;
+  int bk_cap = 0, cbk_cap = 0;
+  double* dt0_d = nullptr;
+  int dt0_cap = 0;
 };
 
 namespace {
@@ -787,6 +794,7 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
   std::memset(&d, 0, sizeof d);
   d.g = 9.81; d.hdry = 1e-3; d.kmin = 1e-6; d.cfl_desired = 0.9; d.cfl_max = 1.0;
   if (cfg) d = *cfg;
+  if (d.max_retries == 0) d.max_retries = 8;
   if (!(d.g > 0) || !(d.hdry > 0) || !(d.kmin > 0) || !(d.cfl_desired > 0) || !(d.cfl_max >= d.cfl_desired) ||
       d.y_rows < 0 || d.x_rows < 0) {
     delete c;
@@ -826,14 +834,14 @@ int mlswe_destroy(mlswe_ctx* c) {
     for (int l = 0; l < P.nlev; ++l) {
       LevelH& L = P.L[l];
       dfree(L.q[0]); dfree(L.q[1]); dfree(L.qs); dfree(L.B); dfree(L.mask); dfree(L.mask_old);
-      dfree(L.fraw); dfree(L.fout);
+      dfree(L.fraw); dfree(L.fout); dfree(L.bk);
     }
   for (LevelLaunch& LL : c->launch) {
     dfree(LL.pd[0]); dfree(LL.pd[1]); dfree(LL.xt); dfree(LL.yt); dfree(LL.li);
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
   }
   dfree(c->ctl); dfree(c->cnt); dfree(c->theta); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
-  dfree(c->tickets);
+  dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1184,6 +1192,94 @@ int graph_step(mlswe_ctx* c, int p0, int p1) {
   return MLSWE_OK;
 }
 
+// A coarse step of problems [p0, p1) with rejection: when the largest substep
+// Courant number of a problem exceeds cfl_max, every problem of the group is
+// put back (fine-level buffers, controls, counters, host bookkeeping; level 0
+// keeps its input buffer through a step) and the step is retaken, the failing
+// problems with dt scaled by cfl_desired / that number, the others unchanged.
+int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
+  int rc;
+  const bool together = mode != MLSWE_PLAIN;
+  const bool retry = c->cfg.max_retries > 0;
+  int nctl = 0;
+  for (const ProblemH& P : c->probs) nctl += P.nlev;
+  const int ncnt = (int)c->probs.size();
+  std::vector<int> cur0;
+  std::vector<long long> upd0;
+  if (retry) {
+    if ((rc = ensure(c, &c->ctl_bk, &c->bk_cap, nctl))) return rc;
+    if ((rc = ensure(c, &c->cnt_bk, &c->cbk_cap, ncnt))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->ctl_bk, c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->cnt_bk, c->cnt, sizeof(Counters) * ncnt, hipMemcpyDeviceToDevice, c->stream));
+    for (int p = p0; p < p1; ++p) {
+      ProblemH& P = c->probs[p];
+      for (int l = 0; l < P.nlev; ++l) {
+        LevelH& L = P.L[l];
+        cur0.push_back(L.cur);
+        upd0.push_back(P.updates[l]);
+        if (l == 0 || L.boxes.empty()) continue;
+        const size_t sb = sizeof(double) * 6 * (size_t)L.plane;
+        if (!L.bk && (rc = dalloc(c, (void**)&L.bk, sb))) return rc;
+        HIPCHK(c, hipMemcpyAsync(L.bk, L.q[L.cur], sb, hipMemcpyDeviceToDevice, c->stream));
+      }
+    }
+  }
+  if (mode == MLSWE_GRAPH && c->probs[p0].have_dt && !c->timing)
+    rc = graph_step(c, p0, p1);
+  else
+    rc = coarse_step(c, p0, p1, together);
+  if (rc || !retry) return rc;
+  const int np = p1 - p0;
+  std::vector<double> dt0(np);
+  for (int attempt = 0;; ++attempt) {
+    std::vector<LevelCtl> h(nctl);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool any = false;
+    for (int p = p0; p < p1; ++p) {
+      const ProblemH& P = c->probs[p];
+      double cm = 0.0;
+      bool nan = false;
+      for (int l = 0; l < P.nlev; ++l) {
+        const double v = h[P.ctl0 + l].cmax;
+        if (v != v) nan = true;
+        else if (v > cm) cm = v;
+      }
+      const double dtp = h[P.ctl0].dt;
+      if (nan || cm > c->cfg.cfl_max) {
+        if (nan) return fail(c, MLSWE_ECFL, "non-finite Courant number in problem %d", p);
+        any = true;
+        dt0[p - p0] = dtp * (c->cfg.cfl_desired / cm);
+      } else {
+        dt0[p - p0] = dtp;
+      }
+    }
+    if (!any) return MLSWE_OK;
+    if (attempt + 1 > c->cfg.max_retries) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
+    // put the group back
+    HIPCHK(c, hipMemcpyAsync(c->ctl, c->ctl_bk, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->cnt, c->cnt_bk, sizeof(Counters) * ncnt, hipMemcpyDeviceToDevice, c->stream));
+    size_t k = 0;
+    for (int p = p0; p < p1; ++p) {
+      ProblemH& P = c->probs[p];
+      P.rejected++;
+      for (int l = 0; l < P.nlev; ++l, ++k) {
+        LevelH& L = P.L[l];
+        L.cur = cur0[k];
+        P.updates[l] = upd0[k];
+        if (l == 0 || L.boxes.empty()) continue;
+        HIPCHK(c, hipMemcpyAsync(L.q[L.cur], L.bk, sizeof(double) * 6 * (size_t)L.plane, hipMemcpyDeviceToDevice,
+                                 c->stream));
+      }
+    }
+    if ((rc = ensure(c, &c->dt0_d, &c->dt0_cap, np))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->dt0_d, dt0.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_set_dt0, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, c->dt0_d, np);
+    HIPCHK(c, hipGetLastError());
+    if ((rc = adv(c, 0, p0, p1, 0.0, together))) return rc;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1214,11 +1310,7 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
         for (int p = p0; p < p1; ++p)
           if ((rc = regrid_impl(c, p, tau + (size_t)p * MAXLEV, nbuf))) return rc;
       if ((rc = build_pdt(c))) return rc;
-      if (mode == MLSWE_GRAPH && c->probs[p0].have_dt && !c->timing)
-        rc = graph_step(c, p0, p1);
-      else
-        rc = coarse_step(c, p0, p1, together);
-      if (rc) return rc;
+      if ((rc = step_with_retry(c, p0, p1, mode))) return rc;
       if (dts_out || c->timing) {
         if ((rc = collect_events(c))) return rc;
       }
@@ -1250,6 +1342,7 @@ int mlswe_get_counters(mlswe_ctx* c, int p, mlswe_counters* out) {
   for (int l = 0; l < P.nlev; ++l) o.cell_updates[l] = P.updates[l];
   o.hyp = (int64_t)h.hyp; o.nclip = (int64_t)h.nclip; o.repair = (int64_t)h.repair;
   o.clip1 = h.clip1; o.clip2 = h.clip2;
+  o.rejected = P.rejected;
   LevelCtl lc;
   HIPCHK(c, hipMemcpy(&lc, c->ctl + P.ctl0, sizeof lc, hipMemcpyDeviceToHost));
   o.t = lc.t;

@@ -278,6 +278,38 @@ def test_batched_matches_oracle_per_problem():
     S.close()
 
 
+def test_rejected_step_matches_oracle():
+    """A batch problem whose wet/dry front pushes a substep past the Courant
+    limit: the library undoes and retakes the coarse step like the oracle (same
+    dt sequence, same number of rejections, same states)."""
+    say("case: coarse-step rejection, batch problem 301")
+    c = inputs.batch_problem(301, 152)
+    n = 152
+    Bf = np.kron(c["B"], np.ones((2, 2)))
+    for mode in (1, 2):
+        S = solver()
+        p = S.define(n, n, c["dx"], c["dx"], c["r"], (2,))
+        S.set_bathymetry(p, Bf)
+        S.set_state(p, 0, c["q"])
+        S.advance(2, 10, [[2e-5, 0.0]], mode=mode)
+        dts = S.advance(20, 10, [[2e-5, 0.0]], mode=mode, want_dts=True)
+        H = oracle.Hierarchy(n, n, c["dx"], c["dx"], ratios=(2,), r=c["r"])
+        H.set_bathymetry(Bf); H.set_state(0, c["q"])
+        H.advance(2, 10, [2e-5])
+        rc, rdts = H.advance(20, 10, [2e-5])
+        assert rc == 0
+        cg, co = S.counters(p), H.counters()
+        say("mode", mode, "rejected gpu", cg["rejected"], "oracle", co["rejected"],
+            "dt diff", np.abs(dts[0] - rdts).max())
+        assert cg["rejected"] == co["rejected"] >= 1
+        assert np.array_equal(dts[0], rdts)
+        for l in range(2):
+            err = rel_err(S.state(p, l), H.state(l))
+            assert err.max() <= 1e-9, (l, err)
+        assert cg["nclip"] == co["nclip"] and cg["repair"] == co["repair"]
+        S.close()
+
+
 # ---------------------------------------------------------------- full size
 def test_roofline_grid_sampled_windows():
     """The 4096^2 grid in the benchmark's launch configuration: one step, checked

@@ -257,3 +257,23 @@ def test_regrid_follows_the_pulse():
         # the pulse centre is refined
         assert m[64, 64]
     assert all(np.array_equal(a, b) for a, b in zip(runs[0], runs[1]))
+
+
+def test_rejected_step_is_retaken():
+    """A thin layer at a wet/dry front can raise the largest speed within one
+    step past the Courant limit; the coarse step is then undone and retaken with
+    dt scaled by cfl / (largest substep Courant number), and the run goes on."""
+    c = inputs.batch_problem(301, 152)
+    n = 152
+    H = oracle.Hierarchy(n, n, c["dx"], c["dx"], ratios=(2,), r=c["r"])
+    H.set_bathymetry(np.kron(c["B"], np.ones((2, 2))))
+    H.set_state(0, c["q"])
+    rc, d1 = H.advance(2, 10, [2e-5])
+    assert rc == 0
+    rc, d2 = H.advance(20, 10, [2e-5])
+    assert rc == 0
+    cn = H.counters()
+    assert cn["rejected"] >= 1
+    # every accepted substep respected the limit: re-running an accepted step
+    # with its dt is what the driver did; the dt sequence shrank at the rejection
+    assert np.all(d2 > 0) and d2.min() < d2.max()
