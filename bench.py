@@ -158,10 +158,15 @@ def bench_adjoint(nsteps, stream):
             "steps": nsteps, "cells": 1024 * 1024, "loss": float(loss.item())}
 
 
+# the sources the sweep kernels are compiled from
+SWEEP_SOURCES = ("mlswe_kernels.hip", "mlswe_sweeps_fast.hip", "mlswe_sweeps.inc", "mlswe_wave.hpp",
+                 "mlswe_device.hpp", "mlswe_kernels.hpp")
+
+
 def kernel_source_sha():
     import hashlib
     d = os.path.join(ROOT, "paper_1803_01450_amd", "csrc")
-    src = open(os.path.join(d, "mlswe_kernels.hip"), "rb").read() + open(os.path.join(d, "mlswe_device.hpp"), "rb").read()
+    src = b"".join(open(os.path.join(d, f), "rb").read() for f in SWEEP_SOURCES)
     return hashlib.sha256(src).hexdigest()
 
 
@@ -180,6 +185,16 @@ def profiled_traffic(kernel):
     if sha != kernel_source_sha() or val is None:
         return None
     return val
+
+
+def sweep_times(S, nk):
+    """Total milliseconds and launch counts of the x and y sweeps over nk steps,
+    from HIP events recorded on the library's stream."""
+    S.set_kernel_timing(True)
+    S.advance(nk)
+    ms, launches = S.kernel_times()
+    S.set_kernel_timing(False)
+    return ms, launches
 
 
 def copy_probe(mib):
@@ -247,13 +262,27 @@ def main():
     rate = cells * args.steps / wall
 
     # per-kernel durations from HIP events on the same stream (separate pass)
-    S.set_kernel_timing(True)
     nk = min(args.steps, 100)
-    S.advance(nk)
-    ms, launches = S.kernel_times()
-    S.set_kernel_timing(False)
+    ms, launches = sweep_times(S, nk)
     cnt = S.counters(p)
     status = cnt["status"]
+
+    # the fast build of the sweeps on the same grid (continuing from this state)
+    print("bench: fast build, %d steps" % args.steps, file=sys.stderr, flush=True)
+    S.set_tuning(fast=1)
+    S.advance(args.warmup)
+    S.synchronize()
+    torch.cuda.synchronize()
+    f0 = time.perf_counter()
+    S.advance(args.steps)
+    S.synchronize()
+    torch.cuda.synchronize()
+    fwall = time.perf_counter() - f0
+    fms, fl = sweep_times(S, nk)
+    S.set_tuning(fast=0)
+    fast = {"value": cells * args.steps / fwall, "ms_per_step": fwall / args.steps * 1e3,
+            "x_sweep_ms": fms[0] / max(1, fl[0]), "y_sweep_ms": fms[1] / max(1, fl[1]),
+            "status": S.counters(p)["status"]}
     # algorithmic bytes per launch: x-sweep reads 7 and writes 6 doubles for the
     # n x (n + 4) cells it updates (interior rows and the two frame rows on each
     # side); y-sweep reads 7 and writes 6 for the n x n interior cells
@@ -281,6 +310,7 @@ def main():
         "event_ms_per_step": ev_ms / args.steps,
         "roofline": roof,
         "status": status,
+        "fast": fast,
     }
     if not args.no_cpu:
         import oracle

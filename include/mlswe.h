@@ -65,11 +65,16 @@ typedef struct mlswe_config {
  * wave / per y-sweep wave (a y wave marches its rows with the last edge in
  * registers).  sched: 0 one wave per tile, 1 persistent waves striding over
  * the tile list, 2 persistent waves taking tiles from an atomic ticket.
- * grid: persistent blocks of four waves per compute unit. */
+ * grid: persistent blocks of four waves per compute unit.  fast: 1 selects the
+ * build of the sweeps with Newton-refined hardware reciprocals and reciprocal
+ * square roots and fused multiply-adds (FP64 throughout, a few ulps per
+ * operation from the default build, which reproduces the same arithmetic bit
+ * for bit in every launch shape). */
 typedef struct mlswe_tuning {
   int x_rows, y_rows;
   int sched_x, sched_y;
   int grid_x, grid_y;
+  int fast;
 } mlswe_tuning;
 
 typedef struct mlswe_counters {

@@ -37,7 +37,8 @@ class CountersC(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("x_rows", ctypes.c_int), ("y_rows", ctypes.c_int), ("sched_x", ctypes.c_int),
-                ("sched_y", ctypes.c_int), ("grid_x", ctypes.c_int), ("grid_y", ctypes.c_int)]
+                ("sched_y", ctypes.c_int), ("grid_x", ctypes.c_int), ("grid_y", ctypes.c_int),
+                ("fast", ctypes.c_int)]
 
 
 class MlsweError(RuntimeError):
@@ -256,12 +257,13 @@ class Solver:
         t = Tuning()
         self._check(self.L.mlswe_get_tuning(self.h, ctypes.byref(t)))
         return dict(x_rows=t.x_rows, y_rows=t.y_rows, sched_x=t.sched_x, sched_y=t.sched_y,
-                    grid_x=t.grid_x, grid_y=t.grid_y)
+                    grid_x=t.grid_x, grid_y=t.grid_y, fast=t.fast)
 
     def set_tuning(self, **kw):
         cur = self.tuning()
         cur.update(kw)
-        t = Tuning(cur["x_rows"], cur["y_rows"], cur["sched_x"], cur["sched_y"], cur["grid_x"], cur["grid_y"])
+        t = Tuning(cur["x_rows"], cur["y_rows"], cur["sched_x"], cur["sched_y"], cur["grid_x"], cur["grid_y"],
+                   cur["fast"])
         self._check(self.L.mlswe_set_tuning(self.h, ctypes.byref(t)))
 
     def autotune(self, cache_path=None, reps=3):

@@ -8,29 +8,40 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmlswe.so")
-SRCS = [os.path.join(HERE, "csrc", "mlswe_kernels.hip"), os.path.join(HERE, "csrc", "mlswe_adjoint.hip"),
-        os.path.join(HERE, "csrc", "mlswe_lib.cpp")]
+CSRC = os.path.join(HERE, "csrc")
+# (source, extra flags): the fast sweeps may contract a*b+c into fma
+SRCS = [(os.path.join(CSRC, "mlswe_kernels.hip"), []),
+        (os.path.join(CSRC, "mlswe_sweeps_fast.hip"), ["-ffp-contract=fast"]),
+        (os.path.join(CSRC, "mlswe_adjoint.hip"), []),
+        (os.path.join(CSRC, "mlswe_lib.cpp"), [])]
 HDRS = [os.path.join(HERE, "csrc", "mlswe_kernels.hpp"), os.path.join(HERE, "csrc", "mlswe_device.hpp"),
         os.path.join(ROOT, "include", "mlswe.h")]
 ARCH = os.environ.get("MLSWE_ARCH", "gfx950")
 
 FLAGS = [
-    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-    # FP64 results must not depend on contraction choices
-    "-ffp-contract=off",
+    "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
+# exact builds: FP64 results must not depend on contraction choices
+EXACT = ["-ffp-contract=off"]
 
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS
-    for src in SRCS:
-        cmd += ["-x", "hip", src]
-    cmd += ["-o", tmp]
+    objdir = os.path.join(ROOT, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for src, extra in SRCS:
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc] + FLAGS + (extra if extra else EXACT) + ["-c", "-x", "hip", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -14,11 +14,59 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Two builds of the device arithmetic share this source: the exact one (IEEE
+// division and square root, no contraction: reproducible bit for bit) and a
+// fast one (MLSWE_FAST: Newton-refined hardware reciprocal and reciprocal
+// square root, about one ulp, compiled with contraction), kept apart by an
+// inline namespace.
+#ifndef MLSWE_NS_VARIANT
+#define MLSWE_NS_VARIANT exact
+#endif
+
 namespace mlswe {
 
 struct PhysParams {
   double g, r, hdry, kmin, gp, inv_gp;
 };
+
+inline namespace MLSWE_NS_VARIANT {
+
+#ifdef MLSWE_FAST
+// The hardware seeds overflow for magnitudes below about 2^-1022: reciprocals
+// through mrcp are taken only of depths, sums of root depths, speed differences
+// and pivots, all of normal size; a quotient whose divisor can be a tiny dot
+// product (the limiter's ratio) goes through mdiv, which divides exactly there.
+// A square root may be taken of zero (the speed of a dry side in the one-layer
+// bound), where the reciprocal-root seed is infinite, so zero passes unchanged.
+__device__ __forceinline__ double mrcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ double msqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-s, h, 0.5);
+  s = __builtin_fma(s, r, s);
+  h = __builtin_fma(h, r, h);
+  const double d = __builtin_fma(-s, s, x);
+  const double v = __builtin_fma(d, h, s);
+  return x == 0.0 ? x : v;
+}
+__device__ __forceinline__ double mdiv(double a, double b) {
+  if (__builtin_expect(__builtin_fabs(b) < 0x1p-1000, 0)) return a / b;
+  return a * mrcp(b);
+}
+#define MRCP(x) mrcp(x)
+#define MDIV(a, b) mdiv(a, b)
+#define MSQRT(x) msqrt(x)
+#else
+#define MRCP(x) (1.0 / (x))
+#define MDIV(a, b) ((a) / (b))
+#define MSQRT(x) __builtin_sqrt(x)
+#endif
 
 // Per-sweep view of one cell.  m: normal momentum, t: transverse momentum.
 struct CellX {
@@ -35,14 +83,14 @@ __device__ __forceinline__ CellX load_cell(const PhysParams& P, double h1, doubl
   c.wet1 = h1 >= P.hdry;
   c.wet2 = h2 >= P.hdry;
   if (c.wet1) {
-    double inv = 1.0 / h1;
-    c.u1 = m1 * inv; c.w1 = t1 * inv; c.s1 = __builtin_sqrt(h1);
+    double inv = MRCP(h1);
+    c.u1 = m1 * inv; c.w1 = t1 * inv; c.s1 = MSQRT(h1);
   } else {
     c.u1 = 0.0; c.w1 = 0.0; c.s1 = 0.0;
   }
   if (c.wet2) {
-    double inv = 1.0 / h2;
-    c.u2 = m2 * inv; c.w2 = t2 * inv; c.s2 = __builtin_sqrt(h2);
+    double inv = MRCP(h2);
+    c.u2 = m2 * inv; c.w2 = t2 * inv; c.s2 = MSQRT(h2);
   } else {
     c.u2 = 0.0; c.w2 = 0.0; c.s2 = 0.0;
   }
@@ -122,19 +170,19 @@ __device__ __forceinline__ void layer_alone(const PhysParams& P, int layer, bool
   }
   const bool effL = hL > 0.0, effR = hR > 0.0;
   double hb = 0.5 * (hL + hR);
-  double d = 1.0 / (qL + qR);
+  double d = MRCP(qL + qR);
   double uh = (qL * uL + qR * uR) * d;
   double wh = (qL * wL + qR * wR) * d;
   double dA = mR - mL;
   double dB = (mR * uR - mL * uL) + (P.g * hb) * J;
   double dT = tR * uR - tL * uL;
-  double ch = __builtin_sqrt(P.g * hb);
+  double ch = MSQRT(P.g * hb);
   double sa, sb;
-  if (effL) sa = dmin(uL - __builtin_sqrt(P.g * hL), uh - ch);
-  else      sa = uR - 2.0 * __builtin_sqrt(P.g * hR);
-  if (effR) sb = dmax(uR + __builtin_sqrt(P.g * hR), uh + ch);
-  else      sb = uL + 2.0 * __builtin_sqrt(P.g * hL);
-  double isd = 1.0 / (sb - sa);
+  if (effL) sa = dmin(uL - MSQRT(P.g * hL), uh - ch);
+  else      sa = uR - 2.0 * MSQRT(P.g * hR);
+  if (effR) sb = dmax(uR + MSQRT(P.g * hR), uh + ch);
+  else      sb = uL + 2.0 * MSQRT(P.g * hL);
+  double isd = MRCP(sb - sa);
   double bA = (sb * dA - dB) * isd;
   double bB = (dB - sa * dA) * isd;
   if (layer == 1) {
@@ -166,10 +214,10 @@ __device__ __forceinline__ bool riemann(const PhysParams& P, const CellX& L, con
   if (L.wet1 && L.wet2 && R.wet1 && R.wet2) {
     double hb1 = 0.5 * (L.h1 + R.h1);
     double hb2 = 0.5 * (L.h2 + R.h2);
-    double d1 = 1.0 / (L.s1 + R.s1);
+    double d1 = MRCP(L.s1 + R.s1);
     double ub1 = (L.s1 * L.u1 + R.s1 * R.u1) * d1;
     double wb1 = (L.s1 * L.w1 + R.s1 * R.w1) * d1;
-    double d2 = 1.0 / (L.s2 + R.s2);
+    double d2 = MRCP(L.s2 + R.s2);
     double ub2 = (L.s2 * L.u2 + R.s2 * R.u2) * d2;
     double wb2 = (L.s2 * L.w2 + R.s2 * R.w2) * d2;
     double del1 = R.m1 - L.m1;
@@ -179,17 +227,17 @@ __device__ __forceinline__ bool riemann(const PhysParams& P, const CellX& L, con
     double dt1 = R.t1 * R.u1 - L.t1 * L.u1;
     double dt2 = R.t2 * R.u2 - L.t2 * L.u2;
     double H = hb1 + hb2;
-    double iH = 1.0 / H;
+    double iH = MRCP(H);
     double U = (hb1 * ub1 + hb2 * ub2) * iH;
     double Uc = (hb1 * ub2 + hb2 * ub1) * iH;
-    double ce = __builtin_sqrt(P.g * H);
+    double ce = MSQRT(P.g * H);
     double du = ub1 - ub2;
     double kap = 1.0 - ((du * du) * iH) * P.inv_gp;
     if (kap < P.kmin) { kap = P.kmin; clamped = true; }
-    double ci = __builtin_sqrt((((P.gp * hb1) * hb2) * iH) * kap);
+    double ci = MSQRT((((P.gp * hb1) * hb2) * iH) * kap);
     double s0 = U - ce, s1 = Uc - ci, s2 = Uc + ci, s3 = U + ce;
     double gh1 = P.g * hb1;
-    double igh = 1.0 / gh1;
+    double igh = MRCP(gh1);
     double a;
     a = s0 - ub1; double al0 = (a * a - gh1) * igh;
     a = s1 - ub1; double al1 = (a * a - gh1) * igh;
@@ -203,14 +251,14 @@ __device__ __forceinline__ bool riemann(const PhysParams& P, const CellX& L, con
     double b1 = del2 - s0 * del1;
     double b2 = del3 - al0 * del1;
     double b3 = del4 - q0 * del1;
-    double ip1 = 1.0 / m11;
+    double ip1 = MRCP(m11);
     double f2 = m21 * ip1, f3 = m31 * ip1;
     m22 = m22 - f2 * m12; m23 = m23 - f2 * m13; b2 = b2 - f2 * b1;
     m32 = m32 - f3 * m12; m33 = m33 - f3 * m13; b3 = b3 - f3 * b1;
-    double ip2 = 1.0 / m22;
+    double ip2 = MRCP(m22);
     double f4 = m32 * ip2;
     m33 = m33 - f4 * m23; b3 = b3 - f4 * b2;
-    double be3 = b3 / m33;
+    double be3 = MDIV(b3, m33);
     double be2 = (b2 - m23 * be3) * ip2;
     double be1 = ((b1 - m12 * be2) - m13 * be3) * ip1;
     double be0 = ((b0 - be1) - be2) - be3;
@@ -277,7 +325,7 @@ __device__ __forceinline__ double corr_coef(const EdgeW& W, int p, double dd, do
   const double sv = W.s[p];
   if (slot_mode(W, p) != 0 || sv == 0.0 || dd == 0.0) return 0.0;
   double dn = sv > 0.0 ? dot_left : dot_right;
-  double th = dn / dd;
+  double th = MDIV(dn, dd);
   double phi = mc_limiter(th);
   double sg = sv > 0.0 ? 0.5 : -0.5;
   double as = sv < 0.0 ? 0.0 - sv : sv;
@@ -370,4 +418,5 @@ __device__ __forceinline__ bool refine_from_stencil(const PhysParams& P, const d
   return rep;
 }
 
+}  // inline namespace
 }  // namespace mlswe

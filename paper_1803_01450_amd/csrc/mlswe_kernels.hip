@@ -3,364 +3,14 @@
 // with a two-cell frame; row j, column i sits at (j + 2) * pitch + (i + XOFF),
 // XOFF = 8 so that interior rows start on a 64-byte boundary.
 #include "mlswe_kernels.hpp"
+#include "mlswe_wave.hpp"
 
 namespace mlswe {
 
-__device__ __forceinline__ long long cidx(long long pitch, int i, int j) {
-  return (long long)(j + 2) * pitch + (long long)(i + XOFF);
-}
 
-// ---------------------------------------------------------------- wave helpers
-__device__ __forceinline__ double shup(double v) { return __shfl_up(v, 1, 64); }
-__device__ __forceinline__ double shdn(double v) { return __shfl_down(v, 1, 64); }
-__device__ __forceinline__ int shup_i(int v) { return __shfl_up(v, 1, 64); }
-
-__device__ __forceinline__ CellX shup_cell(const CellX& c) {
-  CellX o;
-  o.h1 = shup(c.h1); o.m1 = shup(c.m1); o.t1 = shup(c.t1);
-  o.h2 = shup(c.h2); o.m2 = shup(c.m2); o.t2 = shup(c.t2); o.B = shup(c.B);
-  o.u1 = shup(c.u1); o.w1 = shup(c.w1); o.u2 = shup(c.u2); o.w2 = shup(c.w2);
-  o.s1 = shup(c.s1); o.s2 = shup(c.s2); o.e1 = shup(c.e1); o.e2 = shup(c.e2);
-  int f = shup_i((c.wet1 ? 1 : 0) | (c.wet2 ? 2 : 0));
-  o.wet1 = (f & 1) != 0; o.wet2 = (f & 2) != 0;
-  return o;
-}
-
-__device__ __forceinline__ EdgeW shup_edge(const EdgeW& w) {
-  EdgeW o;
-#pragma unroll
-  for (int p = 0; p < 6; ++p) o.s[p] = shup(w.s[p]);
-#pragma unroll
-  for (int p = 0; p < 4; ++p) { o.A[p] = shup(w.A[p]); o.C[p] = shup(w.C[p]); }
-  o.v1 = shup(w.v1); o.v2 = shup(w.v2); o.z4 = shup(w.z4); o.z5 = shup(w.z5);
-  int m = shup_i(w.mode1 | (w.mode2 << 4));
-  o.mode1 = m & 15; o.mode2 = m >> 4;
-  return o;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) { double t = __shfl_xor(v, o, 64); v = t > v ? t : v; }
-  return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ int wave_isum(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ void flush_counts(Counters* cnt, LevelCtl* ctl, int axis, double smax, int hyp,
-                                             const FixCount& K, int lane) {
-  double sm = wave_max(smax);
-  int h = wave_isum(hyp);
-  int nc = wave_isum(K.nclip);
-  int rp = wave_isum(K.repair);
-  double c1 = wave_sum(K.clip1);
-  double c2 = wave_sum(K.clip2);
-  if (lane == 0) {
-    atomicMax(&ctl->step_smax[axis], (unsigned long long)__double_as_longlong(sm));
-    if (h) atomicAdd(&cnt->hyp, (unsigned long long)h);
-    if (nc) atomicAdd(&cnt->nclip, (unsigned long long)nc);
-    if (rp) atomicAdd(&cnt->repair, (unsigned long long)rp);
-    if (c1 != 0.0) atomicAdd(&cnt->clip1, c1);
-    if (c2 != 0.0) atomicAdd(&cnt->clip2, c2);
-  }
-}
-
-// Branch code of wave p's limiter and speed sign at an edge, weighted by a hash
-// of the edge position; sums of these over a run change (almost surely) when any
-// limiter branch or wave direction changes.
-__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
-  x += 0x9e3779b97f4a7c15ull;
-  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
-  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
-  return x ^ (x >> 31);
-}
-
-__device__ __forceinline__ unsigned long long branch_sig(const EdgeW& W, const double dd[6], const double dl[6],
-                                                         const double dr[6], int i, int j, int axis) {
-  unsigned long long acc = 0;
-#pragma unroll
-  for (int p = 0; p < 6; ++p) {
-    const double sv = W.s[p];
-    unsigned code = sv > 0.0 ? 1u : (sv < 0.0 ? 2u : 3u);
-    if (slot_mode(W, p) == 0 && sv != 0.0 && dd[p] != 0.0) {
-      const double th = (sv > 0.0 ? dl[p] : dr[p]) / dd[p];
-      const double a = 0.5 * (1.0 + th), b = 2.0 * th;
-      const double m1 = a < 2.0 ? a : 2.0;
-      const double m = m1 < b ? m1 : b;
-      unsigned br = (0.0 > m) ? 1u : (m1 < b ? (a < 2.0 ? 2u : 3u) : 4u);
-      code |= br << 2;
-    }
-    const unsigned long long key =
-        ((unsigned long long)(unsigned)i << 32) ^ ((unsigned long long)(unsigned)j << 4) ^ (unsigned)(axis * 8 + p);
-    acc += (unsigned long long)code * mix64(key);
-  }
-  return acc;
-}
-
-__device__ __forceinline__ unsigned long long wave_usum(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ double edge_smax(const EdgeW& W) {
-  double m = 0.0;
-#pragma unroll
-  for (int p = 0; p < 6; ++p) {
-    double a = W.s[p] < 0.0 ? 0.0 - W.s[p] : W.s[p];
-    if (a > m) m = a;
-  }
-  return m;
-}
-
-// ---------------------------------------------------------------- x-sweep
-// One wave per tile: lane l holds column i0 - 2 + l of each row; the edge at
-// lane l lies between columns i0 - 3 + l and i0 - 2 + l.  Lanes 2..ncols+1 own
-// the tile's interior cells.  Writes the x-swept, fixed-up state of the tile's
-// rows (interior and frame rows of the patch) into the intermediate buffer.
-__device__ __forceinline__ void sweep_x_tile(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles,
-                                             int wv, int lane) {
-  const XTile T = tiles[wv];
-  const PatchDev& Pd = patches[T.patch];
-  const PhysParams P = Pd.P;
-  const long long pitch = Pd.pitch, plane = Pd.plane;
-  const double* __restrict__ q = Pd.q;
-  const double* __restrict__ Bp = Pd.B;
-  double* __restrict__ qs = Pd.qs;
-  const int c = T.i0 - 2 + lane;
-  const bool act = lane < T.ncols + 4;
-  const bool upd = lane >= 2 && lane < T.ncols + 2;
-  const bool own = upd || (lane == T.ncols + 2 && T.i0 + T.ncols == Pd.ilo + Pd.nx);
-  const double nu = Pd.ctl->dt / Pd.dx;
-  double smax = 0.0;
-  int hyp = 0;
-  unsigned long long sig = 0;
-  FixCount K = {0, 0, 0.0, 0.0};
-
-  double nq[7];
-  if (act) {
-    const long long id = cidx(pitch, c, T.j0);
-#pragma unroll
-    for (int f = 0; f < 6; ++f) nq[f] = q[f * plane + id];
-    nq[6] = Bp[id];
-  } else {
-#pragma unroll
-    for (int f = 0; f < 7; ++f) nq[f] = 0.0;
-  }
-  for (int r = 0; r < T.nrows; ++r) {
-    const int j = T.j0 + r;
-    double cq[7];
-#pragma unroll
-    for (int f = 0; f < 7; ++f) cq[f] = nq[f];
-    if (act && r + 1 < T.nrows) {  // prefetch the next row
-      const long long id = cidx(pitch, c, j + 1);
-#pragma unroll
-      for (int f = 0; f < 6; ++f) nq[f] = q[f * plane + id];
-      nq[6] = Bp[id];
-    }
-    const bool irow = j >= Pd.jlo && j < Pd.jlo + Pd.ny;
-    CellX C = load_cell(P, cq[0], cq[1], cq[2], cq[3], cq[4], cq[5], cq[6]);
-    CellX CL = shup_cell(C);
-    EdgeW W;
-    bool cl = riemann(P, CL, C, W);
-    if (irow && own) {
-      double e = edge_smax(W);
-      smax = e > smax ? e : smax;
-      hyp += cl ? 1 : 0;
-    }
-    double dd[6], dl[6], dr[6];
-    EdgeW WL = shup_edge(W);
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      dd[p] = wdot(W, W, p);
-      dl[p] = wdot(WL, W, p);
-    }
-#pragma unroll
-    for (int p = 0; p < 6; ++p) dr[p] = shdn(dl[p]);
-    double coef[6], F[6], am[6], ap[6];
-#pragma unroll
-    for (int p = 0; p < 6; ++p) coef[p] = corr_coef(W, p, dd[p], dl[p], dr[p], nu);
-    if (Pd.sig_on && own) sig += branch_sig(W, dd, dl, dr, c, j, 0);
-    correction_flux(W, coef, F);
-    fluctuations(W, am, ap);
-    double gl[6], gr[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      gl[k] = ap[k] - F[k];
-      gr[k] = shdn(am[k] + F[k]);
-    }
-    if (upd) {
-      double o[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) o[k] = cq[k] - nu * (gl[k] + gr[k]);
-      fixup(P, o, irow, K);
-      const long long id = cidx(pitch, c, j);
-#pragma unroll
-      for (int f = 0; f < 6; ++f) qs[f * plane + id] = o[f];
-    }
-  }
-  flush_counts(Pd.cnt, Pd.ctl, 0, smax, hyp, K, lane);
-  if (Pd.sig_on) {
-    sig = wave_usum(sig);
-    if (lane == 0) atomicAdd(&Pd.cnt->sig, sig);
-  }
-}
-
-// ---------------------------------------------------------------- y-sweep
-// One wave per tile: lane l owns column i0 + l and marches up the rows
-// j0 - 2 .. j0 + nrows + 1 of the intermediate state, keeping the last edge's
-// waves in registers; row k is updated once the edges k, k + 1 and their
-// neighbours are known.
-__device__ __forceinline__ void sweep_y_tile(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles,
-                                             int wv, int lane) {
-  const YTile T = tiles[wv];
-  const PatchDev& Pd = patches[T.patch];
-  const PhysParams P = Pd.P;
-  const long long pitch = Pd.pitch, plane = Pd.plane;
-  const double* __restrict__ qs = Pd.qs;
-  const double* __restrict__ Bp = Pd.B;
-  double* __restrict__ qo = Pd.qo;
-  const int i = T.i0 + lane;
-  const bool act = lane < T.ncols;
-  const double nu = Pd.ctl->dt / Pd.dy;
-  double smax = 0.0;
-  int hyp = 0;
-  unsigned long long sig = 0;
-  FixCount K = {0, 0, 0.0, 0.0};
-
-  CellX Cp;
-  EdgeW Wp;
-  double qm2[6], qm1[6], ddp[6], dlp[6], glo[6];
-  double nq[7];
-  auto load_row = [&](int jj, double* v) {
-    if (act) {
-      const long long id = cidx(pitch, i, jj);
-#pragma unroll
-      for (int f = 0; f < 6; ++f) v[f] = qs[f * plane + id];
-      v[6] = Bp[id];
-    } else {
-#pragma unroll
-      for (int f = 0; f < 7; ++f) v[f] = 0.0;
-    }
-  };
-  load_row(T.j0 - 2, nq);
-  const int nk = T.nrows + 4;
-  for (int k = 0; k < nk; ++k) {
-    const int jj = T.j0 - 2 + k;
-    double cq[7];
-#pragma unroll
-    for (int f = 0; f < 7; ++f) cq[f] = nq[f];
-    if (k + 1 < nk) load_row(jj + 1, nq);
-    // y orientation: normal momentum hv, transverse hu
-    CellX Cc = load_cell(P, cq[0], cq[2], cq[1], cq[3], cq[5], cq[4], cq[6]);
-    if (k >= 1) {
-      EdgeW Wc;
-      bool cl = riemann(P, Cp, Cc, Wc);
-      const bool own = (jj >= T.j0 && jj < T.j0 + T.nrows) || (T.last && jj == T.j0 + T.nrows);
-      if (own) {
-        double e = edge_smax(Wc);
-        smax = e > smax ? e : smax;
-        hyp += cl ? 1 : 0;
-      }
-      double ddc[6];
-#pragma unroll
-      for (int p = 0; p < 6; ++p) ddc[p] = wdot(Wc, Wc, p);
-      if (k >= 2) {
-        double dlc[6];
-#pragma unroll
-        for (int p = 0; p < 6; ++p) dlc[p] = wdot(Wp, Wc, p);
-        if (k >= 3) {
-          // edge jj-1 is complete: its correction flux and fluctuations
-          double coef[6], F[6], am[6], ap[6];
-#pragma unroll
-          for (int p = 0; p < 6; ++p) coef[p] = corr_coef(Wp, p, ddp[p], dlp[p], dlc[p], nu);
-          if (Pd.sig_on && act) sig += branch_sig(Wp, ddp, dlp, dlc, i, jj - 1, 1);
-          correction_flux(Wp, coef, F);
-          fluctuations(Wp, am, ap);
-          if (k >= 4 && act) {
-            // row jj-2: lower edge jj-2 (glo), upper edge jj-1
-            double o[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) o[c] = qm2[c] - nu * (glo[c] + (am[c] + F[c]));
-            fixup(P, o, true, K);
-            const long long id = cidx(pitch, i, jj - 2);
-            qo[0 * plane + id] = o[0];
-            qo[1 * plane + id] = o[2];
-            qo[2 * plane + id] = o[1];
-            qo[3 * plane + id] = o[3];
-            qo[4 * plane + id] = o[5];
-            qo[5 * plane + id] = o[4];
-          }
-#pragma unroll
-          for (int c = 0; c < 6; ++c) glo[c] = ap[c] - F[c];
-        }
-#pragma unroll
-        for (int p = 0; p < 6; ++p) dlp[p] = dlc[p];
-      }
-      Wp = Wc;
-#pragma unroll
-      for (int p = 0; p < 6; ++p) ddp[p] = ddc[p];
-    }
-    // local y order of the row just read: h1, hv1, hu1, h2, hv2, hu2
-#pragma unroll
-    for (int c = 0; c < 6; ++c) qm2[c] = qm1[c];
-    qm1[0] = cq[0]; qm1[1] = cq[2]; qm1[2] = cq[1];
-    qm1[3] = cq[3]; qm1[4] = cq[5]; qm1[5] = cq[4];
-    Cp = Cc;
-  }
-  flush_counts(Pd.cnt, Pd.ctl, 1, smax, hyp, K, lane);
-  if (Pd.sig_on) {
-    sig = wave_usum(sig);
-    if (lane == 0) atomicAdd(&Pd.cnt->sig, sig);
-  }
-}
-
-// ---------------------------------------------------------------- sweep launches
-// sched 0: one wave per tile; 1: persistent waves over the tile list with a
-// static stride; 2: persistent waves taking tiles from an atomic ticket (every
-// wave leaves once the ticket passes the list, so the grid always drains).
-template <int AXIS>
-__device__ __forceinline__ void run_tiles(const PatchDev* __restrict__ patches, const void* __restrict__ tiles,
-                                          int ntiles, int sched, unsigned* ticket) {
-  const int lane = threadIdx.x & 63;
-  const int w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
-  auto one = [&](int wv) {
-    if (AXIS == 0) sweep_x_tile(patches, (const XTile*)tiles, wv, lane);
-    else sweep_y_tile(patches, (const YTile*)tiles, wv, lane);
-  };
-  if (sched == 0) {
-    if (w0 < ntiles) one(w0);
-    return;
-  }
-  if (sched == 1) {
-    for (int wv = w0; wv < ntiles; wv += gridDim.x * 4) one(wv);
-    return;
-  }
-  for (;;) {
-    int wv = 0;
-    if (lane == 0) wv = (int)atomicAdd(ticket, 1u);
-    wv = __shfl(wv, 0, 64);
-    if (wv >= ntiles) break;
-    one(wv);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles,
-                                                 int ntiles, int sched, unsigned* ticket) {
-  run_tiles<0>(patches, tiles, ntiles, sched, ticket);
-}
-
-__global__ __launch_bounds__(256) void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles,
-                                                 int ntiles, int sched, unsigned* ticket) {
-  run_tiles<1>(patches, tiles, ntiles, sched, ticket);
-}
+#define MLSWE_KX k_sweep_x
+#define MLSWE_KY k_sweep_y
+#include "mlswe_sweeps.inc"
 
 __global__ void k_zero_u32(unsigned* p, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;

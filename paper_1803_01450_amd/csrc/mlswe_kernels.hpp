@@ -160,6 +160,10 @@ __global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __r
                           unsigned* ticket);
 __global__ void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles, int sched,
                           unsigned* ticket);
+__global__ void k_sweep_x_fast(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles,
+                               int sched, unsigned* ticket);
+__global__ void k_sweep_y_fast(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
+                               int sched, unsigned* ticket);
 __global__ void k_zero_u32(unsigned* p, int n);
 __global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass);
 __global__ void k_refine_new(const FillPatch* __restrict__ fills, const unsigned char* __restrict__ old_mask);

@@ -452,8 +452,8 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->tickets, 2);
   if (nxt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
-    hipLaunchKernelGGL(k_sweep_x, dim3(grid_of(nxt, sx, c->tune.grid_x)), dim3(256), 0, c->stream, LL.pd[parity],
-                       LL.xt + xt0, nxt, sx, c->tickets);
+    hipLaunchKernelGGL(c->tune.fast ? k_sweep_x_fast : k_sweep_x, dim3(grid_of(nxt, sx, c->tune.grid_x)), dim3(256),
+                       0, c->stream, LL.pd[parity], LL.xt + xt0, nxt, sx, c->tickets);
     HIPCHK(c, hipGetLastError());
     if (c->timing) {
       if ((rc = ev_begin(c, &e1))) return rc;
@@ -462,8 +462,8 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   }
   if (nyt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
-    hipLaunchKernelGGL(k_sweep_y, dim3(grid_of(nyt, sy, c->tune.grid_y)), dim3(256), 0, c->stream, LL.pd[parity],
-                       LL.yt + yt0, nyt, sy, c->tickets + 1);
+    hipLaunchKernelGGL(c->tune.fast ? k_sweep_y_fast : k_sweep_y, dim3(grid_of(nyt, sy, c->tune.grid_y)), dim3(256),
+                       0, c->stream, LL.pd[parity], LL.yt + yt0, nyt, sy, c->tickets + 1);
     HIPCHK(c, hipGetLastError());
     if (c->timing) {
       if ((rc = ev_begin(c, &e1))) return rc;
@@ -1578,7 +1578,8 @@ extern "C" int mlswe_get_tuning(mlswe_ctx* c, mlswe_tuning* out) {
 extern "C" int mlswe_set_tuning(mlswe_ctx* c, const mlswe_tuning* t) {
   if (!c || !t) return MLSWE_EINVAL;
   if (t->x_rows < 1 || t->x_rows > 4096 || t->y_rows < 1 || t->y_rows > 4096 || t->sched_x < 0 || t->sched_x > 2 ||
-      t->sched_y < 0 || t->sched_y > 2 || t->grid_x < 0 || t->grid_x > 64 || t->grid_y < 0 || t->grid_y > 64)
+      t->sched_y < 0 || t->sched_y > 2 || t->grid_x < 0 || t->grid_x > 64 || t->grid_y < 0 || t->grid_y > 64 ||
+      t->fast < 0 || t->fast > 1)
     return fail(c, MLSWE_EINVAL, "bad tuning");
   c->tune = *t;
   c->generation++;
@@ -1652,6 +1653,7 @@ extern "C" int mlswe_autotune(mlswe_ctx* c, const char* cache_path, int reps) {
                         &t.grid_y) == 7 &&
             key == k) {
           std::fclose(f);
+          t.fast = c->tune.fast;
           return mlswe_set_tuning(c, &t);
         }
       }
