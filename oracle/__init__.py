@@ -22,7 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
-_SRCS = ["ora_amr.cpp", "ora_adjoint.cpp"]
+_SRCS = ["ora_amr.cpp", "ora_adjoint.cpp", "ora_count.cpp"]
 
 G = 9.81
 HDRY = 1.0e-3
@@ -84,6 +84,8 @@ def lib():
         L.ora_fixed_steps.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _I, _DP, _DP, _DP]
         L.ora_time_fixed.restype = _D
         L.ora_time_fixed.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _I, _D, _DP]
+        L.ora_count_ops.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _D,
+                                    ctypes.POINTER(ctypes.c_longlong)]
         L.ora_step_window.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _IP, _D, _DP, _DP]
         L.ora_gauge_loss.restype = _D
         L.ora_gauge_loss.argtypes = [_I, _D, _D, _D, _D, _D, _DP, _DP, _D, _I, _DP, _I, _I, _I, _I,
@@ -154,6 +156,24 @@ def time_fixed(B, q, dx, dy, nsteps, dt, r=0.95, g=G, hdry=HDRY, kmin=KMIN):
     sec = ctypes.c_double(0.0)
     rate = lib().ora_time_fixed(nx, ny, dx, dy, g, r, hdry, kmin, _dp(B), _dp(q), nsteps, dt, ctypes.byref(sec))
     return rate, sec.value
+
+
+def count_ops(B, q, dx, dy, dt, r=0.95, g=G, hdry=HDRY, kmin=KMIN):
+    """FP64 operations of one oracle step of this grid, per sweep:
+    {"x": {...}, "y": {...}} with counts of add (incl. subtract), mul, div, sqrt
+    and neg, plus the cells each pass updates."""
+    B = _f64(B); q = _f64(q)
+    ny, nx = B.shape
+    out = (ctypes.c_longlong * 10)()
+    rc = lib().ora_count_ops(nx, ny, dx, dy, g, r, hdry, kmin, _dp(B), _dp(q), dt, out)
+    if rc != 0:
+        raise ValueError("grid below 2 x 2")
+    names = ("add", "mul", "div", "sqrt", "neg")
+    x = {k: int(out[i]) for i, k in enumerate(names)}
+    y = {k: int(out[5 + i]) for i, k in enumerate(names)}
+    x["cells"] = nx * (ny + 4)
+    y["cells"] = nx * ny
+    return {"x": x, "y": y}
 
 
 def gauge_loss(eta1_0, B, dx, eta2_0, dts, every, gauge, targets, v_eta=None, v_B=None, r=0.95,

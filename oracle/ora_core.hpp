@@ -424,37 +424,44 @@ inline void mirror_src(const Grid& G, int i, int j, int& si, int& sj, bool& fx, 
   else if (j >= G.ny) { sj = 2 * G.ny - 1 - j; fy = true; }
 }
 
-// One split step of the box `bx` of a level: reads q (interior and two-cell frame
-// valid around the box), writes the box interior of qo.  x-sweep over the box rows
-// and the two frame rows on each side, fix-up, y-sweep, fix-up.
+// x-sweep of a box: the box rows and the two frame rows on each side, each
+// line fixed up; writes the intermediate state qs (six planes of
+// nx x (ny + 4), rows jlo-2 .. jlo+ny+1, columns ilo .. ilo+nx-1).
 template <class T>
-void step_box(const Params& P, const Grid& G, const T* q, const T* B, const Box& bx, double dx,
-              double dy, double dt, T* qo, double smax[2], Counters& C) {
+double x_pass(const Params& P, const Grid& G, const T* q, const T* B, const Box& bx, T nux, T* qs,
+              Counters& C) {
   const size_t pl = G.plane();
   const int nx = bx.nx, ny = bx.ny;
-  const T nux = T(dt / dx);
-  const T nuy = T(dt / dy);
-  // intermediate state for rows jlo-2 .. jlo+ny+1, columns ilo .. ilo+nx-1
-  std::vector<T> qs(size_t(6) * size_t(nx) * size_t(ny + 4));
   std::vector<T> line(6 * (nx + 4)), Bl(nx + 4), out(6 * nx);
-  static const int xmap[6] = {0, 1, 2, 3, 4, 5};
-  static const int ymap[6] = {0, 2, 1, 3, 5, 4};
-  smax[0] = 0.0; smax[1] = 0.0;
+  double smax = 0.0;
   for (int jj = -2; jj < ny + 2; ++jj) {
     int j = bx.jlo + jj;
     for (int k = -2; k < nx + 2; ++k) {
       int i = bx.ilo + k;
-      for (int c = 0; c < 6; ++c) line[6 * (k + 2) + c] = q[xmap[c] * pl + G.idx(i, j)];
+      for (int c = 0; c < 6; ++c) line[6 * (k + 2) + c] = q[c * pl + G.idx(i, j)];
       Bl[k + 2] = B[G.idx(i, j)];
     }
     bool interior = (jj >= 0 && jj < ny);
     double s = sweep_line(P, nx, line.data(), Bl.data(), nux, out.data(), interior, C);
-    if (interior && s > smax[0]) smax[0] = s;
+    if (interior && s > smax) smax = s;
     for (int k = 0; k < nx; ++k)
       for (int c = 0; c < 6; ++c)
-        qs[(size_t(c) * (ny + 4) + (jj + 2)) * nx + k] = out[6 * k + xmap[c]];
+        qs[(size_t(c) * (ny + 4) + (jj + 2)) * nx + k] = out[6 * k + c];
   }
+  return smax;
+}
+
+// y-sweep of a box over the intermediate state: columns in the y orientation
+// (normal momentum hv, transverse hu), each fixed up; writes the box interior
+// of qo.
+template <class T>
+double y_pass(const Params& P, const Grid& G, const T* qs, const T* B, const Box& bx, T nuy, T* qo,
+              Counters& C) {
+  const size_t pl = G.plane();
+  const int nx = bx.nx, ny = bx.ny;
+  static const int ymap[6] = {0, 2, 1, 3, 5, 4};
   std::vector<T> linev(6 * (ny + 4)), Bv(ny + 4), outv(6 * ny);
+  double smax = 0.0;
   for (int k = 0; k < nx; ++k) {
     int i = bx.ilo + k;
     for (int jj = -2; jj < ny + 2; ++jj) {
@@ -463,11 +470,23 @@ void step_box(const Params& P, const Grid& G, const T* q, const T* B, const Box&
       Bv[jj + 2] = B[G.idx(i, bx.jlo + jj)];
     }
     double s = sweep_line(P, ny, linev.data(), Bv.data(), nuy, outv.data(), true, C);
-    if (s > smax[1]) smax[1] = s;
+    if (s > smax) smax = s;
     for (int jj = 0; jj < ny; ++jj)
       for (int c = 0; c < 6; ++c)
         qo[size_t(ymap[c]) * pl + G.idx(i, bx.jlo + jj)] = outv[6 * jj + c];
   }
+  return smax;
+}
+
+// One split step of the box `bx` of a level: reads q (interior and two-cell frame
+// valid around the box), writes the box interior of qo.  x-sweep over the box rows
+// and the two frame rows on each side, fix-up, y-sweep, fix-up.
+template <class T>
+void step_box(const Params& P, const Grid& G, const T* q, const T* B, const Box& bx, double dx,
+              double dy, double dt, T* qo, double smax[2], Counters& C) {
+  std::vector<T> qs(size_t(6) * size_t(bx.nx) * size_t(bx.ny + 4));
+  smax[0] = x_pass(P, G, q, B, bx, T(dt / dx), qs.data(), C);
+  smax[1] = y_pass(P, G, qs.data(), B, bx, T(dt / dy), qo, C);
 }
 
 // Reflecting-wall fill of every frame cell of a single-box level.

@@ -285,18 +285,18 @@ __device__ __forceinline__ void fluctuations(const EdgeW& W, double am[6], doubl
   for (int p = 0; p < 6; ++p) {
     const double sv = W.s[p];
     const int md = slot_mode(W, p);
+    // Weight 1, 1/2 (tie) or 0 of the wave in each fluctuation.  A zero weight
+    // adds a zero term, which leaves a sum unchanged: the sums start at +0 and
+    // in round-to-nearest a sum is -0 only if both terms are, so none ever holds
+    // -0.  This is the same result as skipping the wave, without a branch.
+    const double wl = (md != 2 && sv < 0.0) ? 1.0 : ((md != 2 && sv == 0.0) ? 0.5 : 0.0);
+    const double wr = (md != 1 && sv > 0.0) ? 1.0 : ((md != 1 && sv == 0.0) ? 0.5 : 0.0);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       if ((p == 4 && c != 2) || (p == 5 && c != 5)) continue;  // the shear waves' zero components
-      double z = wcomp(W, p, c);
-      if (md != 2) {
-        if (sv < 0.0) am[c] = am[c] + z;
-        else if (sv == 0.0) am[c] = am[c] + 0.5 * z;
-      }
-      if (md != 1) {
-        if (sv > 0.0) ap[c] = ap[c] + z;
-        else if (sv == 0.0) ap[c] = ap[c] + 0.5 * z;
-      }
+      const double z = wcomp(W, p, c);
+      am[c] = am[c] + wl * z;
+      ap[c] = ap[c] + wr * z;
     }
   }
 }
@@ -323,13 +323,15 @@ __device__ __forceinline__ double mc_limiter(double th) {
 __device__ __forceinline__ double corr_coef(const EdgeW& W, int p, double dd, double dot_left,
                                             double dot_right, double nu) {
   const double sv = W.s[p];
-  if (slot_mode(W, p) != 0 || sv == 0.0 || dd == 0.0) return 0.0;
+  // evaluated on every lane (a safe divisor where the wave takes no correction)
+  // and selected, so the wave needs no branch
+  const bool on = slot_mode(W, p) == 0 && sv != 0.0 && dd != 0.0;
   double dn = sv > 0.0 ? dot_left : dot_right;
-  double th = MDIV(dn, dd);
+  double th = MDIV(dn, on ? dd : 1.0);
   double phi = mc_limiter(th);
   double sg = sv > 0.0 ? 0.5 : -0.5;
   double as = sv < 0.0 ? 0.0 - sv : sv;
-  return (sg * (1.0 - nu * as)) * phi;
+  return on ? (sg * (1.0 - nu * as)) * phi : 0.0;
 }
 
 // F[c] = sum_p coef_p Z_p[c] in slot order.

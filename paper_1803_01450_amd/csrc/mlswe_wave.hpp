@@ -10,9 +10,21 @@ __device__ __forceinline__ long long cidx(long long pitch, int i, int j) {
   return (long long)(j + 2) * pitch + (long long)(i + XOFF);
 }
 
-__device__ __forceinline__ double shup(double v) { return __shfl_up(v, 1, 64); }
-__device__ __forceinline__ double shdn(double v) { return __shfl_down(v, 1, 64); }
-__device__ __forceinline__ int shup_i(int v) { return __shfl_up(v, 1, 64); }
+// Whole-wave shifts by one lane through DPP (wave_shr:1 / wave_shl:1); the end
+// lane without a source keeps its own value.
+__device__ __forceinline__ int dpp_up_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_dn_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ double shup(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)dpp_up_i((int)(unsigned)b), hi = (unsigned)dpp_up_i((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double shdn(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)dpp_dn_i((int)(unsigned)b), hi = (unsigned)dpp_dn_i((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ int shup_i(int v) { return dpp_up_i(v); }
 
 __device__ __forceinline__ CellX shup_cell(const CellX& c) {
   CellX o;
