@@ -311,11 +311,16 @@ __device__ __forceinline__ double wdot(const EdgeW& U, const EdgeW& W, int p) {
   return acc;
 }
 
+// The hardware min/max may return either zero for a (-0, +0) pair, where the
+// compare-and-select form returns a fixed one.  The sign of a zero limiter
+// value is immaterial: it only scales terms added to correction sums that start
+// at +0 (which never hold -0), and adding a zero of either sign leaves them
+// unchanged.  For finite ratios the two forms agree in every other case.
 __device__ __forceinline__ double mc_limiter(double th) {
   double a = 0.5 * (1.0 + th);
   double b = 2.0 * th;
-  double m = dmin(dmin(a, 2.0), b);
-  return dmax(0.0, m);
+  double m = __builtin_fmin(__builtin_fmin(a, 2.0), b);
+  return __builtin_fmax(0.0, m);
 }
 
 // Correction-flux coefficient of wave p at an edge from its own self dot

@@ -10,6 +10,23 @@ __device__ __forceinline__ long long cidx(long long pitch, int i, int j) {
   return (long long)(j + 2) * pitch + (long long)(i + XOFF);
 }
 
+// Row access in the sweeps: a wave-uniform base (field plane and row, kept in
+// scalar registers) plus the lane's 32-bit byte offset within the row, which
+// is the scalar-base form of the global loads and stores.  Offsets stay far
+// below 2^32: a row holds at most a few thousand columns.
+// The level arrays are device allocations, so the accesses are issued as
+// global (not flat) memory operations.
+typedef __attribute__((address_space(1))) const char gchar_c;
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ unsigned lane_boff(int i) { return (unsigned)(i + XOFF) * 8u; }
+__device__ __forceinline__ gchar_c* row_of(const double* a, long long off) { return (gchar_c*)(a + off); }
+__device__ __forceinline__ double ld_at(gchar_c* row, unsigned boff) {
+  return *(__attribute__((address_space(1))) const double*)(row + boff);
+}
+__device__ __forceinline__ void st_at(double* a, long long off, unsigned boff, double v) {
+  *(__attribute__((address_space(1))) double*)((gchar*)(a + off) + boff) = v;
+}
+
 // Whole-wave shifts by one lane through DPP (wave_shr:1 / wave_shl:1); the end
 // lane without a source keeps its own value.
 __device__ __forceinline__ int dpp_up_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
