@@ -160,17 +160,20 @@ def time_fixed(B, q, dx, dy, nsteps, dt, r=0.95, g=G, hdry=HDRY, kmin=KMIN):
 
 def count_ops(B, q, dx, dy, dt, r=0.95, g=G, hdry=HDRY, kmin=KMIN):
     """FP64 operations of one oracle step of this grid, per sweep:
-    {"x": {...}, "y": {...}} with counts of add (incl. subtract), mul, div, sqrt
-    and neg, plus the cells each pass updates."""
+    {"x": {...}, "y": {...}} with counts of add (incl. subtract), mul, div, sqrt,
+    neg and fma, the flops (fma counted as two) and the cells each pass
+    updates."""
     B = _f64(B); q = _f64(q)
     ny, nx = B.shape
-    out = (ctypes.c_longlong * 10)()
+    out = (ctypes.c_longlong * 12)()
     rc = lib().ora_count_ops(nx, ny, dx, dy, g, r, hdry, kmin, _dp(B), _dp(q), dt, out)
     if rc != 0:
         raise ValueError("grid below 2 x 2")
-    names = ("add", "mul", "div", "sqrt", "neg")
+    names = ("add", "mul", "div", "sqrt", "neg", "fma")
     x = {k: int(out[i]) for i, k in enumerate(names)}
-    y = {k: int(out[5 + i]) for i, k in enumerate(names)}
+    y = {k: int(out[6 + i]) for i, k in enumerate(names)}
+    for d in (x, y):
+        d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"] + d["neg"] + 2 * d["fma"]
     x["cells"] = nx * (ny + 4)
     y["cells"] = nx * ny
     return {"x": x, "y": y}

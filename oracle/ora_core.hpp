@@ -46,6 +46,11 @@ inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
 inline double sqrt_(double x) { return std::sqrt(x); }
 inline Dual sqrt_(const Dual& x) { return sqrt(x); }
+// Fused multiply-add a*b + c with a single rounding (IEEE 754 fusedMultiplyAdd).
+inline double fma_(double a, double b, double c) { return std::fma(a, b, c); }
+inline Dual fma_(const Dual& a, const Dual& b, const Dual& c) {
+  return Dual(std::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d);
+}
 template <class T> inline T absv(const T& x) { return val(x) < 0.0 ? T(0.0) - x : x; }
 template <class T> inline T minv(const T& a, const T& b) { return val(a) < val(b) ? a : b; }
 template <class T> inline T maxv(const T& a, const T& b) { return val(a) > val(b) ? a : b; }
@@ -296,21 +301,25 @@ template <class T> void fluctuations(const Waves<T>& W, T am[6], T ap[6]) {
   for (int p = 0; p < 6; ++p) {
     double sv = val(W.s[p]);
     for (int c = 0; c < 6; ++c) {
+      // a tie adds half the wave: 0.5 Z is exact, so the fused form rounds once
+      // like the plain sum
       if (W.mode[p] != 2) {
         if (sv < 0.0) am[c] = am[c] + W.Z[p][c];
-        else if (sv == 0.0) am[c] = am[c] + T(0.5) * W.Z[p][c];
+        else if (sv == 0.0) am[c] = fma_(T(0.5), W.Z[p][c], am[c]);
       }
       if (W.mode[p] != 1) {
         if (sv > 0.0) ap[c] = ap[c] + W.Z[p][c];
-        else if (sv == 0.0) ap[c] = ap[c] + T(0.5) * W.Z[p][c];
+        else if (sv == 0.0) ap[c] = fma_(T(0.5), W.Z[p][c], ap[c]);
       }
     }
   }
 }
 
+// Dot product of two 6-vectors, accumulated left to right with fused
+// multiply-adds.
 template <class T> inline T dot6(const T* a, const T* b) {
   T acc = a[0] * b[0];
-  for (int c = 1; c < 6; ++c) acc = acc + a[c] * b[c];
+  for (int c = 1; c < 6; ++c) acc = fma_(a[c], b[c], acc);
   return acc;
 }
 
@@ -340,7 +349,7 @@ void correction(const Waves<T>& Wm, const Waves<T>& W, const Waves<T>& Wp, T nu,
         coef = (sg * (T(1.0) - nu * absv(W.s[p]))) * phi;
       }
     }
-    for (int c = 0; c < 6; ++c) F[c] = F[c] + coef * W.Z[p][c];
+    for (int c = 0; c < 6; ++c) F[c] = fma_(coef, W.Z[p][c], F[c]);
   }
 }
 
@@ -387,14 +396,16 @@ double sweep_line(const Params& P, int n, const T* line, const T* Bl, T nu, T* o
     fluctuations(W[e + 1], &am[6 * e], &ap[6 * e]);
     correction(W[e], W[e + 1], W[e + 2], nu, &F[6 * e]);
   }
+  const T mnu = T(0.0) - nu;
   for (int k = 0; k < n; ++k) {
     const T* q = line + 6 * (k + 2);
     T* o = out + 6 * k;
-    // Q - nu (A+dQ_left + A-dQ_right + F_right - F_left), grouped per edge
+    // Q - nu (A+dQ_left + A-dQ_right + F_right - F_left), grouped per edge, the
+    // product and the sum rounded once
     for (int c = 0; c < 6; ++c) {
       T gl = ap[6 * k + c] - F[6 * k + c];
       T gr = am[6 * (k + 1) + c] + F[6 * (k + 1) + c];
-      o[c] = q[c] - nu * (gl + gr);
+      o[c] = fma_(mnu, gl + gr, q[c]);
     }
     fixup(P, o, interior, C);
   }

@@ -4,15 +4,16 @@
 // Runs the oracle's own x- and y-passes of one split step (the same templated
 // code as every other oracle entry point) in a number type that counts each
 // FP64 operation the method performs: add/subtract, multiply, divide, square
-// root and negation.  The totals, per sweep, give the algorithmic operation
-// count per cell update of a workload, which prices the arithmetic roof of the
-// sweeps the way 104 bytes per cell update prices their memory roof.
+// root, negation and fused multiply-add.  The totals, per sweep, give the
+// algorithmic operation count per cell update of a workload, which prices the
+// arithmetic roof of the sweeps the way 104 bytes per cell update prices their
+// memory roof.
 #include "ora_core.hpp"
 
 namespace ora {
 
 struct OpTally {
-  long long add = 0, mul = 0, div = 0, sqrt = 0, neg = 0;
+  long long add = 0, mul = 0, div = 0, sqrt = 0, neg = 0, fma = 0;
 };
 static OpTally g_tally;
 
@@ -28,6 +29,10 @@ inline Tally operator*(Tally a, Tally b) { g_tally.mul++; return Tally(a.v * b.v
 inline Tally operator/(Tally a, Tally b) { g_tally.div++; return Tally(a.v / b.v); }
 inline double val(const Tally& x) { return x.v; }
 inline Tally sqrt_(const Tally& x) { g_tally.sqrt++; return Tally(std::sqrt(x.v)); }
+inline Tally fma_(const Tally& a, const Tally& b, const Tally& c) {
+  g_tally.fma++;
+  return Tally(std::fma(a.v, b.v, c.v));
+}
 
 }  // namespace ora
 
@@ -36,8 +41,8 @@ using namespace ora;
 extern "C" {
 
 // One step of an nx x ny wall-bounded grid (inputs as for ora_fixed_steps) with
-// the census on: out[0..4] = add, mul, div, sqrt, neg of the x-pass (ny + 4 rows
-// of nx cells), out[5..9] the same for the y-pass (nx columns of ny cells).
+// the census on: out[0..5] = add, mul, div, sqrt, neg, fma of the x-pass (ny + 4
+// rows of nx cells), out[6..11] the same for the y-pass (nx columns of ny cells).
 // Returns 0, or -1 for sizes below 2.
 int ora_count_ops(int nx, int ny, double dx, double dy, double g, double r, double hdry, double kmin,
                   const double* Bi, const double* q, double dt, long long* out) {
@@ -65,11 +70,12 @@ int ora_count_ops(int nx, int ny, double dx, double dy, double g, double r, doub
   const OpTally ty = g_tally;
   const OpTally* t[2] = {&tx, &ty};
   for (int k = 0; k < 2; ++k) {
-    out[5 * k + 0] = t[k]->add;
-    out[5 * k + 1] = t[k]->mul;
-    out[5 * k + 2] = t[k]->div;
-    out[5 * k + 3] = t[k]->sqrt;
-    out[5 * k + 4] = t[k]->neg;
+    out[6 * k + 0] = t[k]->add;
+    out[6 * k + 1] = t[k]->mul;
+    out[6 * k + 2] = t[k]->div;
+    out[6 * k + 3] = t[k]->sqrt;
+    out[6 * k + 4] = t[k]->neg;
+    out[6 * k + 5] = t[k]->fma;
   }
   return 0;
 }

@@ -285,18 +285,20 @@ __device__ __forceinline__ void fluctuations(const EdgeW& W, double am[6], doubl
   for (int p = 0; p < 6; ++p) {
     const double sv = W.s[p];
     const int md = slot_mode(W, p);
-    // Weight 1, 1/2 (tie) or 0 of the wave in each fluctuation.  A zero weight
-    // adds a zero term, which leaves a sum unchanged: the sums start at +0 and
-    // in round-to-nearest a sum is -0 only if both terms are, so none ever holds
-    // -0.  This is the same result as skipping the wave, without a branch.
+    // Weight 1, 1/2 (tie) or 0 of the wave in each fluctuation, applied by a
+    // fused multiply-add: with weight 1 it is the plain sum, with 1/2 the
+    // product is exact, and a zero weight adds a zero term, which leaves a sum
+    // unchanged (the sums start at +0 and in round-to-nearest a result is -0
+    // only if both terms are, so none ever holds -0).  The same result as
+    // skipping the wave, without a branch.
     const double wl = (md != 2 && sv < 0.0) ? 1.0 : ((md != 2 && sv == 0.0) ? 0.5 : 0.0);
     const double wr = (md != 1 && sv > 0.0) ? 1.0 : ((md != 1 && sv == 0.0) ? 0.5 : 0.0);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       if ((p == 4 && c != 2) || (p == 5 && c != 5)) continue;  // the shear waves' zero components
       const double z = wcomp(W, p, c);
-      am[c] = am[c] + wl * z;
-      ap[c] = ap[c] + wr * z;
+      am[c] = __builtin_fma(wl, z, am[c]);
+      ap[c] = __builtin_fma(wr, z, ap[c]);
     }
   }
 }
@@ -307,7 +309,7 @@ __device__ __forceinline__ double wdot(const EdgeW& U, const EdgeW& W, int p) {
   if (p == 5) return U.z5 * W.z5;
   double acc = wcomp(U, p, 0) * wcomp(W, p, 0);
 #pragma unroll
-  for (int c = 1; c < 6; ++c) acc = acc + wcomp(U, p, c) * wcomp(W, p, c);
+  for (int c = 1; c < 6; ++c) acc = __builtin_fma(wcomp(U, p, c), wcomp(W, p, c), acc);
   return acc;
 }
 
@@ -348,7 +350,7 @@ __device__ __forceinline__ void correction_flux(const EdgeW& W, const double coe
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       if ((p == 4 && c != 2) || (p == 5 && c != 5)) continue;
-      F[c] = F[c] + coef[p] * wcomp(W, p, c);
+      F[c] = __builtin_fma(coef[p], wcomp(W, p, c), F[c]);
     }
   }
 }
