@@ -217,27 +217,28 @@ void riemann(const Params& P, const CellV<T>& L, const CellV<T>& R, Waves<T>& W,
     T hb1 = T(0.5) * (L.h1 + R.h1);
     T hb2 = T(0.5) * (L.h2 + R.h2);
     T d1 = T(1.0) / (L.s1 + R.s1);
-    T ub1 = (L.s1 * L.u1 + R.s1 * R.u1) * d1;
-    T wb1 = (L.s1 * L.w1 + R.s1 * R.w1) * d1;
+    T ub1 = fma_(L.s1, L.u1, R.s1 * R.u1) * d1;
+    T wb1 = fma_(L.s1, L.w1, R.s1 * R.w1) * d1;
     T d2 = T(1.0) / (L.s2 + R.s2);
-    T ub2 = (L.s2 * L.u2 + R.s2 * R.u2) * d2;
-    T wb2 = (L.s2 * L.w2 + R.s2 * R.w2) * d2;
+    T ub2 = fma_(L.s2, L.u2, R.s2 * R.u2) * d2;
+    T wb2 = fma_(L.s2, L.w2, R.s2 * R.w2) * d2;
     // flux-minus-source jumps; the hydrostatic parts are written through the surfaces
+    // (products and sums fused where a product meets a sum)
     T del1 = R.m1 - L.m1;
-    T del2 = (R.m1 * R.u1 - L.m1 * L.u1) + (T(P.g) * hb1) * (R.eta1 - L.eta1);
+    T del2 = fma_(T(P.g) * hb1, R.eta1 - L.eta1, fma_(R.m1, R.u1, -(L.m1 * L.u1)));
     T del3 = R.m2 - L.m2;
-    T del4 = (R.m2 * R.u2 - L.m2 * L.u2) +
-             (T(P.g) * hb2) * ((R.eta2 - L.eta2) + T(P.r) * (R.h1 - L.h1));
-    T dt1 = R.t1 * R.u1 - L.t1 * L.u1;
-    T dt2 = R.t2 * R.u2 - L.t2 * L.u2;
+    T J2 = fma_(T(P.r), R.h1 - L.h1, R.eta2 - L.eta2);
+    T del4 = fma_(T(P.g) * hb2, J2, fma_(R.m2, R.u2, -(L.m2 * L.u2)));
+    T dt1 = fma_(R.t1, R.u1, -(L.t1 * L.u1));
+    T dt2 = fma_(R.t2, R.u2, -(L.t2 * L.u2));
     // speeds: external U -+ sqrt(gH), internal Uc -+ sqrt(g' h1 h2 / H * kappa)
     T H = hb1 + hb2;
     T iH = T(1.0) / H;
-    T U = (hb1 * ub1 + hb2 * ub2) * iH;
-    T Uc = (hb1 * ub2 + hb2 * ub1) * iH;
+    T U = fma_(hb1, ub1, hb2 * ub2) * iH;
+    T Uc = fma_(hb1, ub2, hb2 * ub1) * iH;
     T ce = sqrt_(T(P.g) * H);
     T du = ub1 - ub2;
-    T kap = T(1.0) - ((du * du) * iH) * T(P.inv_gp);
+    T kap = fma_(-((du * du) * iH), T(P.inv_gp), T(1.0));
     if (val(kap) < P.kmin) {
       kap = T(P.kmin);
       if (count) C.hyp++;
@@ -251,28 +252,28 @@ void riemann(const Params& P, const CellV<T>& L, const CellV<T>& R, Waves<T>& W,
     T al[4];
     for (int p = 0; p < 4; ++p) {
       T a = s[p] - ub1;
-      al[p] = (a * a - gh1) * igh;
+      al[p] = fma_(a, a, -gh1) * igh;
     }
     // Gaussian elimination of R beta = delta, no pivoting, fixed order
     T m11 = s[1] - s[0], m12 = s[2] - s[0], m13 = s[3] - s[0];
     T m21 = al[1] - al[0], m22 = al[2] - al[0], m23 = al[3] - al[0];
     T q0 = al[0] * s[0];
-    T m31 = al[1] * s[1] - q0, m32 = al[2] * s[2] - q0, m33 = al[3] * s[3] - q0;
+    T m31 = fma_(al[1], s[1], -q0), m32 = fma_(al[2], s[2], -q0), m33 = fma_(al[3], s[3], -q0);
     T b0 = del1;
-    T b1 = del2 - s[0] * del1;
-    T b2 = del3 - al[0] * del1;
-    T b3 = del4 - q0 * del1;
+    T b1 = fma_(-s[0], del1, del2);
+    T b2 = fma_(-al[0], del1, del3);
+    T b3 = fma_(-q0, del1, del4);
     T ip1 = T(1.0) / m11;
     T f2 = m21 * ip1, f3 = m31 * ip1;
-    m22 = m22 - f2 * m12; m23 = m23 - f2 * m13; b2 = b2 - f2 * b1;
-    m32 = m32 - f3 * m12; m33 = m33 - f3 * m13; b3 = b3 - f3 * b1;
+    m22 = fma_(-f2, m12, m22); m23 = fma_(-f2, m13, m23); b2 = fma_(-f2, b1, b2);
+    m32 = fma_(-f3, m12, m32); m33 = fma_(-f3, m13, m33); b3 = fma_(-f3, b1, b3);
     T ip2 = T(1.0) / m22;
     T f4 = m32 * ip2;
-    m33 = m33 - f4 * m23; b3 = b3 - f4 * b2;
+    m33 = fma_(-f4, m23, m33); b3 = fma_(-f4, b2, b3);
     T be[4];
     be[3] = b3 / m33;
-    be[2] = (b2 - m23 * be[3]) * ip2;
-    be[1] = ((b1 - m12 * be[2]) - m13 * be[3]) * ip1;
+    be[2] = fma_(-m23, be[3], b2) * ip2;
+    be[1] = fma_(-m13, be[3], fma_(-m12, be[2], b1)) * ip1;
     be[0] = ((b0 - be[1]) - be[2]) - be[3];
     for (int p = 0; p < 4; ++p) {
       T ba = be[p] * al[p];
@@ -284,8 +285,8 @@ void riemann(const Params& P, const CellV<T>& L, const CellV<T>& R, Waves<T>& W,
       W.Z[p][4] = ba * s[p];
       W.Z[p][5] = ba * wb2;
     }
-    W.s[4] = ub1; W.Z[4][2] = dt1 - wb1 * del1;
-    W.s[5] = ub2; W.Z[5][5] = dt2 - wb2 * del3;
+    W.s[4] = ub1; W.Z[4][2] = fma_(-wb1, del1, dt1);
+    W.s[5] = ub2; W.Z[5][5] = fma_(-wb2, del3, dt2);
     return;
   }
   // some layer dry on some side: each layer alone over its effective bottom

@@ -162,32 +162,32 @@ __device__ __forceinline__ void riemann_reverse(const PhysParams& P, const CellX
   const double hb1 = 0.5 * (L.h1 + R.h1);
   const double hb2 = 0.5 * (L.h2 + R.h2);
   const double d1 = 1.0 / (L.s1 + R.s1);
-  const double nu1 = L.s1 * L.u1 + R.s1 * R.u1, nw1 = L.s1 * L.w1 + R.s1 * R.w1;
+  const double nu1 = FMA(L.s1, L.u1, R.s1 * R.u1), nw1 = FMA(L.s1, L.w1, R.s1 * R.w1);
   const double ub1 = nu1 * d1, wb1 = nw1 * d1;
   const double d2 = 1.0 / (L.s2 + R.s2);
-  const double nu2 = L.s2 * L.u2 + R.s2 * R.u2, nw2 = L.s2 * L.w2 + R.s2 * R.w2;
+  const double nu2 = FMA(L.s2, L.u2, R.s2 * R.u2), nw2 = FMA(L.s2, L.w2, R.s2 * R.w2);
   const double ub2 = nu2 * d2, wb2 = nw2 * d2;
   const double del1 = R.m1 - L.m1;
-  const double del2 = (R.m1 * R.u1 - L.m1 * L.u1) + (P.g * hb1) * (R.e1 - L.e1);
+  const double del2 = FMA(P.g * hb1, R.e1 - L.e1, FMA(R.m1, R.u1, -(L.m1 * L.u1)));
   const double del3 = R.m2 - L.m2;
-  const double J4 = (R.e2 - L.e2) + P.r * (R.h1 - L.h1);
-  const double del4 = (R.m2 * R.u2 - L.m2 * L.u2) + (P.g * hb2) * J4;
+  const double J4 = FMA(P.r, R.h1 - L.h1, R.e2 - L.e2);
+  const double del4 = FMA(P.g * hb2, J4, FMA(R.m2, R.u2, -(L.m2 * L.u2)));
   const double H = hb1 + hb2;
   const double iH = 1.0 / H;
   const double ce = __builtin_sqrt(P.g * H);
   const double du = ub1 - ub2;
-  double kap = 1.0 - ((du * du) * iH) * P.inv_gp;
+  double kap = FMA(-((du * du) * iH), P.inv_gp, 1.0);
   bool clamped = false;
   if (kap < P.kmin) { kap = P.kmin; clamped = true; }
   const double ci = __builtin_sqrt((((P.gp * hb1) * hb2) * iH) * kap);
-  const double U = (hb1 * ub1 + hb2 * ub2) * iH;
-  const double Uc = (hb1 * ub2 + hb2 * ub1) * iH;
+  const double U = FMA(hb1, ub1, hb2 * ub2) * iH;
+  const double Uc = FMA(hb1, ub2, hb2 * ub1) * iH;
   double s[4] = {U - ce, Uc - ci, Uc + ci, U + ce};
   const double gh1 = P.g * hb1;
   const double igh = 1.0 / gh1;
   double a[4], al[4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p) { a[p] = s[p] - ub1; al[p] = (a[p] * a[p] - gh1) * igh; }
+  for (int p = 0; p < 4; ++p) { a[p] = s[p] - ub1; al[p] = FMA(a[p], a[p], -gh1) * igh; }
   double Rm[4][4];
 #pragma unroll
   for (int p = 0; p < 4; ++p) { Rm[0][p] = 1.0; Rm[1][p] = s[p]; Rm[2][p] = al[p]; Rm[3][p] = al[p] * s[p]; }
@@ -197,24 +197,24 @@ __device__ __forceinline__ void riemann_reverse(const PhysParams& P, const CellX
     double m11 = s[1] - s[0], m12 = s[2] - s[0], m13 = s[3] - s[0];
     double m21 = al[1] - al[0], m22 = al[2] - al[0], m23 = al[3] - al[0];
     double q0 = al[0] * s[0];
-    double m31 = al[1] * s[1] - q0, m32 = al[2] * s[2] - q0, m33 = al[3] * s[3] - q0;
-    double b0 = del1, b1 = del2 - s[0] * del1, b2 = del3 - al[0] * del1, b3 = del4 - q0 * del1;
+    double m31 = FMA(al[1], s[1], -q0), m32 = FMA(al[2], s[2], -q0), m33 = FMA(al[3], s[3], -q0);
+    double b0 = del1, b1 = FMA(-s[0], del1, del2), b2 = FMA(-al[0], del1, del3), b3 = FMA(-q0, del1, del4);
     double ip1 = 1.0 / m11;
     double f2 = m21 * ip1, f3 = m31 * ip1;
-    m22 = m22 - f2 * m12; m23 = m23 - f2 * m13; b2 = b2 - f2 * b1;
-    m32 = m32 - f3 * m12; m33 = m33 - f3 * m13; b3 = b3 - f3 * b1;
+    m22 = FMA(-f2, m12, m22); m23 = FMA(-f2, m13, m23); b2 = FMA(-f2, b1, b2);
+    m32 = FMA(-f3, m12, m32); m33 = FMA(-f3, m13, m33); b3 = FMA(-f3, b1, b3);
     double ip2 = 1.0 / m22;
     double f4 = m32 * ip2;
-    m33 = m33 - f4 * m23; b3 = b3 - f4 * b2;
+    m33 = FMA(-f4, m23, m33); b3 = FMA(-f4, b2, b3);
     be[3] = b3 / m33;
-    be[2] = (b2 - m23 * be[3]) * ip2;
-    be[1] = ((b1 - m12 * be[2]) - m13 * be[3]) * ip1;
+    be[2] = FMA(-m23, be[3], b2) * ip2;
+    be[1] = FMA(-m13, be[3], FMA(-m12, be[2], b1)) * ip1;
     be[0] = ((b0 - be[1]) - be[2]) - be[3];
   }
   // ---- reverse
   double sb[4], alb[4], beb[4];
   double ub1b = sb_in[4], ub2b = sb_in[5];
-  double wb1b = v1b - z4b * del1, wb2b = v2b - z5b * del3;
+  double wb1b = v1b - z4b * del1, wb2b = v2b - z5b * del3;  // z4 = dt1 - wb1 del1, z5 likewise
   double dt1b = z4b, dt2b = z5b;
   double del1b = -z4b * wb1, del3b = -z5b * wb2, del2b = 0.0, del4b = 0.0;
 #pragma unroll

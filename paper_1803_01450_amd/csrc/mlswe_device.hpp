@@ -68,6 +68,8 @@ __device__ __forceinline__ double mdiv(double a, double b) {
 #define MSQRT(x) __builtin_sqrt(x)
 #endif
 
+#define FMA(a, b, c) __builtin_fma(a, b, c)
+
 // Per-sweep view of one cell.  m: normal momentum, t: transverse momentum.
 struct CellX {
   double h1, m1, t1, h2, m2, t2, B;
@@ -215,59 +217,60 @@ __device__ __forceinline__ bool riemann(const PhysParams& P, const CellX& L, con
     double hb1 = 0.5 * (L.h1 + R.h1);
     double hb2 = 0.5 * (L.h2 + R.h2);
     double d1 = MRCP(L.s1 + R.s1);
-    double ub1 = (L.s1 * L.u1 + R.s1 * R.u1) * d1;
-    double wb1 = (L.s1 * L.w1 + R.s1 * R.w1) * d1;
+    double ub1 = FMA(L.s1, L.u1, R.s1 * R.u1) * d1;
+    double wb1 = FMA(L.s1, L.w1, R.s1 * R.w1) * d1;
     double d2 = MRCP(L.s2 + R.s2);
-    double ub2 = (L.s2 * L.u2 + R.s2 * R.u2) * d2;
-    double wb2 = (L.s2 * L.w2 + R.s2 * R.w2) * d2;
+    double ub2 = FMA(L.s2, L.u2, R.s2 * R.u2) * d2;
+    double wb2 = FMA(L.s2, L.w2, R.s2 * R.w2) * d2;
     double del1 = R.m1 - L.m1;
-    double del2 = (R.m1 * R.u1 - L.m1 * L.u1) + (P.g * hb1) * (R.e1 - L.e1);
+    double del2 = FMA(P.g * hb1, R.e1 - L.e1, FMA(R.m1, R.u1, -(L.m1 * L.u1)));
     double del3 = R.m2 - L.m2;
-    double del4 = (R.m2 * R.u2 - L.m2 * L.u2) + (P.g * hb2) * ((R.e2 - L.e2) + P.r * (R.h1 - L.h1));
-    double dt1 = R.t1 * R.u1 - L.t1 * L.u1;
-    double dt2 = R.t2 * R.u2 - L.t2 * L.u2;
+    double J2 = FMA(P.r, R.h1 - L.h1, R.e2 - L.e2);
+    double del4 = FMA(P.g * hb2, J2, FMA(R.m2, R.u2, -(L.m2 * L.u2)));
+    double dt1 = FMA(R.t1, R.u1, -(L.t1 * L.u1));
+    double dt2 = FMA(R.t2, R.u2, -(L.t2 * L.u2));
     double H = hb1 + hb2;
     double iH = MRCP(H);
-    double U = (hb1 * ub1 + hb2 * ub2) * iH;
-    double Uc = (hb1 * ub2 + hb2 * ub1) * iH;
+    double U = FMA(hb1, ub1, hb2 * ub2) * iH;
+    double Uc = FMA(hb1, ub2, hb2 * ub1) * iH;
     double ce = MSQRT(P.g * H);
     double du = ub1 - ub2;
-    double kap = 1.0 - ((du * du) * iH) * P.inv_gp;
+    double kap = FMA(-((du * du) * iH), P.inv_gp, 1.0);
     if (kap < P.kmin) { kap = P.kmin; clamped = true; }
     double ci = MSQRT((((P.gp * hb1) * hb2) * iH) * kap);
     double s0 = U - ce, s1 = Uc - ci, s2 = Uc + ci, s3 = U + ce;
     double gh1 = P.g * hb1;
     double igh = MRCP(gh1);
     double a;
-    a = s0 - ub1; double al0 = (a * a - gh1) * igh;
-    a = s1 - ub1; double al1 = (a * a - gh1) * igh;
-    a = s2 - ub1; double al2 = (a * a - gh1) * igh;
-    a = s3 - ub1; double al3 = (a * a - gh1) * igh;
+    a = s0 - ub1; double al0 = FMA(a, a, -gh1) * igh;
+    a = s1 - ub1; double al1 = FMA(a, a, -gh1) * igh;
+    a = s2 - ub1; double al2 = FMA(a, a, -gh1) * igh;
+    a = s3 - ub1; double al3 = FMA(a, a, -gh1) * igh;
     double m11 = s1 - s0, m12 = s2 - s0, m13 = s3 - s0;
     double m21 = al1 - al0, m22 = al2 - al0, m23 = al3 - al0;
     double q0 = al0 * s0;
-    double m31 = al1 * s1 - q0, m32 = al2 * s2 - q0, m33 = al3 * s3 - q0;
+    double m31 = FMA(al1, s1, -q0), m32 = FMA(al2, s2, -q0), m33 = FMA(al3, s3, -q0);
     double b0 = del1;
-    double b1 = del2 - s0 * del1;
-    double b2 = del3 - al0 * del1;
-    double b3 = del4 - q0 * del1;
+    double b1 = FMA(-s0, del1, del2);
+    double b2 = FMA(-al0, del1, del3);
+    double b3 = FMA(-q0, del1, del4);
     double ip1 = MRCP(m11);
     double f2 = m21 * ip1, f3 = m31 * ip1;
-    m22 = m22 - f2 * m12; m23 = m23 - f2 * m13; b2 = b2 - f2 * b1;
-    m32 = m32 - f3 * m12; m33 = m33 - f3 * m13; b3 = b3 - f3 * b1;
+    m22 = FMA(-f2, m12, m22); m23 = FMA(-f2, m13, m23); b2 = FMA(-f2, b1, b2);
+    m32 = FMA(-f3, m12, m32); m33 = FMA(-f3, m13, m33); b3 = FMA(-f3, b1, b3);
     double ip2 = MRCP(m22);
     double f4 = m32 * ip2;
-    m33 = m33 - f4 * m23; b3 = b3 - f4 * b2;
+    m33 = FMA(-f4, m23, m33); b3 = FMA(-f4, b2, b3);
     double be3 = MDIV(b3, m33);
-    double be2 = (b2 - m23 * be3) * ip2;
-    double be1 = ((b1 - m12 * be2) - m13 * be3) * ip1;
+    double be2 = FMA(-m23, be3, b2) * ip2;
+    double be1 = FMA(-m13, be3, FMA(-m12, be2, b1)) * ip1;
     double be0 = ((b0 - be1) - be2) - be3;
     W.s[0] = s0; W.s[1] = s1; W.s[2] = s2; W.s[3] = s3;
     W.A[0] = be0; W.A[1] = be1; W.A[2] = be2; W.A[3] = be3;
     W.C[0] = be0 * al0; W.C[1] = be1 * al1; W.C[2] = be2 * al2; W.C[3] = be3 * al3;
     W.v1 = wb1; W.v2 = wb2;
-    W.s[4] = ub1; W.z4 = dt1 - wb1 * del1;
-    W.s[5] = ub2; W.z5 = dt2 - wb2 * del3;
+    W.s[4] = ub1; W.z4 = FMA(-wb1, del1, dt1);
+    W.s[5] = ub2; W.z5 = FMA(-wb2, del3, dt2);
     return clamped;
   }
   double J1 = R.e1 - L.e1;
