@@ -27,10 +27,12 @@ __device__ __forceinline__ void st_at(double* a, long long off, unsigned boff, d
   *(__attribute__((address_space(1))) double*)((gchar*)(a + off) + boff) = v;
 }
 
-// Whole-wave shifts by one lane through DPP (wave_shr:1 / wave_shl:1); the end
-// lane without a source keeps its own value.
-__device__ __forceinline__ int dpp_up_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_dn_i(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+// Whole-wave rotations by one lane through DPP (wave_ror:1 / wave_rol:1): every
+// lane receives a value, so no copy of the old register is needed.  The end
+// lanes receive the other end's value; they are halo lanes whose edges feed no
+// update, speed or counter.
+__device__ __forceinline__ int dpp_up_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_dn_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xf, 0xf, false); }
 __device__ __forceinline__ double shup(double v) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
   const unsigned lo = (unsigned)dpp_up_i((int)(unsigned)b), hi = (unsigned)dpp_up_i((int)(unsigned)(b >> 32));
