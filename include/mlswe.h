@@ -51,8 +51,8 @@ typedef struct mlswe_config {
   double kmin;        /* floor of the internal-wave hyperbolicity factor */
   double cfl_desired; /* Courant number aimed at by the dt rule (0.9) */
   double cfl_max;     /* Courant number above which a substep fails (1.0) */
-  int y_rows;         /* rows per y-sweep wave on large patches (0 = 128) */
-  int x_rows;         /* rows per x-sweep wave (0 = 16) */
+  int y_rows;         /* rows per y-sweep wave (0 = chosen per level, see mlswe_tuning) */
+  int x_rows;         /* rows per x-sweep wave (0 = chosen per level) */
   int64_t max_device_bytes; /* cap on the library's device memory (0 = none) */
   int max_retries;    /* a coarse step whose largest substep Courant number exceeds
                          cfl_max is undone and retaken with dt scaled by
@@ -63,7 +63,8 @@ typedef struct mlswe_config {
 
 /* Launch shape of the two sweep kernels.  rows: rows of a patch per x-sweep
  * wave / per y-sweep wave (a y wave marches its rows with the last edge in
- * registers).  sched: 0 one wave per tile, 1 persistent waves striding over
+ * registers); 0 chooses them per level: 16 (x) and 128 (y), halved while the
+ * level's tiles over all problems would not fill the device, down to 4 and 8.  sched: 0 one wave per tile, 1 persistent waves striding over
  * the tile list, 2 persistent waves taking tiles from an atomic ticket.
  * grid: persistent blocks of four waves per compute unit.  fast: 1 selects the
  * build of the sweeps with Newton-refined hardware reciprocals and reciprocal

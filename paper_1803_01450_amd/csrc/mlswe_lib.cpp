@@ -83,6 +83,7 @@ struct LevelLaunch {
   XTile* xt = nullptr;
   YTile* yt = nullptr;
   int nxt = 0, nyt = 0;
+  int rows_x = 0, rows_y = 0;                // rows per sweep wave in the current tiles
   FillPatch* fp[4] = {nullptr, nullptr, nullptr, nullptr};   // [fine parity * 2 + coarse parity]
   CoarsenPatch* cp[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<int> fill_first;               // per problem: first fill entry (or -1) and count
@@ -259,8 +260,32 @@ std::vector<Box> cluster_tiles(const LevelH& C, int r, const std::vector<unsigne
 int build_launch(mlswe_ctx* c, int l) {
   LevelLaunch& LL = c->launch[l];
   if (!LL.dirty) return MLSWE_OK;
-  const int xrows = c->tune.x_rows > 0 ? c->tune.x_rows : 16;
-  const int yrows = c->tune.y_rows > 0 ? c->tune.y_rows : 128;
+  // Rows per sweep wave: the tuned value, or (0) the largest of 16 (x) / 128 (y)
+  // halved while the level's tiles, over every problem, would not fill the
+  // device (two x waves and one y wave per SIMD, four SIMDs per compute unit);
+  // never below 4 (x) / 8 (y), where the halo rows start to dominate.
+  auto count_tiles = [&](int axis, int rows) {
+    long long n = 0;
+    for (const ProblemH& P : c->probs) {
+      if (l >= P.nlev) continue;
+      for (const Box& b : P.L[l].boxes) {
+        if (axis == 0) n += (long long)((b.nx + XTILE_COLS - 1) / XTILE_COLS) * ((b.ny + 4 + rows - 1) / rows);
+        else n += (long long)((b.nx + 63) / 64) * ((b.ny + rows - 1) / rows);
+      }
+    }
+    return n;
+  };
+  int xrows = c->tune.x_rows, yrows = c->tune.y_rows;
+  if (xrows <= 0) {
+    xrows = 16;
+    while (xrows > 4 && count_tiles(0, xrows) < 8LL * c->ncu) xrows /= 2;
+  }
+  if (yrows <= 0) {
+    yrows = 128;
+    while (yrows > 8 && count_tiles(1, yrows) < 4LL * c->ncu) yrows /= 2;
+  }
+  LL.rows_x = xrows;
+  LL.rows_y = yrows;
   std::vector<PatchDev> pd[2];
   std::vector<XTile> xt;
   std::vector<YTile> yt;
@@ -807,8 +832,8 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
     c->ncu = prop.multiProcessorCount;
   std::memset(&c->tune, 0, sizeof c->tune);
-  c->tune.x_rows = d.x_rows > 0 ? d.x_rows : 16;
-  c->tune.y_rows = d.y_rows > 0 ? d.y_rows : 128;
+  c->tune.x_rows = d.x_rows;  // 0: chosen per level when the tiles are built
+  c->tune.y_rows = d.y_rows;
   c->tune.grid_x = 1;
   c->tune.grid_y = 1;
   if (dalloc(c, (void**)&c->tickets, 2 * sizeof(unsigned)) != MLSWE_OK) { delete c; return MLSWE_ENOMEM; }
@@ -1577,7 +1602,7 @@ extern "C" int mlswe_get_tuning(mlswe_ctx* c, mlswe_tuning* out) {
 
 extern "C" int mlswe_set_tuning(mlswe_ctx* c, const mlswe_tuning* t) {
   if (!c || !t) return MLSWE_EINVAL;
-  if (t->x_rows < 1 || t->x_rows > 4096 || t->y_rows < 1 || t->y_rows > 4096 || t->sched_x < 0 || t->sched_x > 2 ||
+  if (t->x_rows < 0 || t->x_rows > 4096 || t->y_rows < 0 || t->y_rows > 4096 || t->sched_x < 0 || t->sched_x > 2 ||
       t->sched_y < 0 || t->sched_y > 2 || t->grid_x < 0 || t->grid_x > 64 || t->grid_y < 0 || t->grid_y > 64 ||
       t->fast < 0 || t->fast > 1)
     return fail(c, MLSWE_EINVAL, "bad tuning");
@@ -1674,9 +1699,10 @@ extern "C" int mlswe_autotune(mlswe_ctx* c, const char* cache_path, int reps) {
   mlswe_tuning best = c->tune;
   int rc = MLSWE_OK;
   for (int axis = 0; axis < 2 && !rc; ++axis) {
-    const int rows_x[3] = {8, 16, 32};
-    const int rows_y[4] = {32, 64, 128, 256};
-    const int nrows = axis == 0 ? 3 : 4;
+    // 0: the per-level choice made when the tiles are built
+    const int rows_x[5] = {0, 4, 8, 16, 32};
+    const int rows_y[6] = {0, 16, 32, 64, 128, 256};
+    const int nrows = axis == 0 ? 5 : 6;
     double best_ms = 1e300;
     for (int ri = 0; ri < nrows && !rc; ++ri)
       for (int si = 0; si < 5 && !rc; ++si) {

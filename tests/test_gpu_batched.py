@@ -117,3 +117,16 @@ def test_autotune_keeps_state_and_caches():
     C.advance(6, 2, TAU, mode=1)
     assert same(states(A), states(C))
     A.close(); B.close(); C.close()
+
+
+def test_auto_tile_heights_bitwise():
+    """Tile heights chosen per level (small levels get short tiles) give the
+    same state, bit for bit, as fixed heights."""
+    say("case: auto tile heights vs fixed 16/128")
+    A = build()
+    assert A.tuning()["x_rows"] == 0 and A.tuning()["y_rows"] == 0
+    A.advance(6, 3, TAU, mode=1)
+    B = build(dict(x_rows=16, y_rows=128))
+    B.advance(6, 3, TAU, mode=1)
+    assert same(states(A), states(B))
+    A.close(); B.close()
