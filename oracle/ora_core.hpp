@@ -297,11 +297,16 @@ void riemann(const Params& P, const CellV<T>& L, const CellV<T>& R, Waves<T>& W,
 }
 
 // A- dQ (into the left cell) and A+ dQ (into the right cell); a tie at s = 0 is split.
+// The shear waves (slots 4 and 5) have a single nonzero component (2 and 5), so
+// sums over their components take that one term only.
+inline bool wave_comp(int p, int c) { return p < 4 || (p == 4 && c == 2) || (p == 5 && c == 5); }
+
 template <class T> void fluctuations(const Waves<T>& W, T am[6], T ap[6]) {
   for (int c = 0; c < 6; ++c) { am[c] = T(0.0); ap[c] = T(0.0); }
   for (int p = 0; p < 6; ++p) {
     double sv = val(W.s[p]);
     for (int c = 0; c < 6; ++c) {
+      if (!wave_comp(p, c)) continue;
       // a tie adds half the wave: 0.5 Z is exact, so the fused form rounds once
       // like the plain sum
       if (W.mode[p] != 2) {
@@ -324,6 +329,13 @@ template <class T> inline T dot6(const T* a, const T* b) {
   return acc;
 }
 
+// Dot product of wave p of two edges over its components.
+template <class T> inline T wave_dot(const Waves<T>& U, const Waves<T>& W, int p) {
+  if (p == 4) return U.Z[4][2] * W.Z[4][2];
+  if (p == 5) return U.Z[5][5] * W.Z[5][5];
+  return dot6(U.Z[p], W.Z[p]);
+}
+
 // MC limiter phi(theta) = max(0, min((1+theta)/2, 2, 2 theta)).
 template <class T> inline T mc_limiter(const T& th) {
   T a = T(0.5) * (T(1.0) + th);
@@ -340,17 +352,18 @@ void correction(const Waves<T>& Wm, const Waves<T>& W, const Waves<T>& Wp, T nu,
     double sv = val(W.s[p]);
     T coef = T(0.0);
     if (W.mode[p] == 0 && sv != 0.0) {
-      T dd = dot6(W.Z[p], W.Z[p]);
+      T dd = wave_dot(W, W, p);
       if (val(dd) != 0.0) {
         const Waves<T>& U = (sv > 0.0) ? Wm : Wp;
-        T dn = dot6(U.Z[p], W.Z[p]);
+        T dn = wave_dot(U, W, p);
         T th = dn / dd;
         T phi = mc_limiter(th);
         T sg = T(sv > 0.0 ? 0.5 : -0.5);
         coef = (sg * (T(1.0) - nu * absv(W.s[p]))) * phi;
       }
     }
-    for (int c = 0; c < 6; ++c) F[c] = fma_(coef, W.Z[p][c], F[c]);
+    for (int c = 0; c < 6; ++c)
+      if (wave_comp(p, c)) F[c] = fma_(coef, W.Z[p][c], F[c]);
   }
 }
 

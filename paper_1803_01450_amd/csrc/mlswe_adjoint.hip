@@ -302,8 +302,10 @@ __global__ __launch_bounds__(256) void k_adj_edges(AdjView V) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long ne = (long long)V.n + 3;
   if (t >= ne * V.nlines) return;
-  const int line = (int)(t / ne);
-  const int e = (int)(t % ne) - 1;
+  // neighbouring threads take neighbouring memory: along the line when the
+  // line is contiguous (x), across lines otherwise (y)
+  const int line = V.orient ? (int)(t % V.nlines) : (int)(t / ne);
+  const int e = (V.orient ? (int)(t / V.nlines) : (int)(t % ne)) - 1;
   const int n = V.n;
   const double nu = V.nu;
   const bool hasPrev = e >= 0;      // edge e-1 exists (its left cell is >= -2)
@@ -455,8 +457,8 @@ __global__ __launch_bounds__(256) void k_adj_gather(AdjView V, double* lam_in, d
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nk = (long long)V.n + 4;
   if (t >= nk * V.nlines) return;
-  const int line = (int)(t / nk);
-  const int k = (int)(t % nk) - 2;
+  const int line = V.orient ? (int)(t % V.nlines) : (int)(t / nk);
+  const int k = (V.orient ? (int)(t / V.nlines) : (int)(t % nk)) - 2;
   const long long id = aidx(V, line, k);
   const long long pl = V.plane;
   const bool upd = k >= 0 && k < V.n;

@@ -193,22 +193,66 @@ __global__ __launch_bounds__(256) void k_flag_dilate(FlagLevel F) {
 // ---------------------------------------------------------------- time step
 // After a level substep: Courant check with this substep's speeds, fold them
 // into the coarse-step maximum, clear them.
-__global__ void k_after_substep(LevelCtl* ctls, const LevelInfo* infos, int n, double cflmax) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  LevelCtl& C = ctls[infos[k].ctl];
-  const double sx = __longlong_as_double((long long)C.step_smax[0]);
-  const double sy = __longlong_as_double((long long)C.step_smax[1]);
-  const double ax = sx / infos[k].dx, ay = sy / infos[k].dy;
+// After a substep: one block per (problem, level) reduces the partials of that
+// problem's x and y tiles (each wave a strided share, then across the waves),
+// then records the largest speeds, the Courant number and the CFL status, and
+// adds the fix-up and clamp counts to the problem's counters.  Speeds are kept
+// as the bit patterns of non-negative doubles.  Block size: a multiple of 64,
+// at most 1024.
+__global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos,
+                                                        const TilePart* parts, double cflmax) {
+  __shared__ double red_d[4][16];
+  __shared__ unsigned long long red_u[3][16];
+  const LevelInfo I = infos[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double sx = 0.0, sy = 0.0, c1 = 0.0, c2 = 0.0;
+  unsigned long long h = 0, nc = 0, rp = 0;
+  for (int k = threadIdx.x; k < I.nx + I.ny; k += blockDim.x) {
+    const TilePart T = parts[k < I.nx ? I.x0 + k : I.y0 + (k - I.nx)];
+    if (k < I.nx) sx = T.smax > sx ? T.smax : sx;
+    else sy = T.smax > sy ? T.smax : sy;
+    c1 += T.clip1;
+    c2 += T.clip2;
+    h += T.hyp;
+    nc += T.nclip;
+    rp += T.repair;
+  }
+  sx = wave_max(sx);
+  sy = wave_max(sy);
+  c1 = wave_sum(c1);
+  c2 = wave_sum(c2);
+  h = wave_usum(h);
+  nc = wave_usum(nc);
+  rp = wave_usum(rp);
+  if (lane == 0) {
+    red_d[0][wave] = sx; red_d[1][wave] = sy; red_d[2][wave] = c1; red_d[3][wave] = c2;
+    red_u[0][wave] = h; red_u[1][wave] = nc; red_u[2][wave] = rp;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < nw; ++w) {
+    sx = red_d[0][w] > sx ? red_d[0][w] : sx;
+    sy = red_d[1][w] > sy ? red_d[1][w] : sy;
+    c1 += red_d[2][w]; c2 += red_d[3][w];
+    h += red_u[0][w]; nc += red_u[1][w]; rp += red_u[2][w];
+  }
+  LevelCtl& C = ctls[I.ctl];
+  const double ax = sx / I.dx, ay = sy / I.dy;
   const double courant = C.dt * (ax > ay ? ax : ay);
   if (courant > C.cmax || courant != courant) C.cmax = courant;
   if (!(courant <= cflmax)) C.status |= STATUS_CFL;
-  C.last_smax[0] = C.step_smax[0];
-  C.last_smax[1] = C.step_smax[1];
-  if (C.step_smax[0] > C.acc_smax[0]) C.acc_smax[0] = C.step_smax[0];
-  if (C.step_smax[1] > C.acc_smax[1]) C.acc_smax[1] = C.step_smax[1];
-  C.step_smax[0] = 0ull;
-  C.step_smax[1] = 0ull;
+  const unsigned long long bx = (unsigned long long)__double_as_longlong(sx);
+  const unsigned long long by = (unsigned long long)__double_as_longlong(sy);
+  C.last_smax[0] = bx;
+  C.last_smax[1] = by;
+  if (bx > C.acc_smax[0]) C.acc_smax[0] = bx;
+  if (by > C.acc_smax[1]) C.acc_smax[1] = by;
+  Counters& K = cnts[I.cnt];
+  K.hyp += h;
+  K.nclip += nc;
+  K.repair += rp;
+  if (c1 != 0.0) K.clip1 += c1;
+  if (c2 != 0.0) K.clip2 += c2;
 }
 
 // Largest initial signal speed max(|u|,|v|) + sqrt(g (h1 + h2)) over covered cells.
@@ -323,6 +367,25 @@ __global__ __launch_bounds__(256) void k_nan_uncovered(double* q, const unsigned
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
 #pragma unroll
   for (int f = 0; f < 6; ++f) q[f * pu + t] = nan;
+}
+
+// Six fields between a level array (interior cells, padded rows) and the
+// compact [6][ny][nx] layout of the interface; dir 0: compact -> level,
+// 1: level -> compact.  One launch instead of one strided copy per field.
+__global__ __launch_bounds__(256) void k_copy6(double* lv, long long pitch, long long plane, double* cq, int nx,
+                                               int ny, int dir) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long pu = (long long)nx * ny;
+  if (t >= pu) return;
+  const int i = (int)(t % nx), j = (int)(t / nx);
+  const long long id = cidx(pitch, i, j);
+  if (dir == 0) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f) lv[f * plane + id] = cq[f * pu + t];
+  } else {
+#pragma unroll
+    for (int f = 0; f < 6; ++f) cq[f * pu + t] = lv[f * plane + id];
+  }
 }
 
 }  // namespace mlswe

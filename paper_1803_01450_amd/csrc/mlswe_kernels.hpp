@@ -19,7 +19,6 @@ struct Counters {
 // Device-resident time-step control of one (problem, level).
 struct LevelCtl {
   double dt;                        // substep of this level
-  unsigned long long step_smax[2];  // largest speeds (bit patterns) of the current substep
   unsigned long long acc_smax[2];   // largest speeds over the current coarse step
   unsigned long long last_smax[2];  // largest speeds of the last finished substep
   double t;                         // simulated time (level 0 entry of a problem)
@@ -83,7 +82,21 @@ struct FlagLevel {
   double dx, dy, tau, hdry;
 };
 
-struct LevelInfo { int ctl; double dx, dy; };
+// Partial results of one sweep tile (largest edge speed, fix-up and clamp
+// counts), written by the tile's wave and reduced per problem and level after
+// the substep, so no two waves update the same word.
+struct TilePart {
+  double smax, clip1, clip2;
+  unsigned hyp, nclip, repair, pad;
+};
+
+// One problem on one level: its control block and counters, spacings, and the
+// ranges of its x- and y-tile partials in the level's partial array.
+struct LevelInfo {
+  int ctl, cnt;
+  double dx, dy;
+  int x0, nx, y0, ny;
+};
 
 struct SpeedLevel {
   const double* q;
@@ -157,24 +170,26 @@ __global__ void k_gauge(Gauge G);
 __global__ void k_set_dt(LevelCtl* ctl, const double* __restrict__ dts, int k);
 
 __global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles, int sched,
-                          unsigned* ticket);
+                          unsigned* ticket, TilePart* parts);
 __global__ void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles, int sched,
-                          unsigned* ticket);
+                          unsigned* ticket, TilePart* parts);
 __global__ void k_sweep_x_fast(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles,
-                               int sched, unsigned* ticket);
+                               int sched, unsigned* ticket, TilePart* parts);
 __global__ void k_sweep_y_fast(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
-                               int sched, unsigned* ticket);
+                               int sched, unsigned* ticket, TilePart* parts);
 __global__ void k_zero_u32(unsigned* p, int n);
 __global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass);
 __global__ void k_refine_new(const FillPatch* __restrict__ fills, const unsigned char* __restrict__ old_mask);
 __global__ void k_coarsen(const CoarsenPatch* __restrict__ cps);
 __global__ void k_flag_raw(FlagLevel F);
 __global__ void k_flag_dilate(FlagLevel F);
-__global__ void k_after_substep(LevelCtl* ctls, const LevelInfo* infos, int n, double cflmax);
+__global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, const TilePart* parts,
+                                double cflmax);
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
 __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial);
 __global__ void k_set_theta(double* th, double v);
 __global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);
+__global__ void k_copy6(double* lv, long long pitch, long long plane, double* cq, int nx, int ny, int dir);
 __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob);
 __global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const double* __restrict__ dt0, int nprob);
 

@@ -84,6 +84,9 @@ struct LevelLaunch {
   YTile* yt = nullptr;
   int nxt = 0, nyt = 0;
   int rows_x = 0, rows_y = 0;                // rows per sweep wave in the current tiles
+  TilePart* parts = nullptr;                 // per tile: x tiles, then y tiles
+  int cap_parts = 0;
+  int max_info_tiles = 0;                    // most tiles of one problem on the level
   FillPatch* fp[4] = {nullptr, nullptr, nullptr, nullptr};   // [fine parity * 2 + coarse parity]
   CoarsenPatch* cp[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<int> fill_first;               // per problem: first fill entry (or -1) and count
@@ -178,6 +181,7 @@ void dfree(void* p) {
 }
 
 long long idx(const LevelH& L, int i, int j) { return (long long)(j + 2) * L.pitch + (i + XOFF); }
+unsigned blocks(long long n) { return (unsigned)((n + 255) / 256); }
 
 bool valid_prob(mlswe_ctx* c, int p) { return p >= 0 && p < (int)c->probs.size(); }
 
@@ -262,8 +266,9 @@ int build_launch(mlswe_ctx* c, int l) {
   if (!LL.dirty) return MLSWE_OK;
   // Rows per sweep wave: the tuned value, or (0) the largest of 16 (x) / 128 (y)
   // halved while the level's tiles, over every problem, would not fill the
-  // device (two x waves and one y wave per SIMD, four SIMDs per compute unit);
-  // never below 4 (x) / 8 (y), where the halo rows start to dominate.
+  // device with room to balance (x: two waves per SIMD, four rounds; y: one
+  // wave per SIMD, one round; four SIMDs per compute unit); never below 4 (x),
+  // where the start of a tile dominates, or 8 (y), where its halo rows do.
   auto count_tiles = [&](int axis, int rows) {
     long long n = 0;
     for (const ProblemH& P : c->probs) {
@@ -278,7 +283,7 @@ int build_launch(mlswe_ctx* c, int l) {
   int xrows = c->tune.x_rows, yrows = c->tune.y_rows;
   if (xrows <= 0) {
     xrows = 16;
-    while (xrows > 4 && count_tiles(0, xrows) < 8LL * c->ncu) xrows /= 2;
+    while (xrows > 4 && count_tiles(0, xrows) < 16LL * c->ncu) xrows /= 2;
   }
   if (yrows <= 0) {
     yrows = 128;
@@ -301,7 +306,10 @@ int build_launch(mlswe_ctx* c, int l) {
     if (l >= P.nlev) continue;
     LevelH& L = P.L[l];
     LL.li_first[pi] = (int)li.size();
-    li.push_back(LevelInfo{P.ctl0 + l, L.dx, L.dy});
+    LevelInfo info;
+    info.ctl = P.ctl0 + l; info.cnt = P.cnt; info.dx = L.dx; info.dy = L.dy;
+    info.x0 = (int)xt.size(); info.nx = 0; info.y0 = (int)yt.size(); info.ny = 0;  // y0: offset added below
+    li.push_back(info);
     if (L.boxes.empty()) continue;
     LL.fill_first[pi] = (int)fp[0].size();
     LL.fill_count[pi] = (int)L.boxes.size();
@@ -365,11 +373,18 @@ int build_launch(mlswe_ctx* c, int l) {
           cp[fpar * 2 + cpar].push_back(cc);
         }
     }
+    li.back().nx = (int)xt.size() - li.back().x0;
+    li.back().ny = (int)yt.size() - li.back().y0;
   }
   LL.nptch = (int)pd[0].size();
   LL.nxt = (int)xt.size();
   LL.nyt = (int)yt.size();
   LL.nli = (int)li.size();
+  LL.max_info_tiles = 0;
+  for (LevelInfo& info : li) {
+    info.y0 += LL.nxt;
+    LL.max_info_tiles = std::max(LL.max_info_tiles, info.nx + info.ny);
+  }
   int rc;
   int cap_pd1 = LL.cap_pd;
   if ((rc = ensure(c, &LL.pd[0], &LL.cap_pd, LL.nptch))) return rc;
@@ -384,6 +399,7 @@ int build_launch(mlswe_ctx* c, int l) {
   }
   LL.cap_fp = capf[0];
   if ((rc = ensure(c, &LL.li, &LL.cap_li, LL.nli))) return rc;
+  if ((rc = ensure(c, &LL.parts, &LL.cap_parts, LL.nxt + LL.nyt))) return rc;
   if (LL.nptch) {
     HIPCHK(c, hipMemcpyAsync(LL.pd[0], pd[0].data(), sizeof(PatchDev) * LL.nptch, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(LL.pd[1], pd[1].data(), sizeof(PatchDev) * LL.nptch, hipMemcpyHostToDevice, c->stream));
@@ -478,7 +494,7 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   if (nxt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
     hipLaunchKernelGGL(c->tune.fast ? k_sweep_x_fast : k_sweep_x, dim3(grid_of(nxt, sx, c->tune.grid_x)), dim3(256),
-                       0, c->stream, LL.pd[parity], LL.xt + xt0, nxt, sx, c->tickets);
+                       0, c->stream, LL.pd[parity], LL.xt + xt0, nxt, sx, c->tickets, LL.parts + xt0);
     HIPCHK(c, hipGetLastError());
     if (c->timing) {
       if ((rc = ev_begin(c, &e1))) return rc;
@@ -488,7 +504,7 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   if (nyt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
     hipLaunchKernelGGL(c->tune.fast ? k_sweep_y_fast : k_sweep_y, dim3(grid_of(nyt, sy, c->tune.grid_y)), dim3(256),
-                       0, c->stream, LL.pd[parity], LL.yt + yt0, nyt, sy, c->tickets + 1);
+                       0, c->stream, LL.pd[parity], LL.yt + yt0, nyt, sy, c->tickets + 1, LL.parts + LL.nxt + yt0);
     HIPCHK(c, hipGetLastError());
     if (c->timing) {
       if ((rc = ev_begin(c, &e1))) return rc;
@@ -533,8 +549,9 @@ int launch_after(mlswe_ctx* c, int l, int p0, int p1) {
     n = LL.li_first[p] + 1 - first;
   }
   if (n == 0) return MLSWE_OK;
-  hipLaunchKernelGGL(k_after_substep, dim3((n + 63) / 64), dim3(64), 0, c->stream, c->ctl, LL.li + first, n,
-                     c->cfg.cfl_max);
+  // one wave per problem suffices for a few tiles; a problem with many gets 16
+  hipLaunchKernelGGL(k_after_substep, dim3(n), dim3(LL.max_info_tiles > 256 ? 1024 : 64), 0, c->stream, c->ctl, c->cnt,
+                     LL.li + first, LL.parts, c->cfg.cfl_max);
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
@@ -782,8 +799,14 @@ int regrid_impl(mlswe_ctx* c, int p, const double* tau, int nbuf) {
 }
 
 int copy_state(mlswe_ctx* c, LevelH& L, int buf, const double* src, int where, bool to_dev, double* dst) {
-  const hipMemcpyKind kind = to_dev ? (where == MLSWE_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
-                                    : (where == MLSWE_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+  if (where == MLSWE_DEVICE) {  // device to device: one kernel for the six fields
+    hipLaunchKernelGGL(k_copy6, dim3(blocks((long long)L.nx * L.ny)), dim3(256), 0, c->stream, L.q[buf],
+                       (long long)L.pitch, (long long)L.plane, to_dev ? const_cast<double*>(src) : dst, L.nx, L.ny,
+                       to_dev ? 0 : 1);
+    HIPCHK(c, hipGetLastError());
+    return MLSWE_OK;
+  }
+  const hipMemcpyKind kind = to_dev ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
   for (int f = 0; f < 6; ++f) {
     double* lv = L.q[buf] + f * L.plane + idx(L, 0, 0);
     const size_t hrow = (size_t)L.nx * sizeof(double);
@@ -862,7 +885,7 @@ int mlswe_destroy(mlswe_ctx* c) {
       dfree(L.fraw); dfree(L.fout); dfree(L.bk);
     }
   for (LevelLaunch& LL : c->launch) {
-    dfree(LL.pd[0]); dfree(LL.pd[1]); dfree(LL.xt); dfree(LL.yt); dfree(LL.li);
+    dfree(LL.pd[0]); dfree(LL.pd[1]); dfree(LL.xt); dfree(LL.yt); dfree(LL.li); dfree(LL.parts);
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
   }
   dfree(c->ctl); dfree(c->cnt); dfree(c->theta); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
@@ -1437,7 +1460,6 @@ static int check_single(mlswe_ctx* c, int p) {
   return MLSWE_OK;
 }
 
-static unsigned blocks(long long n) { return (unsigned)((n + 255) / 256); }
 
 extern "C" int mlswe_run_fixed(mlswe_ctx* c, int p, int n, const double* dts) {
   if (!c) return MLSWE_EINVAL;
@@ -1486,10 +1508,8 @@ extern "C" int mlswe_adjoint_step(mlswe_ctx* c, int p, const double* q_n, const 
   if (k0 < 0) return fail(c, MLSWE_ESTATE, "problem %d has no patch", p);
   if ((rc = launch_sweeps(c, 0, L.cur, LL.xr[k0].first, LL.xr[k0].second, 0, 0))) return rc;
   // adjoint of the step's output into the level layout
-  for (int f = 0; f < 6; ++f)
-    HIPCHK(c, hipMemcpy2DAsync(A.lam1 + f * L.plane + idx(L, 0, 0), L.pitch * sizeof(double),
-                               lam_np1 + (size_t)f * L.nx * L.ny, (size_t)L.nx * sizeof(double),
-                               (size_t)L.nx * sizeof(double), L.ny, hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(k_copy6, dim3(blocks((long long)L.nx * L.ny)), dim3(256), 0, c->stream, A.lam1, (long long)L.pitch,
+                     (long long)L.plane, const_cast<double*>(lam_np1), L.nx, L.ny, 0);
   AdjView V;
   std::memset(&V, 0, sizeof V);
   V.B = L.B; V.cL = A.cL; V.cR = A.cR; V.plane = L.plane; V.P = P.P; V.status = A.status;
@@ -1512,8 +1532,6 @@ extern "C" int mlswe_adjoint_step(mlswe_ctx* c, int p, const double* q_n, const 
   F.pitch = L.pitch; F.plane = L.plane; F.nx = L.nx; F.ny = L.ny;
   hipLaunchKernelGGL(k_adj_fold, dim3(blocks((long long)L.nx * L.ny)), dim3(256), 0, c->stream, F);
   HIPCHK(c, hipGetLastError());
-  // the recomputed x-sweep must not leave speeds behind for the next real step
-  HIPCHK(c, hipMemsetAsync(&c->ctl[P.ctl0].step_smax[0], 0, 2 * sizeof(unsigned long long), c->stream));
   int st = 0;
   HIPCHK(c, hipMemcpyAsync(&st, A.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -84,21 +84,21 @@ __device__ __forceinline__ int wave_isum(int v) {
   return v;
 }
 
-__device__ __forceinline__ void flush_counts(Counters* cnt, LevelCtl* ctl, int axis, double smax, int hyp,
-                                             const FixCount& K, int lane) {
-  double sm = wave_max(smax);
-  int h = wave_isum(hyp);
-  int nc = wave_isum(K.nclip);
-  int rp = wave_isum(K.repair);
-  double c1 = wave_sum(K.clip1);
-  double c2 = wave_sum(K.clip2);
+__device__ __forceinline__ void flush_part(TilePart* part, double smax, int hyp, const FixCount& K, int lane) {
+  const double sm = wave_max(smax);
+  const int h = wave_isum(hyp);
+  const int nc = wave_isum(K.nclip);
+  const int rp = wave_isum(K.repair);
+  const double c1 = wave_sum(K.clip1);
+  const double c2 = wave_sum(K.clip2);
   if (lane == 0) {
-    atomicMax(&ctl->step_smax[axis], (unsigned long long)__double_as_longlong(sm));
-    if (h) atomicAdd(&cnt->hyp, (unsigned long long)h);
-    if (nc) atomicAdd(&cnt->nclip, (unsigned long long)nc);
-    if (rp) atomicAdd(&cnt->repair, (unsigned long long)rp);
-    if (c1 != 0.0) atomicAdd(&cnt->clip1, c1);
-    if (c2 != 0.0) atomicAdd(&cnt->clip2, c2);
+    part->smax = sm;
+    part->clip1 = c1;
+    part->clip2 = c2;
+    part->hyp = (unsigned)h;
+    part->nclip = (unsigned)nc;
+    part->repair = (unsigned)rp;
+    part->pad = 0u;
   }
 }
 
