@@ -63,7 +63,7 @@ typedef struct mlswe_config {
 
 /* Launch shape of the two sweep kernels.  rows: rows of a patch per x-sweep
  * wave / per y-sweep wave (a y wave marches its rows with the last edge in
- * registers); 0 chooses them per level: 16 (x) and 128 (y), halved while the
+ * registers); 0 chooses them per level: 32 (x) and 128 (y), halved while the
  * level's tiles over all problems would not fill the device, down to 4 and 8.  sched: 0 one wave per tile, 1 persistent waves striding over
  * the tile list, 2 persistent waves taking tiles from an atomic ticket.
  * grid: persistent blocks of four waves per compute unit.  fast: 1 selects the

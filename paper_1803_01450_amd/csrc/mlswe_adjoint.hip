@@ -114,7 +114,10 @@ __device__ __forceinline__ void cell_reverse(const CellX& c, const CellBar& b, d
   out[3] = h2; out[4] = m2 + b.m2; out[5] = t2 + b.t2; out[6] = Bb;
 }
 
-// Solves M^T y = r (4 x 4) by elimination with partial pivoting.
+// Solves M^T y = r (4 x 4) by elimination with partial pivoting.  Rows are
+// exchanged by compare-and-swap against the pivot row with fixed indices (the
+// largest entry of the column ends up in the pivot row), so the matrix stays in
+// registers.
 __device__ __forceinline__ void solve4T(const double R[4][4], const double r[4], double y[4]) {
   double a[4][5];
 #pragma unroll
@@ -125,14 +128,15 @@ __device__ __forceinline__ void solve4T(const double R[4][4], const double r[4],
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    int piv = k;
-    double best = fabs(a[k][k]);
 #pragma unroll
-    for (int i = k + 1; i < 4; ++i)
-      if (fabs(a[i][k]) > best) { best = fabs(a[i][k]); piv = i; }
-    if (piv != k) {
+    for (int i = k + 1; i < 4; ++i) {
+      const bool sw = fabs(a[i][k]) > fabs(a[k][k]);
 #pragma unroll
-      for (int j = 0; j < 5; ++j) { double t = a[k][j]; a[k][j] = a[piv][j]; a[piv][j] = t; }
+      for (int j = 0; j < 5; ++j) {
+        const double t = a[k][j];
+        a[k][j] = sw ? a[i][j] : t;
+        a[i][j] = sw ? t : a[i][j];
+      }
     }
     const double ik = 1.0 / a[k][k];
 #pragma unroll
@@ -295,6 +299,23 @@ __device__ __forceinline__ void riemann_reverse(const PhysParams& P, const CellX
 
 __device__ __forceinline__ bool all_wet(const CellX& c) { return c.wet1 && c.wet2; }
 
+// Adjoint of an edge's waves in factored form (strengths A, C, speeds s,
+// transverse velocities v1, v2, shear jumps z4, z5).  add_zbar adds the
+// adjoint X of the six components of wave p, Z = (A, A s, A v1, C, C s, C v2)
+// (shear waves: the single component z4 or z5), pulled back to the factors.
+struct WaveBar {
+  double Ab[4], Cb[4], sb[6], v1b, v2b, z4b, z5b;
+};
+__device__ __forceinline__ void add_zbar(WaveBar& B, const EdgeW& W, int p, const double X[6]) {
+  if (p == 4) { B.z4b += X[2]; return; }
+  if (p == 5) { B.z5b += X[5]; return; }
+  B.Ab[p] += X[0] + X[1] * W.s[p] + X[2] * W.v1;
+  B.Cb[p] += X[3] + X[4] * W.s[p] + X[5] * W.v2;
+  B.sb[p] += X[1] * W.A[p] + X[4] * W.C[p];
+  B.v1b += X[2] * W.A[p];
+  B.v2b += X[5] * W.C[p];
+}
+
 }  // namespace
 
 // One thread per edge e in [-1, n + 1] of every line.
@@ -324,12 +345,12 @@ __global__ __launch_bounds__(256) void k_adj_edges(AdjView V) {
   adj_lam(V, line, e - 1, lm1);
   adj_lam(V, line, e, l0);
   adj_lam(V, line, e + 1, lp1);
-  double zb[6][6];
+  WaveBar Bw;
 #pragma unroll
-  for (int p = 0; p < 6; ++p)
+  for (int p = 0; p < 4; ++p) { Bw.Ab[p] = 0.0; Bw.Cb[p] = 0.0; }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) zb[p][c] = 0.0;
-  double sbx[6] = {0, 0, 0, 0, 0, 0};
+  for (int p = 0; p < 6; ++p) Bw.sb[p] = 0.0;
+  Bw.v1b = 0.0; Bw.v2b = 0.0; Bw.z4b = 0.0; Bw.z5b = 0.0;
   double dd[6], ddm[6], ddp[6], dotm[6], dotp[6];
 #pragma unroll
   for (int p = 0; p < 6; ++p) {
@@ -357,22 +378,24 @@ __global__ __launch_bounds__(256) void k_adj_edges(AdjView V) {
       double z[6], u[6];
       wvec(W, p, z);
       LimP Lm = lim_of(W, p, dd[p], dotm[p], dotp[p], nu);
-      double coefb = 0.0;
+      double coefb = 0.0, X[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        zb[p][c] += wm * amb[c] + wp * apb[c] + Lm.K * Lm.phi * Fb[c];
+        X[c] = wm * amb[c] + wp * apb[c] + Lm.K * Lm.phi * Fb[c];
         coefb += Fb[c] * z[c];
       }
+      add_zbar(Bw, W, p, X);
       if (Lm.on) {
         const double sgn = sv > 0.0 ? 1.0 : -1.0;
-        sbx[p] += coefb * Lm.phi * Lm.sg * (-nu * sgn);
+        Bw.sb[p] += coefb * Lm.phi * Lm.sg * (-nu * sgn);
         const double thb = coefb * Lm.K * Lm.dphi;
         const double dnb = thb / Lm.dd;
         const double ddb = -thb * Lm.th / Lm.dd;
         const EdgeW& Up = sv > 0.0 ? Wm : Wp;
         wvec(Up, p, u);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) zb[p][c] += dnb * u[c] + 2.0 * ddb * z[c];
+        for (int c = 0; c < 6; ++c) X[c] = dnb * u[c] + 2.0 * ddb * z[c];
+        add_zbar(Bw, W, p, X);
       }
     }
   }
@@ -392,8 +415,10 @@ __global__ __launch_bounds__(256) void k_adj_edges(AdjView V) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) coefb += Fb[c] * z[c];
       const double dnb = coefb * Lm.K * Lm.dphi / Lm.dd;
+      double X[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) zb[p][c] += dnb * z[c];
+      for (int c = 0; c < 6; ++c) X[c] = dnb * z[c];
+      add_zbar(Bw, W, p, X);
     }
   }
   // correction flux of edge e+1 whose limiter looks at edge e (right-going waves)
@@ -412,28 +437,16 @@ __global__ __launch_bounds__(256) void k_adj_edges(AdjView V) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) coefb += Fb[c] * z[c];
       const double dnb = coefb * Lm.K * Lm.dphi / Lm.dd;
+      double X[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) zb[p][c] += dnb * z[c];
+      for (int c = 0; c < 6; ++c) X[c] = dnb * z[c];
+      add_zbar(Bw, W, p, X);
     }
   }
-  // factored form of the wave adjoint
-  double Ab[4], Cb[4], sb[6];
-  double v1b = 0.0, v2b = 0.0;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    Ab[p] = zb[p][0] + zb[p][1] * W.s[p] + zb[p][2] * W.v1;
-    Cb[p] = zb[p][3] + zb[p][4] * W.s[p] + zb[p][5] * W.v2;
-    sb[p] = sbx[p] + zb[p][1] * W.A[p] + zb[p][4] * W.C[p];
-    v1b += zb[p][2] * W.A[p];
-    v2b += zb[p][5] * W.C[p];
-  }
-  sb[4] = sbx[4];
-  sb[5] = sbx[5];
-  const double z4b = zb[4][2], z5b = zb[5][5];
   CellBar Lb, Rb;
   zero_cb(Lb);
   zero_cb(Rb);
-  riemann_reverse(V.P, Cm1, C0, Ab, Cb, sb, v1b, v2b, z4b, z5b, Lb, Rb);
+  riemann_reverse(V.P, Cm1, C0, Bw.Ab, Bw.Cb, Bw.sb, Bw.v1b, Bw.v2b, Bw.z4b, Bw.z5b, Lb, Rb);
   double ol[7], orr[7];
   cell_reverse(Cm1, Lb, ol);
   cell_reverse(C0, Rb, orr);

@@ -207,15 +207,27 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double sx = 0.0, sy = 0.0, c1 = 0.0, c2 = 0.0;
   unsigned long long h = 0, nc = 0, rp = 0;
-  for (int k = threadIdx.x; k < I.nx + I.ny; k += blockDim.x) {
-    const TilePart T = parts[k < I.nx ? I.x0 + k : I.y0 + (k - I.nx)];
-    if (k < I.nx) sx = T.smax > sx ? T.smax : sx;
-    else sy = T.smax > sy ? T.smax : sy;
-    c1 += T.clip1;
-    c2 += T.clip2;
-    h += T.hyp;
-    nc += T.nclip;
-    rp += T.repair;
+  // four independent loads in flight per pass (the passes are latency bound)
+  const int ntot = I.nx + I.ny, step = blockDim.x;
+  for (int k0 = threadIdx.x; k0 < ntot; k0 += 4 * step) {
+    TilePart T[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * step;
+      if (k < ntot) T[u] = parts[k < I.nx ? I.x0 + k : I.y0 + (k - I.nx)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * step;
+      if (k >= ntot) continue;
+      if (k < I.nx) sx = T[u].smax > sx ? T[u].smax : sx;
+      else sy = T[u].smax > sy ? T[u].smax : sy;
+      c1 += T[u].clip1;
+      c2 += T[u].clip2;
+      h += T[u].hyp;
+      nc += T[u].nclip;
+      rp += T[u].repair;
+    }
   }
   sx = wave_max(sx);
   sy = wave_max(sy);

@@ -264,7 +264,7 @@ std::vector<Box> cluster_tiles(const LevelH& C, int r, const std::vector<unsigne
 int build_launch(mlswe_ctx* c, int l) {
   LevelLaunch& LL = c->launch[l];
   if (!LL.dirty) return MLSWE_OK;
-  // Rows per sweep wave: the tuned value, or (0) the largest of 16 (x) / 128 (y)
+  // Rows per sweep wave: the tuned value, or (0) the largest of 32 (x) / 128 (y)
   // halved while the level's tiles, over every problem, would not fill the
   // device with room to balance (x: two waves per SIMD, four rounds; y: one
   // wave per SIMD, one round; four SIMDs per compute unit); never below 4 (x),
@@ -282,7 +282,7 @@ int build_launch(mlswe_ctx* c, int l) {
   };
   int xrows = c->tune.x_rows, yrows = c->tune.y_rows;
   if (xrows <= 0) {
-    xrows = 16;
+    xrows = 32;
     while (xrows > 4 && count_tiles(0, xrows) < 16LL * c->ncu) xrows /= 2;
   }
   if (yrows <= 0) {
