@@ -10,6 +10,8 @@ namespace mlswe {
 
 #define MLSWE_KX k_sweep_x
 #define MLSWE_KY k_sweep_y
+#define MLSWE_KX1 k_sweep_x1
+#define MLSWE_KY1 k_sweep_y1
 #include "mlswe_sweeps.inc"
 
 __global__ void k_zero_u32(unsigned* p, int n) {

@@ -173,6 +173,14 @@ __global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __r
                           unsigned* ticket, TilePart* parts);
 __global__ void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles, int sched,
                           unsigned* ticket, TilePart* parts);
+__global__ void k_sweep_x1(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles,
+                           TilePart* parts);
+__global__ void k_sweep_y1(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
+                           TilePart* parts);
+__global__ void k_sweep_x1_fast(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles,
+                                TilePart* parts);
+__global__ void k_sweep_y1_fast(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
+                                TilePart* parts);
 __global__ void k_sweep_x_fast(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles,
                                int sched, unsigned* ticket, TilePart* parts);
 __global__ void k_sweep_y_fast(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,

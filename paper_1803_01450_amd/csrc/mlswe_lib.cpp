@@ -493,8 +493,12 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->tickets, 2);
   if (nxt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
-    hipLaunchKernelGGL(c->tune.fast ? k_sweep_x_fast : k_sweep_x, dim3(grid_of(nxt, sx, c->tune.grid_x)), dim3(256),
-                       0, c->stream, LL.pd[parity], LL.xt + xt0, nxt, sx, c->tickets, LL.parts + xt0);
+    if (sx == 0 && !c->sig_on)  // one wave per tile, no signature: the lean kernels
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_x1_fast : k_sweep_x1, dim3(grid_of(nxt, 0, 0)), dim3(256), 0,
+                         c->stream, LL.pd[parity], LL.xt + xt0, nxt, LL.parts + xt0);
+    else
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_x_fast : k_sweep_x, dim3(grid_of(nxt, sx, c->tune.grid_x)), dim3(256),
+                         0, c->stream, LL.pd[parity], LL.xt + xt0, nxt, sx, c->tickets, LL.parts + xt0);
     HIPCHK(c, hipGetLastError());
     if (c->timing) {
       if ((rc = ev_begin(c, &e1))) return rc;
@@ -503,8 +507,12 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   }
   if (nyt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
-    hipLaunchKernelGGL(c->tune.fast ? k_sweep_y_fast : k_sweep_y, dim3(grid_of(nyt, sy, c->tune.grid_y)), dim3(256),
-                       0, c->stream, LL.pd[parity], LL.yt + yt0, nyt, sy, c->tickets + 1, LL.parts + LL.nxt + yt0);
+    if (sy == 0 && !c->sig_on)
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_y1_fast : k_sweep_y1, dim3(grid_of(nyt, 0, 0)), dim3(256), 0,
+                         c->stream, LL.pd[parity], LL.yt + yt0, nyt, LL.parts + LL.nxt + yt0);
+    else
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_y_fast : k_sweep_y, dim3(grid_of(nyt, sy, c->tune.grid_y)), dim3(256),
+                         0, c->stream, LL.pd[parity], LL.yt + yt0, nyt, sy, c->tickets + 1, LL.parts + LL.nxt + yt0);
     HIPCHK(c, hipGetLastError());
     if (c->timing) {
       if ((rc = ev_begin(c, &e1))) return rc;

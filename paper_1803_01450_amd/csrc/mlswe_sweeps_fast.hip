@@ -10,5 +10,7 @@
 namespace mlswe {
 #define MLSWE_KX k_sweep_x_fast
 #define MLSWE_KY k_sweep_y_fast
+#define MLSWE_KX1 k_sweep_x1_fast
+#define MLSWE_KY1 k_sweep_y1_fast
 #include "mlswe_sweeps.inc"
 }  // namespace mlswe
