@@ -163,6 +163,8 @@ def bench_adjoint(nsteps, stream):
             "steps": nsteps, "cells": 1024 * 1024, "loss": float(loss.item())}
 
 
+# the kernels the timed steps launch (one wave per tile, no branch signature)
+LAUNCHED = {"x_sweep": "k_sweep_x1", "y_sweep": "k_sweep_y1"}
 # the sources the sweep kernels are compiled from
 SWEEP_SOURCES = ("mlswe_kernels.hip", "mlswe_sweeps_fast.hip", "mlswe_sweeps.inc", "mlswe_wave.hpp",
                  "mlswe_device.hpp", "mlswe_kernels.hpp")
@@ -185,7 +187,7 @@ def profiled_traffic(kernel):
     for line in open(path):
         if line.startswith("kernel_source_sha256:"):
             sha = line.split(":", 1)[1].strip()
-        if line.startswith("traffic_bytes_per_launch k_%s:" % kernel):
+        if line.startswith("traffic_bytes_per_launch %s:" % LAUNCHED[kernel]):
             val = float(line.split(":", 1)[1])
     if sha != kernel_source_sha() or val is None:
         return None
