@@ -210,12 +210,15 @@ int mlswe_kernel_times(mlswe_ctx* ctx, double* ms_out /*[2]*/, int64_t* launches
 /* ---------------------------------------------------------------- adjoint
  * Differentiation of a fixed-grid run with a frozen dt sequence, for problems
  * with one level whose states keep both layers wet (the solve's reverse is the
- * transpose of its coupled branch; a dry layer anywhere makes the call fail with
- * MLSWE_ESTATE).  All arrays are device pointers of the context's GPU in the
- * layout of mlswe_set_state; the caller owns them. */
+ * transpose of its coupled branch).  A dry layer met by an adjoint step is
+ * reported, without a host wait in the step itself, as MLSWE_ESTATE by a later
+ * mlswe_adjoint_step of the problem or, at the latest, by
+ * mlswe_param_map_adjoint, which closes the chain.  All arrays are device
+ * pointers of the context's GPU in the layout of mlswe_set_state; the caller
+ * owns them. */
 
-/* n steps of problem p's level 0 with the given substeps (host array [n]),
- * without any host round trip. */
+/* n steps of problem p's level 0 with the given substeps (host array [n], read
+ * before the call returns), without any host round trip. */
 int mlswe_run_fixed(mlswe_ctx* ctx, int p, int n, const double* dts);
 
 /* lam_n = (dQ_{n+1}/dQ_n)^T lam_np1 and B_bar += (dQ_{n+1}/dB)^T lam_np1 for the

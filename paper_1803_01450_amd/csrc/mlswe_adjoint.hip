@@ -584,6 +584,6 @@ __global__ __launch_bounds__(256) void k_gauge(Gauge Gd) {
   if (threadIdx.x == 0 && Gd.loss) *Gd.loss += part[0];
 }
 
-__global__ void k_set_dt(LevelCtl* ctl, const double* __restrict__ dts, int k) { ctl->dt = dts[k]; }
+__global__ void k_set_dt(LevelCtl* ctl, double dt) { ctl->dt = dt; }
 
 }  // namespace mlswe

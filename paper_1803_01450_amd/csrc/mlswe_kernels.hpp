@@ -167,7 +167,7 @@ __global__ void k_adj_fold(AdjFold F);
 __global__ void k_param_map(ParamMap M);
 __global__ void k_param_map_adj(ParamMap M, const double* __restrict__ lam0, double* eta1_bar, double* B_bar);
 __global__ void k_gauge(Gauge G);
-__global__ void k_set_dt(LevelCtl* ctl, const double* __restrict__ dts, int k);
+__global__ void k_set_dt(LevelCtl* ctl, double dt);
 
 __global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles, int sched,
                           unsigned* ticket, TilePart* parts);

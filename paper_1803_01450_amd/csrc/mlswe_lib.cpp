@@ -52,9 +52,9 @@ struct AdjBuf {
   double* cR = nullptr;
   double* Bbx = nullptr;
   double* Bby = nullptr;
-  int* status = nullptr;
-  double* dts = nullptr;
-  int dts_cap = 0;
+  int* status = nullptr;        // device: set by the edge kernel on a non-wet edge (sticky)
+  int* status_host = nullptr;   // pinned copy of status, written after each adjoint step
+  hipEvent_t status_ev = nullptr;
 };
 
 struct ProblemH {
@@ -884,7 +884,9 @@ int mlswe_destroy(mlswe_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (ProblemH& P : c->probs) {
     dfree(P.adj.lam1); dfree(P.adj.lamS); dfree(P.adj.lamG); dfree(P.adj.cL); dfree(P.adj.cR);
-    dfree(P.adj.Bbx); dfree(P.adj.Bby); dfree(P.adj.status); dfree(P.adj.dts);
+    dfree(P.adj.Bbx); dfree(P.adj.Bby); dfree(P.adj.status);
+    if (P.adj.status_host) (void)hipHostFree(P.adj.status_host);
+    if (P.adj.status_ev) (void)hipEventDestroy(P.adj.status_ev);
   }
   for (ProblemH& P : c->probs)
     for (int l = 0; l < P.nlev; ++l) {
@@ -1455,6 +1457,9 @@ static int ensure_adj(mlswe_ctx* c, ProblemH& P) {
   HIPCHK(c, hipMemsetAsync(A.Bbx, 0, pb, c->stream));
   HIPCHK(c, hipMemsetAsync(A.Bby, 0, pb, c->stream));
   HIPCHK(c, hipMemsetAsync(A.status, 0, sizeof(int), c->stream));
+  HIPCHK(c, hipHostMalloc((void**)&A.status_host, sizeof(int), hipHostMallocDefault));
+  *A.status_host = 0;
+  HIPCHK(c, hipEventCreateWithFlags(&A.status_ev, hipEventDisableTiming));
   return MLSWE_OK;
 }
 
@@ -1478,17 +1483,9 @@ extern "C" int mlswe_run_fixed(mlswe_ctx* c, int p, int n, const double* dts) {
   if (!P.state) return fail(c, MLSWE_ESTATE, "set the state first");
   for (int k = 0; k < n; ++k)
     if (!(dts[k] > 0.0) || !std::isfinite(dts[k])) return fail(c, MLSWE_EINVAL, "dt[%d] must be positive", k);
-  if (n > P.adj.dts_cap) {
-    dfree(P.adj.dts);
-    P.adj.dts = nullptr;
-    if ((rc = dalloc(c, (void**)&P.adj.dts, sizeof(double) * (size_t)n))) return rc;
-    P.adj.dts_cap = n;
-  }
-  if (n == 0) return MLSWE_OK;
-  HIPCHK(c, hipMemcpyAsync(P.adj.dts, dts, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // each step's dt travels as a kernel argument: no copy, no host wait
   for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, c->stream, c->ctl + P.ctl0, P.adj.dts, k);
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, c->stream, c->ctl + P.ctl0, dts[k]);
     if ((rc = substep(c, 0, p, p + 1, 0.0, false))) return rc;
   }
   return MLSWE_OK;
@@ -1504,9 +1501,15 @@ extern "C" int mlswe_adjoint_step(mlswe_ctx* c, int p, const double* q_n, const 
   LevelH& L = P.L[0];
   if ((rc = ensure_adj(c, P))) return rc;
   AdjBuf& A = P.adj;
+  // a non-wet edge met by an earlier step (its status copy has landed)
+  if (hipEventQuery(A.status_ev) == hipSuccess && *A.status_host) {
+    *A.status_host = 0;
+    HIPCHK(c, hipMemsetAsync(A.status, 0, sizeof(int), c->stream));
+    return fail(c, MLSWE_ESTATE, "adjoint needs both layers wet at every edge");
+  }
   // forward recomputation: state, walls, x-sweep
   if ((rc = copy_state(c, L, L.cur, q_n, MLSWE_DEVICE, true, nullptr))) return rc;
-  HIPCHK(c, hipMemcpyAsync(&c->ctl[P.ctl0].dt, &dt, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, c->stream, c->ctl + P.ctl0, dt);
   if ((rc = build_launch(c, 0))) return rc;
   if ((rc = launch_fill(c, 0, p, p + 1, 0.0))) return rc;
   LevelLaunch& LL = c->launch[0];
@@ -1540,13 +1543,10 @@ extern "C" int mlswe_adjoint_step(mlswe_ctx* c, int p, const double* q_n, const 
   F.pitch = L.pitch; F.plane = L.plane; F.nx = L.nx; F.ny = L.ny;
   hipLaunchKernelGGL(k_adj_fold, dim3(blocks((long long)L.nx * L.ny)), dim3(256), 0, c->stream, F);
   HIPCHK(c, hipGetLastError());
-  int st = 0;
-  HIPCHK(c, hipMemcpyAsync(&st, A.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (st) {
-    HIPCHK(c, hipMemsetAsync(A.status, 0, sizeof(int), c->stream));
-    return fail(c, MLSWE_ESTATE, "adjoint needs both layers wet at every edge");
-  }
+  // the status travels back without a host wait; a later adjoint call or
+  // mlswe_param_map_adjoint reports it
+  HIPCHK(c, hipMemcpyAsync(A.status_host, A.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipEventRecord(A.status_ev, c->stream));
   return MLSWE_OK;
 }
 
@@ -1591,6 +1591,17 @@ extern "C" int mlswe_param_map_adjoint(mlswe_ctx* c, int p, const double* eta1_0
   if (rc) return rc;
   if (!eta1_0 || !lam0 || !eta1_bar || !B_bar) return fail(c, MLSWE_EINVAL, "null pointer");
   const LevelH& L = c->probs[p].L[0];
+  AdjBuf& A = c->probs[p].adj;
+  if (A.status) {  // the adjoint steps so far: any non-wet edge fails the chain
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int st = 0;
+    HIPCHK(c, hipMemcpy(&st, A.status, sizeof(int), hipMemcpyDeviceToHost));
+    if (st) {
+      *A.status_host = 0;
+      HIPCHK(c, hipMemset(A.status, 0, sizeof(int)));
+      return fail(c, MLSWE_ESTATE, "adjoint needs both layers wet at every edge");
+    }
+  }
   ParamMap M;
   M.eta1 = eta1_0; M.B = L.B; M.q = nullptr; M.pitch = L.pitch; M.nx = L.nx; M.ny = L.ny;
   M.eta2 = eta2_0; M.hdry = c->probs[p].P.hdry;

@@ -134,3 +134,30 @@ def test_adjoint_full_size_central_differences():
     assert np.median(rels) <= 1e-3
     assert rels.max() <= 5e-2
     S.close()
+
+
+def test_adjoint_reports_a_dry_layer():
+    """A bathymetry rising above the flat interface leaves the lower layer dry
+    there: the adjoint steps record the non-wet edge without a host wait and the
+    chain fails with MLSWE_ESTATE by the time it is closed."""
+    import torch
+    from paper_1803_01450_amd import binding
+    from paper_1803_01450_amd.adjoint import GaugeMisfit
+    say("case: adjoint 64x64 with a dry lower layer, error reported")
+    n, nsteps = 64, 20
+    c, dts, tg, S, prob = make(n, nsteps)
+    B = c["B"].copy()
+    B[20:30, 20:30] = c["eta2"] + 10.0   # bottom above the interface
+    S.set_bathymetry(prob.p, B)
+    e = torch.from_numpy(c["eta1"].copy()).cuda().requires_grad_(True)
+    Bt = torch.from_numpy(B).cuda().requires_grad_(True)
+    loss = GaugeMisfit.apply(e, Bt, prob)
+    with pytest.raises(binding.MlsweError) as err:
+        loss.backward()
+    torch.cuda.synchronize()
+    assert err.value.code == binding.ESTATE
+    # the context stays usable: a wet problem differentiates afterwards
+    S.set_bathymetry(prob.p, c["B"])
+    L, ge, gB = gradients(c, prob)
+    assert np.isfinite(L) and np.isfinite(ge).all() and np.isfinite(gB).all()
+    S.close()
