@@ -109,14 +109,13 @@ __global__ __launch_bounds__(256) void k_ghost_fill(const FillPatch* __restrict_
 
 // Regrid fill: every cell of a new fine patch not covered by an old patch is
 // refined from the coarser level's current state.
-__global__ __launch_bounds__(256) void k_refine_new(const FillPatch* __restrict__ fills,
-                                                    const unsigned char* __restrict__ old_mask) {
+__global__ __launch_bounds__(256) void k_refine_new(const FillPatch* __restrict__ fills) {
   const FillPatch& F = fills[blockIdx.y];
   const int n = F.bnx * F.bny;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int i = F.ilo + k % F.bnx, j = F.jlo + k / F.bnx;
-  if (old_mask[cidx(F.pitch, i, j)]) return;
+  if (F.mask_old[cidx(F.pitch, i, j)]) return;
   bool rep = refine_cell_into(F, i, j, 0.0, F.q, F.plane);
   if (rep && F.cnt) atomicAdd(&F.cnt->repair, 1ull);
 }
@@ -153,10 +152,12 @@ __device__ __forceinline__ void mirror_ij(int nx, int ny, int& i, int& j) {
   if (j < 0) j = -1 - j; else if (j >= ny) j = 2 * ny - 1 - j;
 }
 
-__global__ __launch_bounds__(256) void k_flag_raw(FlagLevel F) {
+// Flags of level blockIdx.z of a list (one launch for many problems).
+__global__ __launch_bounds__(256) void k_flag_raw(const FlagLevel* __restrict__ Fs) {
+  const FlagLevel F = Fs[blockIdx.z];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
-  if (i >= F.nx) return;
+  if (i >= F.nx || j >= F.ny) return;
   auto ok = [&](int a, int b) {
     mirror_ij(F.nx, F.ny, a, b);
     const long long id = cidx(F.pitch, a, b);
@@ -177,10 +178,11 @@ __global__ __launch_bounds__(256) void k_flag_raw(FlagLevel F) {
   F.raw[(long long)j * F.nx + i] = f;
 }
 
-__global__ __launch_bounds__(256) void k_flag_dilate(FlagLevel F) {
+__global__ __launch_bounds__(256) void k_flag_dilate(const FlagLevel* __restrict__ Fs) {
+  const FlagLevel F = Fs[blockIdx.z];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
-  if (i >= F.nx) return;
+  if (i >= F.nx || j >= F.ny) return;
   unsigned char f = 0;
   if (F.mask[cidx(F.pitch, i, j)]) {
     const int j0 = j - F.nbuf < 0 ? 0 : j - F.nbuf, j1 = j + F.nbuf > F.ny - 1 ? F.ny - 1 : j + F.nbuf;
@@ -193,8 +195,6 @@ __global__ __launch_bounds__(256) void k_flag_dilate(FlagLevel F) {
 }
 
 // ---------------------------------------------------------------- time step
-// After a level substep: Courant check with this substep's speeds, fold them
-// into the coarse-step maximum, clear them.
 // After a substep: one block per (problem, level) reduces the partials of that
 // problem's x and y tiles (each wave a strided share, then across the waves),
 // then records the largest speeds, the Courant number and the CFL status, and
@@ -381,6 +381,28 @@ __global__ __launch_bounds__(256) void k_nan_uncovered(double* q, const unsigned
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
 #pragma unroll
   for (int f = 0; f < 6; ++f) q[f * pu + t] = nan;
+}
+
+// Byte runs in one launch (block row y: run y), copied or filled.
+__global__ __launch_bounds__(256) void k_byte_segs(const ByteSeg* __restrict__ segs) {
+  const ByteSeg S = segs[blockIdx.y];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < S.n; k += (long long)gridDim.x * blockDim.x)
+    S.dst[k] = S.src ? S.src[k] : (unsigned char)S.value;
+}
+
+// Coverage of patch boxes (block row y: box y) set to 1.
+__global__ __launch_bounds__(256) void k_mask_boxes(const MaskBox* __restrict__ boxes) {
+  const MaskBox M = boxes[blockIdx.y];
+  const int n = M.nx * M.ny;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    M.mask[cidx(M.pitch, M.ilo + k % M.nx, M.jlo + k / M.nx)] = 1;
+}
+
+// Many contiguous copies in one launch: block row y copies segment y.
+__global__ __launch_bounds__(256) void k_copy_segs(const CopySeg* __restrict__ segs) {
+  const CopySeg S = segs[blockIdx.y];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < S.n; k += (long long)gridDim.x * blockDim.x)
+    S.dst[k] = S.src[k];
 }
 
 // Six fields between a level array (interior cells, padded rows) and the

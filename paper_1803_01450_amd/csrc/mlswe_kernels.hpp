@@ -50,6 +50,7 @@ struct FillPatch {
   double* q;                  // fine level buffer written
   const double* B;            // fine bathymetry
   const unsigned char* mask;  // fine coverage
+  const unsigned char* mask_old;  // coverage before a regrid (new-cell fill only)
   const double* qco;          // coarse state at the start of its step
   const double* qcn;          // coarse state at the end of its step
   const double* Bc;
@@ -187,16 +188,38 @@ __global__ void k_sweep_y_fast(const PatchDev* __restrict__ patches, const YTile
                                int sched, unsigned* ticket, TilePart* parts);
 __global__ void k_zero_u32(unsigned* p, int n);
 __global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass);
-__global__ void k_refine_new(const FillPatch* __restrict__ fills, const unsigned char* __restrict__ old_mask);
+__global__ void k_refine_new(const FillPatch* __restrict__ fills);
 __global__ void k_coarsen(const CoarsenPatch* __restrict__ cps);
-__global__ void k_flag_raw(FlagLevel F);
-__global__ void k_flag_dilate(FlagLevel F);
+__global__ void k_flag_raw(const FlagLevel* __restrict__ Fs);
+__global__ void k_flag_dilate(const FlagLevel* __restrict__ Fs);
 __global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, const TilePart* parts,
                                 double cflmax);
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
 __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial);
 __global__ void k_set_theta(double* th, double v);
 __global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);
+// A contiguous run of doubles to copy (one row range of one field plane).
+struct CopySeg {
+  const double* src;
+  double* dst;
+  long long n;
+};
+__global__ void k_copy_segs(const CopySeg* __restrict__ segs);
+// Byte runs: copied (src set) or filled with a value (src null).
+struct ByteSeg {
+  const unsigned char* src;
+  unsigned char* dst;
+  long long n;
+  int value;
+};
+__global__ void k_byte_segs(const ByteSeg* __restrict__ segs);
+// One patch box of a level's coverage mask, set to 1.
+struct MaskBox {
+  unsigned char* mask;
+  long long pitch;
+  int ilo, jlo, nx, ny;
+};
+__global__ void k_mask_boxes(const MaskBox* __restrict__ boxes);
 __global__ void k_copy6(double* lv, long long pitch, long long plane, double* cq, int nx, int ny, int dir);
 __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob);
 __global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const double* __restrict__ dt0, int nprob);

@@ -147,6 +147,18 @@ struct mlswe_ctx {
   int bk_cap = 0, cbk_cap = 0;
   double* dt0_d = nullptr;
   int dt0_cap = 0;
+  CopySeg* segs_d = nullptr;   // copy list of the fine levels' backups
+  int segs_cap = 0;
+  unsigned char* pin = nullptr;  // pinned staging of the regrid flags
+  size_t pin_cap = 0;
+  ByteSeg* bsegs_d = nullptr;    // regrid descriptor lists
+  int bsegs_cap = 0;
+  MaskBox* mboxes_d = nullptr;
+  int mboxes_cap = 0;
+  FillPatch* rfills_d = nullptr;
+  int rfills_cap = 0;
+  FlagLevel* flv_d = nullptr;    // flag descriptors
+  int flv_cap = 0;
 };
 
 namespace {
@@ -213,7 +225,7 @@ void mirror_frame_host(const LevelH& L, std::vector<double>& a) {
 // 16x16 fine tiles marked by a flagged coarse cell, kept if their coarse
 // footprint grown by two coarse cells (clipped at the domain) is covered by the
 // coarse level, merged greedily row-major into rectangles of at most 4x4 tiles.
-std::vector<Box> cluster_tiles(const LevelH& C, int r, const std::vector<unsigned char>& flags) {
+std::vector<Box> cluster_tiles(const LevelH& C, int r, const unsigned char* flags) {
   const int fnx = C.nx * r, fny = C.ny * r;
   const int tx = (fnx + TILE - 1) / TILE, ty = (fny + TILE - 1) / TILE;
   std::vector<char> keep((size_t)tx * ty, 0), taken((size_t)tx * ty, 0);
@@ -688,17 +700,18 @@ int read_status(mlswe_ctx* c, int p0, int p1, int* status) {
 }
 
 // ------------------------------------------------------------ patches
+void host_mask(LevelH& L);
+
 int upload_mask(mlswe_ctx* c, LevelH& L) {
-  std::fill(L.mask_h.begin(), L.mask_h.end(), 0);
-  for (const Box& b : L.boxes)
-    for (int j = b.jlo; j < b.jlo + b.ny; ++j)
-      std::memset(&L.mask_h[idx(L, b.ilo, j)], 1, b.nx);
+  host_mask(L);
   HIPCHK(c, hipMemcpyAsync(L.mask, L.mask_h.data(), L.mask_h.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return MLSWE_OK;
 }
 
-int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
+// Validates a patch list of level l of problem p (inside the level, aligned to
+// the ratio, covered by the coarser level, no overlaps; level 0 covered).
+int check_patches(mlswe_ctx* c, int p, int l, int n, const int32_t* bx, std::vector<Box>& nb_out) {
   ProblemH& P = c->probs[p];
   if (l < 0 || l >= P.nlev) return fail(c, MLSWE_EINVAL, "level %d out of range", l);
   if (n < 0 || (n > 0 && !bx)) return fail(c, MLSWE_EINVAL, "bad patch list");
@@ -730,6 +743,22 @@ int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
     for (unsigned char m : cov)
       if (!m) return fail(c, MLSWE_EINVAL, "level 0 patches must cover the domain");
   }
+  nb_out = nb;
+  return MLSWE_OK;
+}
+
+void host_mask(LevelH& L) {
+  std::fill(L.mask_h.begin(), L.mask_h.end(), 0);
+  for (const Box& b : L.boxes)
+    for (int j = b.jlo; j < b.jlo + b.ny; ++j) std::memset(&L.mask_h[idx(L, b.ilo, j)], 1, b.nx);
+}
+
+int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
+  std::vector<Box> nb;
+  int rc0 = check_patches(c, p, l, n, bx, nb);
+  if (rc0) return rc0;
+  ProblemH& P = c->probs[p];
+  LevelH& L = P.L[l];
   // keep the old coverage for the fill of new cells
   if (l > 0) {
     HIPCHK(c, hipMemcpyAsync(L.mask_old, L.mask, L.mask_h.size(), hipMemcpyDeviceToDevice, c->stream));
@@ -745,7 +774,7 @@ int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
     for (const Box& b : L.boxes) {
       FillPatch x;
       std::memset(&x, 0, sizeof x);
-      x.q = L.q[L.cur]; x.B = L.B; x.mask = L.mask;
+      x.q = L.q[L.cur]; x.B = L.B; x.mask = L.mask; x.mask_old = L.mask_old;
       x.qco = C.q[C.cur]; x.qcn = C.q[C.cur]; x.Bc = C.B;
       x.cnt = c->cnt + P.cnt;
       x.pitch = L.pitch; x.plane = L.plane; x.cpitch = C.pitch; x.cplane = C.plane;
@@ -759,8 +788,7 @@ int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
     FillPatch* fd = nullptr;
     if ((rc = dalloc(c, (void**)&fd, sizeof(FillPatch) * f.size()))) return rc;
     HIPCHK(c, hipMemcpyAsync(fd, f.data(), sizeof(FillPatch) * f.size(), hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(k_refine_new, dim3((maxn + 255) / 256, (unsigned)f.size()), dim3(256), 0, c->stream, fd,
-                       L.mask_old);
+    hipLaunchKernelGGL(k_refine_new, dim3((maxn + 255) / 256, (unsigned)f.size()), dim3(256), 0, c->stream, fd);
     hipError_t e = hipGetLastError();
     hipError_t s = hipStreamSynchronize(c->stream);
     dfree(fd);
@@ -783,8 +811,10 @@ int flag_impl(mlswe_ctx* c, int p, int l, double tau, int nbuf, std::vector<unsi
   F.q = L.q[L.cur]; F.B = L.B; F.mask = L.mask; F.raw = L.fraw; F.out = L.fout;
   F.pitch = L.pitch; F.plane = L.plane; F.nx = L.nx; F.ny = L.ny; F.nbuf = nbuf;
   F.dx = L.dx; F.dy = L.dy; F.tau = tau; F.hdry = P.P.hdry;
-  hipLaunchKernelGGL(k_flag_raw, dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, c->stream, F);
-  hipLaunchKernelGGL(k_flag_dilate, dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, c->stream, F);
+  if ((rc = ensure(c, &c->flv_d, &c->flv_cap, 1))) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->flv_d, &F, sizeof F, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_flag_raw, dim3((L.nx + 255) / 256, L.ny, 1), dim3(256), 0, c->stream, c->flv_d);
+  hipLaunchKernelGGL(k_flag_dilate, dim3((L.nx + 255) / 256, L.ny, 1), dim3(256), 0, c->stream, c->flv_d);
   HIPCHK(c, hipGetLastError());
   out.resize((size_t)L.nx * L.ny);
   HIPCHK(c, hipMemcpyAsync(out.data(), L.fout, out.size(), hipMemcpyDeviceToHost, c->stream));
@@ -798,10 +828,135 @@ int regrid_impl(mlswe_ctx* c, int p, const double* tau, int nbuf) {
     std::vector<unsigned char> f;
     int rc = flag_impl(c, p, l, tau[l], nbuf, f);
     if (rc) return rc;
-    std::vector<Box> bx = cluster_tiles(P.L[l], P.ratio[l], f);
+    std::vector<Box> bx = cluster_tiles(P.L[l], P.ratio[l], f.data());
     std::vector<int32_t> flat;
     for (const Box& b : bx) { flat.push_back(b.ilo); flat.push_back(b.jlo); flat.push_back(b.nx); flat.push_back(b.ny); }
     if ((rc = set_patches_impl(c, p, l + 1, (int)bx.size(), flat.data()))) return rc;
+  }
+  return MLSWE_OK;
+}
+
+// Regrid of problems [p0, p1) with one host wait per level: the flags of every
+// problem come back in one pinned buffer, clustering and validation run on the
+// host, and the new coverage (old coverage kept for the fill), the masks and
+// the refinement of newly covered cells are each one launch over all problems.
+int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) {
+  int maxlev = 0;
+  for (int p = p0; p < p1; ++p) maxlev = std::max(maxlev, c->probs[p].nlev);
+  for (int l = 0; l + 1 < maxlev; ++l) {
+    std::vector<int> who;
+    std::vector<size_t> off;
+    std::vector<FlagLevel> fl;
+    int mx = 0, my = 0;
+    size_t total = 0;
+    int rc;
+    for (int p = p0; p < p1; ++p) {
+      ProblemH& P = c->probs[p];
+      if (l + 1 >= P.nlev) continue;
+      LevelH& L = P.L[l];
+      if (!L.fraw) {
+        if ((rc = dalloc(c, (void**)&L.fraw, (size_t)L.nx * L.ny))) return rc;
+        if ((rc = dalloc(c, (void**)&L.fout, (size_t)L.nx * L.ny))) return rc;
+      }
+      FlagLevel F;
+      F.q = L.q[L.cur]; F.B = L.B; F.mask = L.mask; F.raw = L.fraw; F.out = L.fout;
+      F.pitch = L.pitch; F.plane = L.plane; F.nx = L.nx; F.ny = L.ny; F.nbuf = nbuf;
+      F.dx = L.dx; F.dy = L.dy; F.tau = tau_all[(size_t)p * MAXLEV + l]; F.hdry = P.P.hdry;
+      fl.push_back(F);
+      mx = std::max(mx, L.nx);
+      my = std::max(my, L.ny);
+      who.push_back(p);
+      off.push_back(total);
+      total += (size_t)L.nx * L.ny;
+    }
+    if (who.empty()) continue;
+    if ((rc = ensure(c, &c->flv_d, &c->flv_cap, (int)fl.size()))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->flv_d, fl.data(), sizeof(FlagLevel) * fl.size(), hipMemcpyHostToDevice, c->stream));
+    for (size_t k0 = 0; k0 < fl.size(); k0 += 65535) {  // grid z is at most 65535
+      const unsigned nz = (unsigned)std::min<size_t>(65535, fl.size() - k0);
+      hipLaunchKernelGGL(k_flag_raw, dim3((mx + 255) / 256, my, nz), dim3(256), 0, c->stream, c->flv_d + k0);
+    }
+    for (size_t k0 = 0; k0 < fl.size(); k0 += 65535) {
+      const unsigned nz = (unsigned)std::min<size_t>(65535, fl.size() - k0);
+      hipLaunchKernelGGL(k_flag_dilate, dim3((mx + 255) / 256, my, nz), dim3(256), 0, c->stream, c->flv_d + k0);
+    }
+    HIPCHK(c, hipGetLastError());
+    if (total > c->pin_cap) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (c->pin) (void)hipHostFree(c->pin);
+      c->pin = nullptr;
+      c->pin_cap = 0;
+      HIPCHK(c, hipHostMalloc((void**)&c->pin, total, hipHostMallocDefault));
+      c->pin_cap = total;
+    }
+    for (size_t k = 0; k < who.size(); ++k) {
+      const LevelH& L = c->probs[who[k]].L[l];
+      HIPCHK(c, hipMemcpyAsync(c->pin + off[k], L.fout, (size_t)L.nx * L.ny, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // host: clusters and validation, then the new layouts and host masks
+    std::vector<std::vector<Box>> nbs(who.size());
+    for (size_t k = 0; k < who.size(); ++k) {
+      ProblemH& P = c->probs[who[k]];
+      std::vector<Box> bx = cluster_tiles(P.L[l], P.ratio[l], c->pin + off[k]);
+      std::vector<int32_t> flat;
+      for (const Box& b : bx) { flat.push_back(b.ilo); flat.push_back(b.jlo); flat.push_back(b.nx); flat.push_back(b.ny); }
+      if ((rc = check_patches(c, who[k], l + 1, (int)bx.size(), flat.data(), nbs[k]))) return rc;
+    }
+    std::vector<ByteSeg> keep, clear;
+    std::vector<MaskBox> mb;
+    std::vector<FillPatch> fills;
+    int maxn = 0, maxbox = 0;
+    for (size_t k = 0; k < who.size(); ++k) {
+      ProblemH& P = c->probs[who[k]];
+      LevelH& L = P.L[l + 1];
+      const LevelH& C = P.L[l];
+      keep.push_back(ByteSeg{L.mask, L.mask_old, (long long)L.mask_h.size(), 0});
+      clear.push_back(ByteSeg{nullptr, L.mask, (long long)L.mask_h.size(), 0});
+      L.boxes = nbs[k];
+      host_mask(L);
+      mark_dirty(c, l + 1);
+      for (const Box& b : L.boxes) {
+        mb.push_back(MaskBox{L.mask, L.pitch, b.ilo, b.jlo, b.nx, b.ny});
+        FillPatch x;
+        std::memset(&x, 0, sizeof x);
+        x.q = L.q[L.cur]; x.B = L.B; x.mask = L.mask; x.mask_old = L.mask_old;
+        x.qco = C.q[C.cur]; x.qcn = C.q[C.cur]; x.Bc = C.B;
+        x.cnt = c->cnt + P.cnt;
+        x.pitch = L.pitch; x.plane = L.plane; x.cpitch = C.pitch; x.cplane = C.plane;
+        x.nx = L.nx; x.ny = L.ny; x.ncx = C.nx; x.ncy = C.ny;
+        x.ilo = b.ilo; x.jlo = b.jlo; x.bnx = b.nx; x.bny = b.ny;
+        x.r = P.ratio[l];
+        x.P = P.P;
+        fills.push_back(x);
+        maxn = std::max(maxn, b.nx * b.ny);
+      }
+      maxbox = std::max(maxbox, (int)L.mask_h.size());
+    }
+    // device: old coverage kept, masks cleared and set, new cells refined
+    if ((rc = ensure(c, &c->bsegs_d, &c->bsegs_cap, (int)(2 * keep.size())))) return rc;
+    std::vector<ByteSeg> both(keep);
+    both.insert(both.end(), clear.begin(), clear.end());
+    HIPCHK(c, hipMemcpyAsync(c->bsegs_d, both.data(), sizeof(ByteSeg) * both.size(), hipMemcpyHostToDevice, c->stream));
+    const unsigned gb = (unsigned)std::min(64, (maxbox + 255) / 256);
+    hipLaunchKernelGGL(k_byte_segs, dim3(gb, (unsigned)keep.size()), dim3(256), 0, c->stream, c->bsegs_d);
+    hipLaunchKernelGGL(k_byte_segs, dim3(gb, (unsigned)clear.size()), dim3(256), 0, c->stream,
+                       c->bsegs_d + keep.size());
+    if (!mb.empty()) {
+      if ((rc = ensure(c, &c->mboxes_d, &c->mboxes_cap, (int)mb.size()))) return rc;
+      HIPCHK(c, hipMemcpyAsync(c->mboxes_d, mb.data(), sizeof(MaskBox) * mb.size(), hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_mask_boxes, dim3((unsigned)std::min(64, (maxn + 255) / 256), (unsigned)mb.size()), dim3(256),
+                         0, c->stream, c->mboxes_d);
+      if ((rc = ensure(c, &c->rfills_d, &c->rfills_cap, (int)fills.size()))) return rc;
+      HIPCHK(c, hipMemcpyAsync(c->rfills_d, fills.data(), sizeof(FillPatch) * fills.size(), hipMemcpyHostToDevice,
+                               c->stream));
+      hipLaunchKernelGGL(k_refine_new, dim3((maxn + 255) / 256, (unsigned)fills.size()), dim3(256), 0, c->stream,
+                         c->rfills_d);
+    }
+    HIPCHK(c, hipGetLastError());
+    // the descriptor lists above are host vectors read by the copies: wait
+    // before they go out of scope (one wait per level of the regrid)
+    HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   return MLSWE_OK;
 }
@@ -899,7 +1054,9 @@ int mlswe_destroy(mlswe_ctx* c) {
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
   }
   dfree(c->ctl); dfree(c->cnt); dfree(c->theta); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
-  dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d);
+  dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d); dfree(c->segs_d);
+  dfree(c->bsegs_d); dfree(c->mboxes_d); dfree(c->rfills_d); dfree(c->flv_d);
+  if (c->pin) (void)hipHostFree(c->pin);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1255,6 +1412,47 @@ int graph_step(mlswe_ctx* c, int p0, int p1) {
 // put back (fine-level buffers, controls, counters, host bookkeeping; level 0
 // keeps its input buffer through a step) and the step is retaken, the failing
 // problems with dt scaled by cfl_desired / that number, the others unchanged.
+// Backup (to_bk) or restore of the patch rows of every fine level of problems
+// [p0, p1) in one launch: each field plane's rows covered by some patch are one
+// contiguous run (merged per level).  Frames and uncovered cells are refilled
+// or unused before they are read again, so they need no copy.
+int copy_fine_levels(mlswe_ctx* c, int p0, int p1, bool to_bk) {
+  std::vector<CopySeg> segs;
+  long long longest = 0;
+  for (int p = p0; p < p1; ++p) {
+    ProblemH& P = c->probs[p];
+    for (int l = 1; l < P.nlev; ++l) {
+      LevelH& L = P.L[l];
+      if (L.boxes.empty()) continue;
+      std::vector<std::pair<int, int>> rows;
+      for (const Box& b : L.boxes) rows.push_back({b.jlo, b.jlo + b.ny});
+      std::sort(rows.begin(), rows.end());
+      std::vector<std::pair<int, int>> merged;
+      for (const auto& r : rows) {
+        if (!merged.empty() && r.first <= merged.back().second) merged.back().second = std::max(merged.back().second, r.second);
+        else merged.push_back(r);
+      }
+      for (const auto& r : merged) {
+        const long long off = idx(L, 0, r.first) - XOFF, n = (long long)(r.second - r.first) * L.pitch;
+        longest = std::max(longest, n);
+        for (int f = 0; f < 6; ++f) {
+          double* q = L.q[L.cur] + f * L.plane + off;
+          double* b = L.bk + f * L.plane + off;
+          segs.push_back(to_bk ? CopySeg{q, b, n} : CopySeg{b, q, n});
+        }
+      }
+    }
+  }
+  if (segs.empty()) return MLSWE_OK;
+  int rc;
+  if ((rc = ensure(c, &c->segs_d, &c->segs_cap, (int)segs.size()))) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->segs_d, segs.data(), sizeof(CopySeg) * segs.size(), hipMemcpyHostToDevice, c->stream));
+  const unsigned gx = (unsigned)std::min<long long>(64, (longest + 255) / 256);
+  hipLaunchKernelGGL(k_copy_segs, dim3(gx, (unsigned)segs.size()), dim3(256), 0, c->stream, c->segs_d);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
 int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
   int rc;
   const bool together = mode != MLSWE_PLAIN;
@@ -1278,9 +1476,9 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
         if (l == 0 || L.boxes.empty()) continue;
         const size_t sb = sizeof(double) * 6 * (size_t)L.plane;
         if (!L.bk && (rc = dalloc(c, (void**)&L.bk, sb))) return rc;
-        HIPCHK(c, hipMemcpyAsync(L.bk, L.q[L.cur], sb, hipMemcpyDeviceToDevice, c->stream));
       }
     }
+    if ((rc = copy_fine_levels(c, p0, p1, true))) return rc;
   }
   if (mode == MLSWE_GRAPH && c->probs[p0].have_dt && !c->timing)
     rc = graph_step(c, p0, p1);
@@ -1325,11 +1523,9 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
         LevelH& L = P.L[l];
         L.cur = cur0[k];
         P.updates[l] = upd0[k];
-        if (l == 0 || L.boxes.empty()) continue;
-        HIPCHK(c, hipMemcpyAsync(L.q[L.cur], L.bk, sizeof(double) * 6 * (size_t)L.plane, hipMemcpyDeviceToDevice,
-                                 c->stream));
       }
     }
+    if ((rc = copy_fine_levels(c, p0, p1, false))) return rc;
     if ((rc = ensure(c, &c->dt0_d, &c->dt0_cap, np))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->dt0_d, dt0.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_set_dt0, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, c->dt0_d, np);
@@ -1365,8 +1561,7 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
     for (int n = 0; n < nsteps; ++n) {
       int rc;
       if (regrid_every > 0 && n % regrid_every == 0)
-        for (int p = p0; p < p1; ++p)
-          if ((rc = regrid_impl(c, p, tau + (size_t)p * MAXLEV, nbuf))) return rc;
+        if ((rc = regrid_group(c, p0, p1, tau, nbuf))) return rc;
       if ((rc = build_pdt(c))) return rc;
       if ((rc = step_with_retry(c, p0, p1, mode))) return rc;
       if (dts_out || c->timing) {
