@@ -12,6 +12,8 @@ namespace mlswe {
 #define MLSWE_KY k_sweep_y
 #define MLSWE_KX1 k_sweep_x1
 #define MLSWE_KY1 k_sweep_y1
+#define MLSWE_KXR k_sweep_xr
+#define MLSWE_KYR k_sweep_yr
 #include "mlswe_sweeps.inc"
 
 __global__ void k_zero_u32(unsigned* p, int n) {
@@ -390,12 +392,15 @@ __global__ __launch_bounds__(256) void k_byte_segs(const ByteSeg* __restrict__ s
     S.dst[k] = S.src ? S.src[k] : (unsigned char)S.value;
 }
 
-// Coverage of patch boxes (block row y: box y) set to 1.
+// Coverage bytes of patch boxes (block row y: box y): interior, first column
+// and first row bits.
 __global__ __launch_bounds__(256) void k_mask_boxes(const MaskBox* __restrict__ boxes) {
   const MaskBox M = boxes[blockIdx.y];
   const int n = M.nx * M.ny;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
-    M.mask[cidx(M.pitch, M.ilo + k % M.nx, M.jlo + k / M.nx)] = 1;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int a = k % M.nx, b = k / M.nx;
+    M.mask[cidx(M.pitch, M.ilo + a, M.jlo + b)] = COV_IN | (a == 0 ? COV_COL0 : 0) | (b == 0 ? COV_ROW0 : 0);
+  }
 }
 
 // Many contiguous copies in one launch: block row y copies segment y.

@@ -40,9 +40,22 @@ struct PatchDev {
   double dx, dy;
   PhysParams P;
   int sig_on;        // accumulate the branch signature into cnt->sig
+  const unsigned char* mask;  // coverage of the level (bits below)
 };
 
-struct XTile { int patch, i0, ncols, j0, nrows; };
+// Coverage byte of a level cell: interior of some patch, and whether the cell
+// is the first column / first row of that patch.  A cell's neighbour to the
+// left (below) lies in the same patch iff both are interior and the cell is
+// not a first column (row).
+constexpr unsigned char COV_IN = 1, COV_COL0 = 2, COV_ROW0 = 4;
+
+// Sweep tiles.  Patch tiles cover one patch (its rows and two frame rows on
+// each side for x, its interior for y).  Run tiles cover fixed blocks of the
+// union of a level's patches (60 or 64 columns by a row chunk): `patch` is then
+// the level's descriptor, cells and edges are told apart through the coverage
+// bytes, and flags bit 0 says the tile owns the edge after its last column (x)
+// or row (y) because no tile of the union follows it.
+struct XTile { int patch, i0, ncols, j0, nrows, flags; };
 struct YTile { int patch, i0, ncols, j0, nrows, last; };
 
 // Ghost fill / regrid refine of one fine patch.
@@ -174,6 +187,14 @@ __global__ void k_sweep_x(const PatchDev* __restrict__ patches, const XTile* __r
                           unsigned* ticket, TilePart* parts);
 __global__ void k_sweep_y(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles, int sched,
                           unsigned* ticket, TilePart* parts);
+__global__ void k_sweep_xr(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles,
+                           TilePart* parts);
+__global__ void k_sweep_yr(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
+                           TilePart* parts);
+__global__ void k_sweep_xr_fast(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles,
+                                TilePart* parts);
+__global__ void k_sweep_yr_fast(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
+                                TilePart* parts);
 __global__ void k_sweep_x1(const PatchDev* __restrict__ patches, const XTile* __restrict__ tiles, int ntiles,
                            TilePart* parts);
 __global__ void k_sweep_y1(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
@@ -213,7 +234,7 @@ struct ByteSeg {
   int value;
 };
 __global__ void k_byte_segs(const ByteSeg* __restrict__ segs);
-// One patch box of a level's coverage mask, set to 1.
+// One patch box of a level's coverage mask, to be set.
 struct MaskBox {
   unsigned char* mask;
   long long pitch;

@@ -80,10 +80,14 @@ struct LevelLaunch {
   std::vector<int> patch_prob;               // problem of each patch
   std::vector<std::pair<int, int>> xr, yr;   // per patch: tile ranges
   PatchDev* pd[2] = {nullptr, nullptr};      // by buffer parity of the level
-  XTile* xt = nullptr;
+  XTile* xt = nullptr;                       // patch tiles, then run tiles
   YTile* yt = nullptr;
-  int nxt = 0, nyt = 0;
+  int nxt = 0, nyt = 0;                      // all tiles
+  int nxt_p = 0, nyt_p = 0;                  // patch tiles
+  bool use_runs = false;                     // some problem has several patches on the level
+  std::vector<std::pair<int, int>> xrun, yrun;  // per problem: run tile ranges
   int rows_x = 0, rows_y = 0;                // rows per sweep wave in the current tiles
+  int rows_xr = 0, rows_yr = 0;              // the same for the run tiles
   TilePart* parts = nullptr;                 // per tile: x tiles, then y tiles
   int cap_parts = 0;
   int max_info_tiles = 0;                    // most tiles of one problem on the level
@@ -91,7 +95,8 @@ struct LevelLaunch {
   CoarsenPatch* cp[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<int> fill_first;               // per problem: first fill entry (or -1) and count
   std::vector<int> fill_count;
-  LevelInfo* li = nullptr;                   // ctl / dx / dy of every problem having the level
+  LevelInfo* li = nullptr;                   // ctl / dx / dy of every problem having the level; four
+                                             // copies (x ranges of patch / run tiles, times y ranges)
   int nli = 0;
   std::vector<int> li_first;
   int cap_pd = 0, cap_xt = 0, cap_yt = 0, cap_fp = 0, cap_li = 0;
@@ -273,6 +278,42 @@ std::vector<Box> cluster_tiles(const LevelH& C, int r, const unsigned char* flag
 }
 
 // ------------------------------------------------------------ launch data
+// Run tiles of one level of one problem: fixed blocks over the union of its
+// patches, x blocks of XTILE_COLS columns by `rows` rows counted from row -2
+// (the patches' rows and two frame rows on each side), y blocks of 64 columns
+// by `rows` interior rows.  A block is kept where a patch region meets it; bit
+// 0 of flags (x) / last (y) marks a block whose successor to the right (x) or
+// above (y) is not kept, so that it owns the edge after its last column / row.
+// Returns the number of blocks kept; appends tiles when the vectors are given.
+long long run_blocks(const LevelH& L, int axis, int rows, int pdi, std::vector<XTile>* xo, std::vector<YTile>* yo) {
+  const int w = axis == 0 ? XTILE_COLS : 64;
+  const int ns = (L.nx + w - 1) / w;
+  const int r0 = axis == 0 ? -2 : 0, hy = axis == 0 ? L.ny + 4 : L.ny;
+  const int nc = (hy + rows - 1) / rows;
+  std::vector<char> keep((size_t)ns * nc, 0);
+  for (const Box& b : L.boxes) {
+    const int ja = axis == 0 ? b.jlo - 2 : b.jlo, jb = axis == 0 ? b.jlo + b.ny + 2 : b.jlo + b.ny;
+    for (int k = (ja - r0) / rows; k <= (jb - 1 - r0) / rows; ++k)
+      for (int s = b.ilo / w; s <= (b.ilo + b.nx - 1) / w; ++s) keep[(size_t)k * ns + s] = 1;
+  }
+  long long n = 0;
+  for (int k = 0; k < nc; ++k)
+    for (int s = 0; s < ns; ++s) {
+      if (!keep[(size_t)k * ns + s]) continue;
+      ++n;
+      const int i0 = s * w, j0 = r0 + k * rows;
+      const int ncol = std::min(w, L.nx - i0), nrow = std::min(rows, r0 + hy - j0);
+      if (axis == 0 && xo) {
+        const bool next = s + 1 < ns && keep[(size_t)k * ns + s + 1];
+        xo->push_back(XTile{pdi, i0, ncol, j0, nrow, next ? 0 : 1});
+      } else if (axis == 1 && yo) {
+        const bool next = k + 1 < nc && keep[(size_t)(k + 1) * ns + s];
+        yo->push_back(YTile{pdi, i0, ncol, j0, nrow, next ? 0 : 1});
+      }
+    }
+  return n;
+}
+
 int build_launch(mlswe_ctx* c, int l) {
   LevelLaunch& LL = c->launch[l];
   if (!LL.dirty) return MLSWE_OK;
@@ -303,6 +344,28 @@ int build_launch(mlswe_ctx* c, int l) {
   }
   LL.rows_x = xrows;
   LL.rows_y = yrows;
+  // run tiles serve levels where some problem has several patches; their rows
+  // follow the same rule over the run blocks
+  LL.use_runs = false;
+  for (const ProblemH& P : c->probs)
+    if (l < P.nlev && P.L[l].boxes.size() > 1) LL.use_runs = true;
+  auto count_runs = [&](int axis, int rows) {
+    long long n = 0;
+    for (const ProblemH& P : c->probs)
+      if (l < P.nlev && !P.L[l].boxes.empty()) n += run_blocks(P.L[l], axis, rows, 0, nullptr, nullptr);
+    return n;
+  };
+  int xrows_r = c->tune.x_rows, yrows_r = c->tune.y_rows;
+  if (LL.use_runs && xrows_r <= 0) {
+    xrows_r = 32;
+    while (xrows_r > 4 && count_runs(0, xrows_r) < 16LL * c->ncu) xrows_r /= 2;
+  }
+  if (LL.use_runs && yrows_r <= 0) {
+    yrows_r = 128;
+    while (yrows_r > 8 && count_runs(1, yrows_r) < 4LL * c->ncu) yrows_r /= 2;
+  }
+  LL.rows_xr = LL.use_runs ? xrows_r : 0;
+  LL.rows_yr = LL.use_runs ? yrows_r : 0;
   std::vector<PatchDev> pd[2];
   std::vector<XTile> xt;
   std::vector<YTile> yt;
@@ -335,6 +398,7 @@ int build_launch(mlswe_ctx* c, int l) {
         d.ilo = b.ilo; d.jlo = b.jlo; d.nx = b.nx; d.ny = b.ny;
         d.dx = L.dx; d.dy = L.dy; d.P = P.P;
         d.sig_on = c->sig_on;
+        d.mask = L.mask;
         pd[par].push_back(d);
       }
       LL.patch_prob.push_back((int)pi);
@@ -389,18 +453,58 @@ int build_launch(mlswe_ctx* c, int l) {
     li.back().ny = (int)yt.size() - li.back().y0;
   }
   LL.nptch = (int)pd[0].size();
+  LL.nxt_p = (int)xt.size();
+  LL.nyt_p = (int)yt.size();
+  // run tiles of each problem, over a level descriptor that follows the patch
+  // descriptors (the patch extent fields are unused there)
+  LL.xrun.assign(c->probs.size(), {0, 0});
+  LL.yrun.assign(c->probs.size(), {0, 0});
+  std::vector<LevelInfo> li_run = li;
+  if (LL.use_runs) {
+    int k = 0;
+    for (size_t pi = 0; pi < c->probs.size(); ++pi) {
+      ProblemH& P = c->probs[pi];
+      if (l >= P.nlev) continue;
+      LevelH& L = P.L[l];
+      LevelInfo& info = li_run[k++];
+      info.x0 = (int)xt.size(); info.y0 = (int)yt.size();
+      if (!L.boxes.empty()) {
+        const int id = (int)pd[0].size();
+        for (int par = 0; par < 2; ++par) {
+          PatchDev d = pd[par][LL.fill_first[pi]];  // the problem's first patch
+          d.ilo = 0; d.jlo = 0; d.nx = L.nx; d.ny = L.ny;
+          pd[par].push_back(d);
+        }
+        run_blocks(L, 0, LL.rows_xr, id, &xt, nullptr);
+        run_blocks(L, 1, LL.rows_yr, id, nullptr, &yt);
+      }
+      info.nx = (int)xt.size() - info.x0;
+      info.ny = (int)yt.size() - info.y0;
+      LL.xrun[pi] = {info.x0, info.nx};
+      LL.yrun[pi] = {info.y0, info.ny};
+    }
+  }
   LL.nxt = (int)xt.size();
   LL.nyt = (int)yt.size();
   LL.nli = (int)li.size();
   LL.max_info_tiles = 0;
-  for (LevelInfo& info : li) {
-    info.y0 += LL.nxt;
-    LL.max_info_tiles = std::max(LL.max_info_tiles, info.nx + info.ny);
-  }
+  // four copies: x ranges of patch (0) or run (1) tiles, plus 2 for run y ranges
+  std::vector<LevelInfo> li4(4 * (size_t)LL.nli);
+  for (int k = 0; k < LL.nli; ++k)
+    for (int v = 0; v < 4; ++v) {
+      LevelInfo info = li[k];
+      const LevelInfo& rinfo = li_run[k];
+      if ((v & 1) && LL.use_runs) { info.x0 = rinfo.x0; info.nx = rinfo.nx; }
+      if ((v & 2) && LL.use_runs) { info.y0 = rinfo.y0; info.ny = rinfo.ny; }
+      info.y0 += LL.nxt;
+      LL.max_info_tiles = std::max(LL.max_info_tiles, info.nx + info.ny);
+      li4[(size_t)v * LL.nli + k] = info;
+    }
+  const int npd = (int)pd[0].size();
   int rc;
   int cap_pd1 = LL.cap_pd;
-  if ((rc = ensure(c, &LL.pd[0], &LL.cap_pd, LL.nptch))) return rc;
-  if ((rc = ensure(c, &LL.pd[1], &cap_pd1, LL.nptch))) return rc;
+  if ((rc = ensure(c, &LL.pd[0], &LL.cap_pd, npd))) return rc;
+  if ((rc = ensure(c, &LL.pd[1], &cap_pd1, npd))) return rc;
   if ((rc = ensure(c, &LL.xt, &LL.cap_xt, LL.nxt))) return rc;
   if ((rc = ensure(c, &LL.yt, &LL.cap_yt, LL.nyt))) return rc;
   int capf[4] = {LL.cap_fp, LL.cap_fp, LL.cap_fp, LL.cap_fp};
@@ -410,11 +514,11 @@ int build_launch(mlswe_ctx* c, int l) {
     if ((rc = ensure(c, &LL.cp[k], &capc[k], LL.nptch))) return rc;
   }
   LL.cap_fp = capf[0];
-  if ((rc = ensure(c, &LL.li, &LL.cap_li, LL.nli))) return rc;
+  if ((rc = ensure(c, &LL.li, &LL.cap_li, 4 * LL.nli))) return rc;
   if ((rc = ensure(c, &LL.parts, &LL.cap_parts, LL.nxt + LL.nyt))) return rc;
   if (LL.nptch) {
-    HIPCHK(c, hipMemcpyAsync(LL.pd[0], pd[0].data(), sizeof(PatchDev) * LL.nptch, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(LL.pd[1], pd[1].data(), sizeof(PatchDev) * LL.nptch, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(LL.pd[0], pd[0].data(), sizeof(PatchDev) * npd, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(LL.pd[1], pd[1].data(), sizeof(PatchDev) * npd, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(LL.xt, xt.data(), sizeof(XTile) * LL.nxt, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(LL.yt, yt.data(), sizeof(YTile) * LL.nyt, hipMemcpyHostToDevice, c->stream));
     for (int k = 0; k < 4; ++k) {
@@ -423,7 +527,7 @@ int build_launch(mlswe_ctx* c, int l) {
     }
   }
   if (LL.nli)
-    HIPCHK(c, hipMemcpyAsync(LL.li, li.data(), sizeof(LevelInfo) * LL.nli, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(LL.li, li4.data(), sizeof(LevelInfo) * li4.size(), hipMemcpyHostToDevice, c->stream));
   // host vectors must outlive the asynchronous copies
   HIPCHK(c, hipStreamSynchronize(c->stream));
   LL.dirty = false;
@@ -490,7 +594,9 @@ int collect_events(mlswe_ctx* c) {
 }
 
 // ------------------------------------------------------------ launches
-int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, int nyt) {
+// Sweeps over tile ranges of level l; rx / ry: the ranges are run tiles.
+int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, int nyt, bool rx = false,
+                  bool ry = false) {
   LevelLaunch& LL = c->launch[l];
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc;
@@ -505,7 +611,10 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->tickets, 2);
   if (nxt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
-    if (sx == 0 && !c->sig_on)  // one wave per tile, no signature: the lean kernels
+    if (rx)
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_xr_fast : k_sweep_xr, dim3(grid_of(nxt, 0, 0)), dim3(256), 0,
+                         c->stream, LL.pd[parity], LL.xt + xt0, nxt, LL.parts + xt0);
+    else if (sx == 0 && !c->sig_on)  // one wave per tile, no signature: the lean kernels
       hipLaunchKernelGGL(c->tune.fast ? k_sweep_x1_fast : k_sweep_x1, dim3(grid_of(nxt, 0, 0)), dim3(256), 0,
                          c->stream, LL.pd[parity], LL.xt + xt0, nxt, LL.parts + xt0);
     else
@@ -519,7 +628,10 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   }
   if (nyt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
-    if (sy == 0 && !c->sig_on)
+    if (ry)
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_yr_fast : k_sweep_yr, dim3(grid_of(nyt, 0, 0)), dim3(256), 0,
+                         c->stream, LL.pd[parity], LL.yt + yt0, nyt, LL.parts + LL.nxt + yt0);
+    else if (sy == 0 && !c->sig_on)
       hipLaunchKernelGGL(c->tune.fast ? k_sweep_y1_fast : k_sweep_y1, dim3(grid_of(nyt, 0, 0)), dim3(256), 0,
                          c->stream, LL.pd[parity], LL.yt + yt0, nyt, LL.parts + LL.nxt + yt0);
     else
@@ -560,7 +672,8 @@ int launch_fill(mlswe_ctx* c, int l, int p0, int p1, double theta) {
   return MLSWE_OK;
 }
 
-int launch_after(mlswe_ctx* c, int l, int p0, int p1) {
+// runs: bit 0 the x tiles were run tiles, bit 1 the y tiles.
+int launch_after(mlswe_ctx* c, int l, int p0, int p1, int runs) {
   LevelLaunch& LL = c->launch[l];
   int first = -1, n = 0;
   for (int p = p0; p < p1; ++p) {
@@ -571,7 +684,7 @@ int launch_after(mlswe_ctx* c, int l, int p0, int p1) {
   if (n == 0) return MLSWE_OK;
   // one wave per problem suffices for a few tiles; a problem with many gets 16
   hipLaunchKernelGGL(k_after_substep, dim3(n), dim3(LL.max_info_tiles > 256 ? 1024 : 64), 0, c->stream, c->ctl, c->cnt,
-                     LL.li + first, LL.parts, c->cfg.cfl_max);
+                     LL.li + (size_t)runs * LL.nli + first, LL.parts, c->cfg.cfl_max);
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
@@ -594,11 +707,29 @@ int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
       if (a < 0) a = k;
       b = k;
     }
+  int runs = 0;
   if (a >= 0) {
     if (batched) {
-      const int xt0 = LL.xr[a].first, nxt = LL.xr[b].first + LL.xr[b].second - xt0;
-      const int yt0 = LL.yr[a].first, nyt = LL.yr[b].first + LL.yr[b].second - yt0;
-      if ((rc = launch_sweeps(c, l, parity, xt0, nxt, yt0, nyt))) return rc;
+      int xt0 = LL.xr[a].first, nxt = LL.xr[b].first + LL.xr[b].second - xt0;
+      int yt0 = LL.yr[a].first, nyt = LL.yr[b].first + LL.yr[b].second - yt0;
+      // levels with several patches per problem: one-wave run tiles over the union
+      const bool rx = LL.use_runs && c->tune.sched_x == 0 && !c->sig_on;
+      const bool ry = LL.use_runs && c->tune.sched_y == 0 && !c->sig_on;
+      auto run_range = [&](const std::vector<std::pair<int, int>>& rr, int& t0, int& n) {
+        int e = -1;
+        t0 = -1;
+        for (int p = p0; p < p1; ++p) {
+          if (rr[p].second == 0) continue;
+          if (t0 < 0) t0 = rr[p].first;
+          e = rr[p].first + rr[p].second;
+        }
+        n = t0 < 0 ? 0 : e - t0;
+        if (t0 < 0) t0 = 0;
+      };
+      if (rx) run_range(LL.xrun, xt0, nxt);
+      if (ry) run_range(LL.yrun, yt0, nyt);
+      runs = (rx ? 1 : 0) | (ry ? 2 : 0);
+      if ((rc = launch_sweeps(c, l, parity, xt0, nxt, yt0, nyt, rx, ry))) return rc;
     } else {
       // plain: x then y of every patch, one launch each
       for (int k = a; k <= b; ++k)
@@ -613,7 +744,7 @@ int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
     L.cur = 1 - L.cur;
     for (const Box& bx : L.boxes) P.updates[l] += (long long)bx.nx * bx.ny;
   }
-  return launch_after(c, l, p0, p1);
+  return launch_after(c, l, p0, p1, runs);
 }
 
 int coarsen_level(mlswe_ctx* c, int lf, int p0, int p1) {
@@ -747,10 +878,16 @@ int check_patches(mlswe_ctx* c, int p, int l, int n, const int32_t* bx, std::vec
   return MLSWE_OK;
 }
 
+// Coverage bytes of a level: COV_IN on patch interiors, plus COV_COL0 / COV_ROW0
+// on each patch's first column / row.
 void host_mask(LevelH& L) {
   std::fill(L.mask_h.begin(), L.mask_h.end(), 0);
   for (const Box& b : L.boxes)
-    for (int j = b.jlo; j < b.jlo + b.ny; ++j) std::memset(&L.mask_h[idx(L, b.ilo, j)], 1, b.nx);
+    for (int j = b.jlo; j < b.jlo + b.ny; ++j) {
+      unsigned char* row = &L.mask_h[idx(L, b.ilo, j)];
+      std::memset(row, j == b.jlo ? COV_IN | COV_ROW0 : COV_IN, b.nx);
+      row[0] |= COV_COL0;
+    }
 }
 
 int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
@@ -1873,7 +2010,13 @@ static int time_sweeps(mlswe_ctx* c, int axis, int reps, double* ms) {
       LevelLaunch& LL = c->launch[l];
       if (LL.nptch == 0) continue;
       const int par = c->probs[LL.patch_prob[0]].L[l].cur;
-      int r2 = axis == 0 ? launch_sweeps(c, l, par, 0, LL.nxt, 0, 0) : launch_sweeps(c, l, par, 0, 0, 0, LL.nyt);
+      // the tiles a batched substep would launch: run tiles for one-wave
+      // schedules on levels with several patches per problem
+      const bool run = LL.use_runs && (axis == 0 ? c->tune.sched_x : c->tune.sched_y) == 0 && !c->sig_on;
+      const int t0 = axis == 0 ? (run ? LL.nxt_p : 0) : (run ? LL.nyt_p : 0);
+      const int n = axis == 0 ? (run ? LL.nxt - LL.nxt_p : LL.nxt_p) : (run ? LL.nyt - LL.nyt_p : LL.nyt_p);
+      int r2 = axis == 0 ? launch_sweeps(c, l, par, t0, n, 0, 0, run, false)
+                         : launch_sweeps(c, l, par, 0, 0, t0, n, false, run);
       if (r2) return r2;
     }
     return MLSWE_OK;

@@ -12,5 +12,7 @@ namespace mlswe {
 #define MLSWE_KY k_sweep_y_fast
 #define MLSWE_KX1 k_sweep_x1_fast
 #define MLSWE_KY1 k_sweep_y1_fast
+#define MLSWE_KXR k_sweep_xr_fast
+#define MLSWE_KYR k_sweep_yr_fast
 #include "mlswe_sweeps.inc"
 }  // namespace mlswe

@@ -23,6 +23,10 @@ __device__ __forceinline__ gchar_c* row_of(const double* a, long long off) { ret
 __device__ __forceinline__ double ld_at(gchar_c* row, unsigned boff) {
   return *(__attribute__((address_space(1))) const double*)(row + boff);
 }
+// Coverage byte: wave-uniform row offset plus the lane's column offset.
+__device__ __forceinline__ int ld_cov(const unsigned char* m, long long rowoff, unsigned col) {
+  return *((__attribute__((address_space(1))) const unsigned char*)(m + rowoff) + col);
+}
 __device__ __forceinline__ void st_at(double* a, long long off, unsigned boff, double v) {
   *(__attribute__((address_space(1))) double*)((gchar*)(a + off) + boff) = v;
 }
