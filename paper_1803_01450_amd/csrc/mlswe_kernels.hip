@@ -403,11 +403,19 @@ __global__ __launch_bounds__(256) void k_mask_boxes(const MaskBox* __restrict__ 
   }
 }
 
-// Many contiguous copies in one launch: block row y copies segment y.
-__global__ __launch_bounds__(256) void k_copy_segs(const CopySeg* __restrict__ segs) {
-  const CopySeg S = segs[blockIdx.y];
-  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < S.n; k += (long long)gridDim.x * blockDim.x)
-    S.dst[k] = S.src[k];
+// Many box copies in one launch: block row y copies box y; its elements are
+// numbered column-fastest over the (field, row) lines and strided over the
+// block row's threads.
+__global__ __launch_bounds__(256) void k_copy_boxes(const CopyBox* __restrict__ boxes) {
+  const CopyBox C = boxes[blockIdx.y];
+  const unsigned nx = (unsigned)C.nx, ny = (unsigned)C.ny;
+  const unsigned n = nx * ny * (unsigned)C.nf;
+  for (unsigned k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const unsigned line = k / nx, a = k - line * nx;
+    const unsigned f = line / ny, b = line - f * ny;
+    const long long off = (long long)f * C.plane + (long long)b * C.pitch + a;
+    C.dst[off] = C.src[off];
+  }
 }
 
 // Six fields between a level array (interior cells, padded rows) and the

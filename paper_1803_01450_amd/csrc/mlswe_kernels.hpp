@@ -220,12 +220,16 @@ __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int npr
 __global__ void k_set_theta(double* th, double v);
 __global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);
 // A contiguous run of doubles to copy (one row range of one field plane).
-struct CopySeg {
+// A box of nf fields copied between two arrays of the same layout: element
+// (f, a, b) at f * plane + b * pitch + a from the box origins src / dst.  A
+// plain run of n doubles is nf = 1, ny = 1, nx = n.
+struct CopyBox {
   const double* src;
   double* dst;
-  long long n;
+  long long pitch, plane;
+  int nx, ny, nf, pad;
 };
-__global__ void k_copy_segs(const CopySeg* __restrict__ segs);
+__global__ void k_copy_boxes(const CopyBox* __restrict__ boxes);
 // Byte runs: copied (src set) or filled with a value (src null).
 struct ByteSeg {
   const unsigned char* src;

@@ -152,8 +152,10 @@ struct mlswe_ctx {
   int bk_cap = 0, cbk_cap = 0;
   double* dt0_d = nullptr;
   int dt0_cap = 0;
-  CopySeg* segs_d = nullptr;   // copy list of the fine levels' backups
-  int segs_cap = 0;
+  CopyBox* boxes_d = nullptr;  // copy list of a coarse step's backup / restore
+  int boxes_cap = 0;
+  LevelCtl* ctl_pin = nullptr;  // pinned readback of the control blocks
+  size_t ctl_pin_cap = 0;
   unsigned char* pin = nullptr;  // pinned staging of the regrid flags
   size_t pin_cap = 0;
   ByteSeg* bsegs_d = nullptr;    // regrid descriptor lists
@@ -816,17 +818,21 @@ int next_dt(mlswe_ctx* c, int p0, int p1, bool initial) {
   return MLSWE_OK;
 }
 
+// Control blocks of problems [p0, p1) (contiguous, problem-major) in one copy.
+int read_ctls(mlswe_ctx* c, int p0, int p1, std::vector<LevelCtl>& h) {
+  const int a = c->probs[p0].ctl0, b = c->probs[p1 - 1].ctl0 + c->probs[p1 - 1].nlev;
+  h.resize((size_t)(b - a));
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->ctl + a, sizeof(LevelCtl) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MLSWE_OK;
+}
+
 int read_status(mlswe_ctx* c, int p0, int p1, int* status) {
   *status = 0;
-  for (int p = p0; p < p1; ++p) {
-    const ProblemH& P = c->probs[p];
-    for (int l = 0; l < P.nlev; ++l) {
-      LevelCtl h;
-      HIPCHK(c, hipMemcpyAsync(&h, c->ctl + P.ctl0 + l, sizeof h, hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      *status |= h.status;
-    }
-  }
+  std::vector<LevelCtl> h;
+  int rc = read_ctls(c, p0, p1, h);
+  if (rc) return rc;
+  for (const LevelCtl& x : h) *status |= x.status;
   return MLSWE_OK;
 }
 
@@ -1191,9 +1197,10 @@ int mlswe_destroy(mlswe_ctx* c) {
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
   }
   dfree(c->ctl); dfree(c->cnt); dfree(c->theta); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
-  dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d); dfree(c->segs_d);
+  dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d); dfree(c->boxes_d);
   dfree(c->bsegs_d); dfree(c->mboxes_d); dfree(c->rfills_d); dfree(c->flv_d);
   if (c->pin) (void)hipHostFree(c->pin);
+  if (c->ctl_pin) (void)hipHostFree(c->ctl_pin);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1544,52 +1551,50 @@ int graph_step(mlswe_ctx* c, int p0, int p1) {
   return MLSWE_OK;
 }
 
-// A coarse step of problems [p0, p1) with rejection: when the largest substep
-// Courant number of a problem exceeds cfl_max, every problem of the group is
-// put back (fine-level buffers, controls, counters, host bookkeeping; level 0
-// keeps its input buffer through a step) and the step is retaken, the failing
-// problems with dt scaled by cfl_desired / that number, the others unchanged.
-// Backup (to_bk) or restore of the patch rows of every fine level of problems
-// [p0, p1) in one launch: each field plane's rows covered by some patch are one
-// contiguous run (merged per level).  Frames and uncovered cells are refilled
-// or unused before they are read again, so they need no copy.
-int copy_fine_levels(mlswe_ctx* c, int p0, int p1, bool to_bk) {
-  std::vector<CopySeg> segs;
+// Backup (to_bk) or restore of a group's coarse-step start: the patch interiors
+// of its finer levels and the control blocks and counters of every problem,
+// in one launch.
+int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt) {
+  std::vector<CopyBox> boxes;
   long long longest = 0;
+  auto add = [&](const double* from, double* to, long long pitch, long long plane, int nx, int ny, int nf) {
+    boxes.push_back(CopyBox{from, to, pitch, plane, nx, ny, nf, 0});
+    longest = std::max(longest, (long long)nx * ny * nf);
+  };
+  auto run = [&](double* live, double* saved, long long n) {
+    if (n > 0) add(to_bk ? live : saved, to_bk ? saved : live, 0, 0, (int)n, 1, 1);
+  };
+  static_assert(sizeof(LevelCtl) % sizeof(double) == 0 && sizeof(Counters) % sizeof(double) == 0, "copied as doubles");
+  run((double*)c->ctl, (double*)c->ctl_bk, (long long)nctl * (long long)(sizeof(LevelCtl) / sizeof(double)));
+  run((double*)c->cnt, (double*)c->cnt_bk, (long long)ncnt * (long long)(sizeof(Counters) / sizeof(double)));
   for (int p = p0; p < p1; ++p) {
     ProblemH& P = c->probs[p];
     for (int l = 1; l < P.nlev; ++l) {
       LevelH& L = P.L[l];
-      if (L.boxes.empty()) continue;
-      std::vector<std::pair<int, int>> rows;
-      for (const Box& b : L.boxes) rows.push_back({b.jlo, b.jlo + b.ny});
-      std::sort(rows.begin(), rows.end());
-      std::vector<std::pair<int, int>> merged;
-      for (const auto& r : rows) {
-        if (!merged.empty() && r.first <= merged.back().second) merged.back().second = std::max(merged.back().second, r.second);
-        else merged.push_back(r);
-      }
-      for (const auto& r : merged) {
-        const long long off = idx(L, 0, r.first) - XOFF, n = (long long)(r.second - r.first) * L.pitch;
-        longest = std::max(longest, n);
-        for (int f = 0; f < 6; ++f) {
-          double* q = L.q[L.cur] + f * L.plane + off;
-          double* b = L.bk + f * L.plane + off;
-          segs.push_back(to_bk ? CopySeg{q, b, n} : CopySeg{b, q, n});
-        }
+      for (const Box& b : L.boxes) {
+        const long long off = idx(L, b.ilo, b.jlo);
+        double* q = L.q[L.cur] + off;
+        double* k = L.bk + off;
+        add(to_bk ? q : k, to_bk ? k : q, L.pitch, L.plane, b.nx, b.ny, 6);
       }
     }
   }
-  if (segs.empty()) return MLSWE_OK;
   int rc;
-  if ((rc = ensure(c, &c->segs_d, &c->segs_cap, (int)segs.size()))) return rc;
-  HIPCHK(c, hipMemcpyAsync(c->segs_d, segs.data(), sizeof(CopySeg) * segs.size(), hipMemcpyHostToDevice, c->stream));
+  if ((rc = ensure(c, &c->boxes_d, &c->boxes_cap, (int)boxes.size()))) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->boxes_d, boxes.data(), sizeof(CopyBox) * boxes.size(), hipMemcpyHostToDevice, c->stream));
   const unsigned gx = (unsigned)std::min<long long>(64, (longest + 255) / 256);
-  hipLaunchKernelGGL(k_copy_segs, dim3(gx, (unsigned)segs.size()), dim3(256), 0, c->stream, c->segs_d);
+  hipLaunchKernelGGL(k_copy_boxes, dim3(gx, (unsigned)boxes.size()), dim3(256), 0, c->stream, c->boxes_d);
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
 
+// A coarse step of problems [p0, p1) with rejection: when the largest substep
+// Courant number of a problem exceeds cfl_max, every problem of the group is
+// put back (fine-level patch interiors, controls, counters, host bookkeeping;
+// level 0 keeps its input buffer through a step) and the step is retaken, the
+// failing problems with dt scaled by cfl_desired / that number, the others
+// unchanged.  Frames and uncovered cells of the finer levels are refilled or
+// unused before they are read again, so the backup leaves them out.
 int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
   int rc;
   const bool together = mode != MLSWE_PLAIN;
@@ -1602,8 +1607,6 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
   if (retry) {
     if ((rc = ensure(c, &c->ctl_bk, &c->bk_cap, nctl))) return rc;
     if ((rc = ensure(c, &c->cnt_bk, &c->cbk_cap, ncnt))) return rc;
-    HIPCHK(c, hipMemcpyAsync(c->ctl_bk, c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->cnt_bk, c->cnt, sizeof(Counters) * ncnt, hipMemcpyDeviceToDevice, c->stream));
     for (int p = p0; p < p1; ++p) {
       ProblemH& P = c->probs[p];
       for (int l = 0; l < P.nlev; ++l) {
@@ -1615,7 +1618,7 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
         if (!L.bk && (rc = dalloc(c, (void**)&L.bk, sb))) return rc;
       }
     }
-    if ((rc = copy_fine_levels(c, p0, p1, true))) return rc;
+    if ((rc = copy_step_start(c, p0, p1, true, nctl, ncnt))) return rc;
   }
   if (mode == MLSWE_GRAPH && c->probs[p0].have_dt && !c->timing)
     rc = graph_step(c, p0, p1);
@@ -1625,8 +1628,15 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
   const int np = p1 - p0;
   std::vector<double> dt0(np);
   for (int attempt = 0;; ++attempt) {
-    std::vector<LevelCtl> h(nctl);
-    HIPCHK(c, hipMemcpyAsync(h.data(), c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToHost, c->stream));
+    if ((size_t)nctl * sizeof(LevelCtl) > c->ctl_pin_cap) {
+      if (c->ctl_pin) (void)hipHostFree(c->ctl_pin);
+      c->ctl_pin = nullptr;
+      c->ctl_pin_cap = 0;
+      HIPCHK(c, hipHostMalloc((void**)&c->ctl_pin, 2 * (size_t)nctl * sizeof(LevelCtl), hipHostMallocDefault));
+      c->ctl_pin_cap = 2 * (size_t)nctl * sizeof(LevelCtl);
+    }
+    const LevelCtl* h = c->ctl_pin;  // pinned: the readback is one short DMA
+    HIPCHK(c, hipMemcpyAsync(c->ctl_pin, c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     bool any = false;
     for (int p = p0; p < p1; ++p) {
@@ -1650,8 +1660,6 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
     if (!any) return MLSWE_OK;
     if (attempt + 1 > c->cfg.max_retries) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
     // put the group back
-    HIPCHK(c, hipMemcpyAsync(c->ctl, c->ctl_bk, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->cnt, c->cnt_bk, sizeof(Counters) * ncnt, hipMemcpyDeviceToDevice, c->stream));
     size_t k = 0;
     for (int p = p0; p < p1; ++p) {
       ProblemH& P = c->probs[p];
@@ -1662,7 +1670,7 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
         P.updates[l] = upd0[k];
       }
     }
-    if ((rc = copy_fine_levels(c, p0, p1, false))) return rc;
+    if ((rc = copy_step_start(c, p0, p1, false, nctl, ncnt))) return rc;
     if ((rc = ensure(c, &c->dt0_d, &c->dt0_cap, np))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->dt0_d, dt0.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_set_dt0, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, c->dt0_d, np);
@@ -1705,11 +1713,9 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
         if ((rc = collect_events(c))) return rc;
       }
       if (dts_out) {
-        for (int p = p0; p < p1; ++p) {
-          LevelCtl h;
-          HIPCHK(c, hipMemcpy(&h, c->ctl + c->probs[p].ctl0, sizeof h, hipMemcpyDeviceToHost));
-          dts_out[(size_t)p * nsteps + n] = h.dt;
-        }
+        std::vector<LevelCtl> h;
+        if ((rc = read_ctls(c, p0, p1, h))) return rc;
+        for (int p = p0; p < p1; ++p) dts_out[(size_t)p * nsteps + n] = h[c->probs[p].ctl0 - c->probs[p0].ctl0].dt;
       }
     }
     int status = 0;
