@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <new>
 #include <string>
@@ -287,7 +288,8 @@ std::vector<Box> cluster_tiles(const LevelH& C, int r, const unsigned char* flag
 // 0 of flags (x) / last (y) marks a block whose successor to the right (x) or
 // above (y) is not kept, so that it owns the edge after its last column / row.
 // Returns the number of blocks kept; appends tiles when the vectors are given.
-long long run_blocks(const LevelH& L, int axis, int rows, int pdi, std::vector<XTile>* xo, std::vector<YTile>* yo) {
+long long run_blocks(const LevelH& L, int axis, int rows, int pdi, std::vector<XTile>* xo, std::vector<YTile>* yo,
+                     std::vector<int>* rows_out = nullptr) {
   const int w = axis == 0 ? XTILE_COLS : 64;
   const int ns = (L.nx + w - 1) / w;
   const int r0 = axis == 0 ? -2 : 0, hy = axis == 0 ? L.ny + 4 : L.ny;
@@ -305,6 +307,7 @@ long long run_blocks(const LevelH& L, int axis, int rows, int pdi, std::vector<X
       ++n;
       const int i0 = s * w, j0 = r0 + k * rows;
       const int ncol = std::min(w, L.nx - i0), nrow = std::min(rows, r0 + hy - j0);
+      if (rows_out) rows_out->push_back(nrow);
       if (axis == 0 && xo) {
         const bool next = s + 1 < ns && keep[(size_t)k * ns + s + 1];
         xo->push_back(XTile{pdi, i0, ncol, j0, nrow, next ? 0 : 1});
@@ -316,58 +319,78 @@ long long run_blocks(const LevelH& L, int axis, int rows, int pdi, std::vector<X
   return n;
 }
 
+// Completion time of tiles started in list order, each on the earliest free of
+// `slots` slots, a tile taking 4 time units per row plus `extra` (its start and,
+// for y, its halo rows).  Integer times: a count of slots freed at each time.
+long long tile_makespan(const std::vector<int>& rows, int extra, long long slots) {
+  if (rows.empty() || slots <= 0) return 0;
+  std::vector<long long> freed(256, 0);
+  freed[0] = slots;
+  size_t t = 0;
+  long long end = 0;
+  for (int r : rows) {
+    while (freed[t] == 0) ++t;
+    --freed[t];
+    const size_t done = t + (size_t)(4 * r + extra);
+    if (done >= freed.size()) freed.resize(2 * done + 1, 0);
+    ++freed[done];
+    end = std::max(end, (long long)done);
+  }
+  return end;
+}
+
 int build_launch(mlswe_ctx* c, int l) {
   LevelLaunch& LL = c->launch[l];
   if (!LL.dirty) return MLSWE_OK;
-  // Rows per sweep wave: the tuned value, or (0) the largest of 32 (x) / 128 (y)
-  // halved while the level's tiles, over every problem, would not fill the
-  // device with room to balance (x: two waves per SIMD, four rounds; y: one
-  // wave per SIMD, one round; four SIMDs per compute unit); never below 4 (x),
-  // where the start of a tile dominates, or 8 (y), where its halo rows do.
-  auto count_tiles = [&](int axis, int rows) {
-    long long n = 0;
+  // Rows per sweep wave: the tuned value, or (0) the candidate whose tiles, in
+  // launch order, finish first by the list-schedule model above, with 24 (x) /
+  // 16 (y) slots per compute unit (twice the lean kernels' resident waves: a
+  // SIMD's waves share it, so it balances finer than whole tiles) and a tile's
+  // start worth half a row (x) or its halo worth 2.5 rows (y), values fitted to
+  // sweep times of uniform grids, batches of uneven problems and their union
+  // tiles.  Ties keep the taller tiles.
+  const int xc[4] = {32, 16, 8, 4}, yc[5] = {128, 64, 32, 16, 8};
+  auto pick = [&](int axis, int tuned, const std::function<void(int, std::vector<int>&)>& rows_of) {
+    if (tuned > 0) return tuned;
+    const int* cand = axis == 0 ? xc : yc;
+    const int nc = axis == 0 ? 4 : 5;
+    const long long slots = (axis == 0 ? 24LL : 16LL) * c->ncu;
+    long long best = -1;
+    int br = cand[0];
+    std::vector<int> d;
+    for (int k = 0; k < nc; ++k) {
+      d.clear();
+      rows_of(cand[k], d);
+      const long long m = tile_makespan(d, axis == 0 ? 2 : 10, slots);
+      if (best < 0 || m < best) { best = m; br = cand[k]; }
+    }
+    return br;
+  };
+  auto patch_rows = [&](int axis, int rows, std::vector<int>& d) {
     for (const ProblemH& P : c->probs) {
       if (l >= P.nlev) continue;
       for (const Box& b : P.L[l].boxes) {
-        if (axis == 0) n += (long long)((b.nx + XTILE_COLS - 1) / XTILE_COLS) * ((b.ny + 4 + rows - 1) / rows);
-        else n += (long long)((b.nx + 63) / 64) * ((b.ny + rows - 1) / rows);
+        const int ns = axis == 0 ? (b.nx + XTILE_COLS - 1) / XTILE_COLS : (b.nx + 63) / 64;
+        const int h = axis == 0 ? b.ny + 4 : b.ny;
+        for (int s = 0; s < ns; ++s)
+          for (int j = 0; j < h; j += rows) d.push_back(std::min(rows, h - j));
       }
     }
-    return n;
   };
-  int xrows = c->tune.x_rows, yrows = c->tune.y_rows;
-  if (xrows <= 0) {
-    xrows = 32;
-    while (xrows > 4 && count_tiles(0, xrows) < 16LL * c->ncu) xrows /= 2;
-  }
-  if (yrows <= 0) {
-    yrows = 128;
-    while (yrows > 8 && count_tiles(1, yrows) < 4LL * c->ncu) yrows /= 2;
-  }
-  LL.rows_x = xrows;
-  LL.rows_y = yrows;
+  LL.rows_x = pick(0, c->tune.x_rows, [&](int r, std::vector<int>& d) { patch_rows(0, r, d); });
+  LL.rows_y = pick(1, c->tune.y_rows, [&](int r, std::vector<int>& d) { patch_rows(1, r, d); });
   // run tiles serve levels where some problem has several patches; their rows
   // follow the same rule over the run blocks
   LL.use_runs = false;
   for (const ProblemH& P : c->probs)
     if (l < P.nlev && P.L[l].boxes.size() > 1) LL.use_runs = true;
-  auto count_runs = [&](int axis, int rows) {
-    long long n = 0;
+  auto run_rows = [&](int axis, int rows, std::vector<int>& d) {
     for (const ProblemH& P : c->probs)
-      if (l < P.nlev && !P.L[l].boxes.empty()) n += run_blocks(P.L[l], axis, rows, 0, nullptr, nullptr);
-    return n;
+      if (l < P.nlev && !P.L[l].boxes.empty()) run_blocks(P.L[l], axis, rows, 0, nullptr, nullptr, &d);
   };
-  int xrows_r = c->tune.x_rows, yrows_r = c->tune.y_rows;
-  if (LL.use_runs && xrows_r <= 0) {
-    xrows_r = 32;
-    while (xrows_r > 4 && count_runs(0, xrows_r) < 16LL * c->ncu) xrows_r /= 2;
-  }
-  if (LL.use_runs && yrows_r <= 0) {
-    yrows_r = 128;
-    while (yrows_r > 8 && count_runs(1, yrows_r) < 4LL * c->ncu) yrows_r /= 2;
-  }
-  LL.rows_xr = LL.use_runs ? xrows_r : 0;
-  LL.rows_yr = LL.use_runs ? yrows_r : 0;
+  LL.rows_xr = LL.use_runs ? pick(0, c->tune.x_rows, [&](int r, std::vector<int>& d) { run_rows(0, r, d); }) : 0;
+  LL.rows_yr = LL.use_runs ? pick(1, c->tune.y_rows, [&](int r, std::vector<int>& d) { run_rows(1, r, d); }) : 0;
+  const int xrows = LL.rows_x, yrows = LL.rows_y;
   std::vector<PatchDev> pd[2];
   std::vector<XTile> xt;
   std::vector<YTile> yt;
