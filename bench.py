@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--amr-steps", type=int, default=16)
     ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--only", choices=("batch", "amr", "adjoint"), default=None,
+                    help="run only this extra measurement and print its JSON (for profiling)")
+    ap.add_argument("--modes", default="plain,batched,graph",
+                    help="launch modes of the batch / AMR measurements")
     return ap.parse_args()
 
 
@@ -69,7 +73,14 @@ def timed_advance(S, steps, every, tau, mode):
     return t1 - t0, after - before
 
 
-def bench_batch(nprob, steps, stream):
+def ratios(out, modes):
+    if "plain" in modes:
+        for m in ("batched", "graph"):
+            if m in modes:
+                out[m + "_vs_plain"] = out[m]["rate"] / out["plain"]["rate"]
+
+
+def bench_batch(nprob, steps, stream, modes=("plain", "batched", "graph")):
     """The batch of uneven problems (48..512 cells a side, two levels, ratio 2,
     regrid every 10 steps): plain per-problem launches against one launch per
     level substep over all problems (eager and graph-replayed)."""
@@ -81,6 +92,8 @@ def bench_batch(nprob, steps, stream):
     tau = np.tile([2e-5, 0.0], (nprob, 1))
     out = {}
     for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH)):
+        if name not in modes:
+            continue
         print("bench: batch %d problems, %s" % (nprob, name), file=sys.stderr, flush=True)
         S = Solver(stream=stream)
         for c in probs:
@@ -95,15 +108,14 @@ def bench_batch(nprob, steps, stream):
         if name == "batched":
             out["tuning"] = S.tuning()
         S.close()
-    out["batched_vs_plain"] = out["batched"]["rate"] / out["plain"]["rate"]
-    out["graph_vs_plain"] = out["graph"]["rate"] / out["plain"]["rate"]
+    ratios(out, modes)
     out["problems"] = nprob
     out["level0_cells"] = int(sum(int(n) ** 2 for n in sizes))
     out["coarse_steps"] = steps
     return out
 
 
-def bench_amr(steps, stream):
+def bench_amr(steps, stream, modes=("plain", "batched", "graph")):
     """Three levels (ratios 2 and 4) over 400 km with shorelines, 16 level-0
     patches of 64^2, regrid every 4 coarse steps."""
     import numpy as np
@@ -113,6 +125,8 @@ def bench_amr(steps, stream):
     tau = [[2e-6, 4e-6]]
     out = {}
     for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH)):
+        if name not in modes:
+            continue
         print("bench: AMR 3 levels, %s" % name, file=sys.stderr, flush=True)
         S = Solver(stream=stream)
         p = S.define(c["n0"], c["n0"], c["dx0"], c["dx0"], c["r"], c["ratios"])
@@ -124,8 +138,7 @@ def bench_amr(steps, stream):
         out[name] = {"seconds": sec, "cell_updates": upd, "rate": upd / sec,
                      "finest_patches": int(len(S.patches(p, 2)))}
         S.close()
-    out["batched_vs_plain"] = out["batched"]["rate"] / out["plain"]["rate"]
-    out["graph_vs_plain"] = out["graph"]["rate"] / out["plain"]["rate"]
+    ratios(out, modes)
     out["coarse_steps"] = steps
     return out
 
@@ -235,6 +248,17 @@ def main():
         sys.exit(3)
     torch.cuda.init()
     stream = torch.cuda.current_stream()
+    if args.only:
+        modes = tuple(args.modes.split(","))
+        st = stream.cuda_stream
+        if args.only == "batch":
+            res = bench_batch(args.batch_problems, args.batch_steps, st, modes)
+        elif args.only == "amr":
+            res = bench_amr(args.amr_steps, st, modes)
+        else:
+            res = bench_adjoint(args.adjoint_steps, st)
+        print(json.dumps({args.only: res}))
+        return
     print("bench: generating %dx%d roofline grid" % (args.n, args.n), file=sys.stderr, flush=True)
     c = inputs.roofline_grid(n=args.n, L=409.6e3 * args.n / 4096)
     n = c["n"]
