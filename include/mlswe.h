@@ -251,6 +251,18 @@ int mlswe_gauge_misfit(mlswe_ctx* ctx, int p, const double* q, int i0, int j0, i
  * difference between them sees a smooth map.  Synchronises when reading. */
 int mlswe_branch_signature(mlswe_ctx* ctx, int enable, int p, uint64_t* sig_out);
 
+/* The union ("run") tiles a batched substep sweeps for one level of one
+ * problem (host only, no GPU needed; for inspection and tests).  The level is
+ * nx x ny cells with nbox patch boxes (ilo, jlo, nx, ny; int32, host memory,
+ * as for mlswe_set_patches, unchecked beyond lying inside the level).  axis 0:
+ * x-sweep blocks of 60 columns by `rows` rows counted from row -2 over the
+ * patches' rows and two frame rows on each side; axis 1: y-sweep blocks of 64
+ * columns by `rows` interior rows.  Writes up to cap tiles of five int32 each
+ * to out: i0, ncols, j0, nrows, flags (bit 0: the tile owns the edge after its
+ * last column (x) or row (y)), in launch order, and returns the number of
+ * tiles (which may exceed cap), or MLSWE_EINVAL. */
+int mlswe_run_tiles(int nx, int ny, int nbox, const int32_t* boxes, int axis, int rows, int32_t* out, int cap);
+
 #ifdef __cplusplus
 }
 #endif

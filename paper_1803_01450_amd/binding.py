@@ -92,6 +92,7 @@ def lib():
             "mlswe_get_tuning": (I, [P, ctypes.POINTER(Tuning)]),
             "mlswe_set_tuning": (I, [P, ctypes.POINTER(Tuning)]),
             "mlswe_autotune": (I, [P, ctypes.c_char_p, I]),
+            "mlswe_run_tiles": (I, [I, I, I, I32P, I, I, I32P, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -99,6 +100,20 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def run_tiles(nx, ny, boxes, axis, rows):
+    """The union tiles of one level (host only): rows of (i0, ncols, j0, nrows,
+    flags) in launch order."""
+    L = lib()
+    b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 4))
+    bp = b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    n = L.mlswe_run_tiles(nx, ny, b.shape[0], bp, axis, rows, None, 0)
+    if n < 0:
+        raise MlsweError(n, "bad run-tile arguments")
+    out = np.zeros((max(n, 1), 5), dtype=np.int32)
+    L.mlswe_run_tiles(nx, ny, b.shape[0], bp, axis, rows, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n)
+    return out[:n]
 
 
 def _f64(a):

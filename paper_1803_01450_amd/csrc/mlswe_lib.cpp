@@ -1911,6 +1911,31 @@ extern "C" int mlswe_adjoint_step(mlswe_ctx* c, int p, const double* q_n, const 
   return MLSWE_OK;
 }
 
+extern "C" int mlswe_run_tiles(int nx, int ny, int nbox, const int32_t* boxes, int axis, int rows, int32_t* out,
+                               int cap) {
+  if (nx <= 0 || ny <= 0 || nbox < 0 || (nbox > 0 && !boxes) || (axis != 0 && axis != 1) || rows <= 0 || cap < 0 ||
+      (cap > 0 && !out))
+    return MLSWE_EINVAL;
+  LevelH L;
+  L.nx = nx;
+  L.ny = ny;
+  for (int k = 0; k < nbox; ++k) {
+    Box b{boxes[4 * k], boxes[4 * k + 1], boxes[4 * k + 2], boxes[4 * k + 3]};
+    if (b.nx <= 0 || b.ny <= 0 || b.ilo < 0 || b.jlo < 0 || b.ilo + b.nx > nx || b.jlo + b.ny > ny) return MLSWE_EINVAL;
+    L.boxes.push_back(b);
+  }
+  std::vector<XTile> xt;
+  std::vector<YTile> yt;
+  run_blocks(L, axis, rows, 0, axis == 0 ? &xt : nullptr, axis == 1 ? &yt : nullptr);
+  const size_t n = axis == 0 ? xt.size() : yt.size();
+  for (size_t k = 0; k < n && k < (size_t)cap; ++k) {
+    int32_t* o = out + 5 * k;
+    if (axis == 0) { o[0] = xt[k].i0; o[1] = xt[k].ncols; o[2] = xt[k].j0; o[3] = xt[k].nrows; o[4] = xt[k].flags; }
+    else { o[0] = yt[k].i0; o[1] = yt[k].ncols; o[2] = yt[k].j0; o[3] = yt[k].nrows; o[4] = yt[k].last; }
+  }
+  return (int)n;
+}
+
 extern "C" int mlswe_branch_signature(mlswe_ctx* c, int enable, int p, uint64_t* sig_out) {
   if (!c) return MLSWE_EINVAL;
   if (enable >= 0 && (enable ? 1 : 0) != c->sig_on) {
