@@ -120,3 +120,37 @@ def test_single_patch_levels_keep_patch_tiles():
     a, b = gpu_run(0, boxes=box), gpu_run(1, boxes=box)
     same_states(a["states"], b["states"])
     assert a["counters"]["hyp"] == b["counters"]["hyp"]
+
+
+def test_odd_first_columns_through_registers():
+    """Level-0 patches with an odd first column: their patch tiles (plain
+    launches) take the rows through registers, the union tiles (batched) through
+    LDS copies; both match each other bit for bit and the oracle."""
+    from paper_1803_01450_amd.binding import Solver
+    say("case: level-0 patches at columns 0 and 33, plain vs batched vs oracle")
+    c = inputs.fixed_small()
+    boxes = [(0, 0, 33, 40), (33, 0, 31, 40), (0, 40, 17, 24), (17, 40, 47, 24)]
+    out = []
+    for mode in (0, 1):
+        S = Solver()
+        p = S.define(64, 64, c["dx"], c["dx"], c["r"])
+        S.set_bathymetry(p, c["B"])
+        S.set_patches(p, 0, boxes)
+        S.set_state(p, 0, c["q"])
+        dts = S.advance(20, want_dts=True, mode=mode)
+        out.append((S.state(p, 0), S.counters(p), dts[0]))
+        S.close()
+    (a, ca, da), (b, cb, db) = out
+    assert np.array_equal(a, b) and np.array_equal(da, db)
+    assert ca["nclip"] == cb["nclip"] and ca["hyp"] == cb["hyp"]
+    H = oracle.Hierarchy(64, 64, c["dx"], c["dx"], r=c["r"])
+    H.set_bathymetry(c["B"])
+    H.set_patches(0, boxes)
+    H.set_state(0, c["q"])
+    rc, rdts = H.advance(20)
+    assert rc == 0
+    err = rel_err(a, H.state(0))
+    say("rel err", err.max(), "dt diff", np.abs(da - rdts).max())
+    assert err.max() <= 1e-9
+    assert np.abs(da - rdts).max() <= 1e-12 * rdts.max()
+    assert ca["hyp"] == H.counters()["hyp"] and ca["nclip"] == H.counters()["nclip"]
