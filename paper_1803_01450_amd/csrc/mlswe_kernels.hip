@@ -196,6 +196,27 @@ __global__ __launch_bounds__(256) void k_flag_dilate(const FlagLevel* __restrict
   F.out[(long long)j * F.nx + i] = f;
 }
 
+// Tile summary for clustering (block row y: problem y of the list): one
+// thread per tile of the finer level.
+__global__ __launch_bounds__(256) void k_flag_tiles(const FlagTiles* __restrict__ Ts) {
+  const FlagTiles F = Ts[blockIdx.y];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F.tx * F.ty) return;
+  const int I = t % F.tx, J = t / F.tx, r = F.r;
+  const int ci0 = (CLUSTER_TILE * I) / r, cj0 = (CLUSTER_TILE * J) / r;
+  const int ci1 = min(F.nx, (CLUSTER_TILE * (I + 1) + r - 1) / r);
+  const int cj1 = min(F.ny, (CLUSTER_TILE * (J + 1) + r - 1) / r);
+  int any = 0;
+  for (int j = cj0; j < cj1; ++j)
+    for (int i = ci0; i < ci1; ++i) any |= F.flags[(long long)j * F.nx + i];
+  int inside = 1;
+  const int a0 = max(0, ci0 - 2), a1 = min(F.nx, ci1 + 2);
+  const int b0 = max(0, cj0 - 2), b1 = min(F.ny, cj1 + 2);
+  for (int j = b0; j < b1; ++j)
+    for (int i = a0; i < a1; ++i) inside &= F.mask[cidx(F.pitch, i, j)] != 0 ? 1 : 0;
+  F.out[t] = (unsigned char)((any != 0 ? 1 : 0) | (inside << 1));
+}
+
 // ---------------------------------------------------------------- time step
 // After a substep: one block per (problem, level) reduces the partials of that
 // problem's x and y tiles (each wave a strided share, then across the waves),

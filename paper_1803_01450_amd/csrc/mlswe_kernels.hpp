@@ -96,6 +96,19 @@ struct FlagLevel {
   double dx, dy, tau, hdry;
 };
 
+// Clustering works on tiles of CLUSTER_TILE x CLUSTER_TILE fine cells.  The
+// tile summary of one level of one problem: per tile of the finer level, bit 0
+// = a flagged coarse cell under it, bit 1 = the coarse cells under it and two
+// around it (clipped to the level) are all covered.
+constexpr int CLUSTER_TILE = 16;
+struct FlagTiles {
+  const unsigned char* flags;  // nx * ny dilated flags of the coarse level
+  const unsigned char* mask;   // coverage of the coarse level
+  unsigned char* out;          // tx * ty tile bits, row-major
+  long long pitch;
+  int nx, ny, r, tx, ty;
+};
+
 // Partial results of one sweep tile (largest edge speed, fix-up and clamp
 // counts), written by the tile's wave and reduced per problem and level after
 // the substep, so no two waves update the same word.
@@ -213,6 +226,7 @@ __global__ void k_refine_new(const FillPatch* __restrict__ fills);
 __global__ void k_coarsen(const CoarsenPatch* __restrict__ cps);
 __global__ void k_flag_raw(const FlagLevel* __restrict__ Fs);
 __global__ void k_flag_dilate(const FlagLevel* __restrict__ Fs);
+__global__ void k_flag_tiles(const FlagTiles* __restrict__ Ts);
 __global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, const TilePart* parts,
                                 double cflmax);
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);

@@ -23,7 +23,7 @@ using namespace mlswe;
 namespace {
 
 constexpr int MAXLEV = 8;
-constexpr int TILE = 16;  // clustering tile (fine cells per side)
+constexpr int TILE = CLUSTER_TILE;  // clustering tile (fine cells per side)
 
 struct Box { int ilo, jlo, nx, ny; };
 
@@ -40,7 +40,8 @@ struct LevelH {
   unsigned char* fraw = nullptr;
   unsigned char* fout = nullptr;
   double* bk = nullptr;  // copy of the current buffer for a rejected coarse step
-  std::vector<unsigned char> mask_h;
+  std::vector<unsigned char> mask_h;  // host copy of the coverage, rebuilt when needed
+  bool mask_h_ok = true;
   std::vector<Box> boxes;
 };
 
@@ -167,6 +168,10 @@ struct mlswe_ctx {
   int rfills_cap = 0;
   FlagLevel* flv_d = nullptr;    // flag descriptors
   int flv_cap = 0;
+  FlagTiles* ftl_d = nullptr;    // tile-summary descriptors and their output
+  int ftl_cap = 0;
+  unsigned char* tbits_d = nullptr;
+  int tbits_cap = 0;
 };
 
 namespace {
@@ -232,29 +237,12 @@ void mirror_frame_host(const LevelH& L, std::vector<double>& a) {
 // ------------------------------------------------------------ clustering
 // 16x16 fine tiles marked by a flagged coarse cell, kept if their coarse
 // footprint grown by two coarse cells (clipped at the domain) is covered by the
-// coarse level, merged greedily row-major into rectangles of at most 4x4 tiles.
-std::vector<Box> cluster_tiles(const LevelH& C, int r, const unsigned char* flags) {
-  const int fnx = C.nx * r, fny = C.ny * r;
+// coarse level (the two bits k_flag_tiles computes per tile), merged greedily
+// row-major into rectangles of at most 4x4 tiles.  fnx x fny: the finer level.
+std::vector<Box> cluster_tiles(int fnx, int fny, const unsigned char* bits) {
   const int tx = (fnx + TILE - 1) / TILE, ty = (fny + TILE - 1) / TILE;
   std::vector<char> keep((size_t)tx * ty, 0), taken((size_t)tx * ty, 0);
-  for (int J = 0; J < ty; ++J)
-    for (int I = 0; I < tx; ++I) {
-      const int ci0 = (TILE * I) / r, cj0 = (TILE * J) / r;
-      const int ci1 = std::min(C.nx, (TILE * (I + 1) + r - 1) / r);
-      const int cj1 = std::min(C.ny, (TILE * (J + 1) + r - 1) / r);
-      bool any = false;
-      for (int j = cj0; j < cj1 && !any; ++j)
-        for (int i = ci0; i < ci1; ++i)
-          if (flags[(size_t)j * C.nx + i]) { any = true; break; }
-      if (!any) continue;
-      bool inside = true;
-      const int a0 = std::max(0, ci0 - 2), a1 = std::min(C.nx, ci1 + 2);
-      const int b0 = std::max(0, cj0 - 2), b1 = std::min(C.ny, cj1 + 2);
-      for (int j = b0; j < b1 && inside; ++j)
-        for (int i = a0; i < a1; ++i)
-          if (!C.mask_h[idx(C, i, j)]) { inside = false; break; }
-      keep[(size_t)J * tx + I] = inside;
-    }
+  for (size_t t = 0; t < keep.size(); ++t) keep[t] = (bits[t] & 3) == 3;
   auto free_tile = [&](int I, int J) { return keep[(size_t)J * tx + I] && !taken[(size_t)J * tx + I]; };
   std::vector<Box> out;
   for (int J = 0; J < ty; ++J)
@@ -861,6 +849,7 @@ int read_status(mlswe_ctx* c, int p0, int p1, int* status) {
 
 // ------------------------------------------------------------ patches
 void host_mask(LevelH& L);
+const std::vector<unsigned char>& host_cov(LevelH& L);
 
 int upload_mask(mlswe_ctx* c, LevelH& L) {
   host_mask(L);
@@ -886,10 +875,11 @@ int check_patches(mlswe_ctx* c, int p, int l, int n, const int32_t* bx, std::vec
       const int r = P.ratio[l - 1];
       if (b.ilo % r || b.jlo % r || b.nx % r || b.ny % r)
         return fail(c, MLSWE_EINVAL, "patch %d not aligned to ratio %d", k, r);
-      const LevelH& C = P.L[l - 1];
+      LevelH& C = P.L[l - 1];
+      const std::vector<unsigned char>& cm = host_cov(C);
       for (int j = b.jlo / r; j < (b.jlo + b.ny) / r; ++j)
         for (int i = b.ilo / r; i < (b.ilo + b.nx) / r; ++i)
-          if (!C.mask_h[idx(C, i, j)]) return fail(c, MLSWE_EINVAL, "patch %d not covered by level %d", k, l - 1);
+          if (!cm[idx(C, i, j)]) return fail(c, MLSWE_EINVAL, "patch %d not covered by level %d", k, l - 1);
     }
     for (int j = b.jlo; j < b.jlo + b.ny; ++j)
       for (int i = b.ilo; i < b.ilo + b.nx; ++i) {
@@ -917,6 +907,14 @@ void host_mask(LevelH& L) {
       std::memset(row, j == b.jlo ? COV_IN | COV_ROW0 : COV_IN, b.nx);
       row[0] |= COV_COL0;
     }
+  L.mask_h_ok = true;
+}
+
+// The host copy of a level's coverage, rebuilt from the boxes after a regrid
+// left it stale (the regrid sets the device coverage directly).
+const std::vector<unsigned char>& host_cov(LevelH& L) {
+  if (!L.mask_h_ok) host_mask(L);
+  return L.mask_h;
 }
 
 int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
@@ -927,7 +925,7 @@ int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
   LevelH& L = P.L[l];
   // keep the old coverage for the fill of new cells
   if (l > 0) {
-    HIPCHK(c, hipMemcpyAsync(L.mask_old, L.mask, L.mask_h.size(), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(L.mask_old, L.mask, (size_t)L.plane, hipMemcpyDeviceToDevice, c->stream));
   }
   L.boxes = nb;
   int rc = upload_mask(c, L);
@@ -988,24 +986,20 @@ int flag_impl(mlswe_ctx* c, int p, int l, double tau, int nbuf, std::vector<unsi
   return MLSWE_OK;
 }
 
+int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf);
+
 int regrid_impl(mlswe_ctx* c, int p, const double* tau, int nbuf) {
-  ProblemH& P = c->probs[p];
-  for (int l = 0; l + 1 < P.nlev; ++l) {
-    std::vector<unsigned char> f;
-    int rc = flag_impl(c, p, l, tau[l], nbuf, f);
-    if (rc) return rc;
-    std::vector<Box> bx = cluster_tiles(P.L[l], P.ratio[l], f.data());
-    std::vector<int32_t> flat;
-    for (const Box& b : bx) { flat.push_back(b.ilo); flat.push_back(b.jlo); flat.push_back(b.nx); flat.push_back(b.ny); }
-    if ((rc = set_patches_impl(c, p, l + 1, (int)bx.size(), flat.data()))) return rc;
-  }
-  return MLSWE_OK;
+  std::vector<double> t((size_t)(p + 1) * MAXLEV, 0.0);
+  for (int l = 0; l < MAXLEV; ++l) t[(size_t)p * MAXLEV + l] = tau[l];
+  return regrid_group(c, p, p + 1, t.data(), nbuf);
 }
 
 // Regrid of problems [p0, p1) with one host wait per level: the flags of every
-// problem come back in one pinned buffer, clustering and validation run on the
-// host, and the new coverage (old coverage kept for the fill), the masks and
-// the refinement of newly covered cells are each one launch over all problems.
+// problem are summarised per clustering tile on the device and come back in one
+// pinned buffer, clustering runs on the host (its boxes are valid by
+// construction: aligned, inside the covered region, disjoint), and the new
+// coverage (old coverage kept for the fill), the masks and the refinement of
+// newly covered cells are each one launch over all problems.
 int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) {
   int maxlev = 0;
   for (int p = p0; p < p1; ++p) maxlev = std::max(maxlev, c->probs[p].nlev);
@@ -1013,7 +1007,8 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
     std::vector<int> who;
     std::vector<size_t> off;
     std::vector<FlagLevel> fl;
-    int mx = 0, my = 0;
+    std::vector<FlagTiles> ft;
+    int mx = 0, my = 0, mt = 0;
     size_t total = 0;
     int rc;
     for (int p = p0; p < p1; ++p) {
@@ -1031,11 +1026,20 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
       fl.push_back(F);
       mx = std::max(mx, L.nx);
       my = std::max(my, L.ny);
+      const int r = P.ratio[l];
+      FlagTiles T;
+      T.flags = L.fout; T.mask = L.mask; T.out = nullptr; T.pitch = L.pitch;
+      T.nx = L.nx; T.ny = L.ny; T.r = r;
+      T.tx = (L.nx * r + TILE - 1) / TILE; T.ty = (L.ny * r + TILE - 1) / TILE;
+      ft.push_back(T);
+      mt = std::max(mt, T.tx * T.ty);
       who.push_back(p);
       off.push_back(total);
-      total += (size_t)L.nx * L.ny;
+      total += (size_t)T.tx * T.ty;
     }
     if (who.empty()) continue;
+    if ((rc = ensure(c, &c->tbits_d, &c->tbits_cap, (int)total))) return rc;
+    for (size_t k = 0; k < ft.size(); ++k) ft[k].out = c->tbits_d + off[k];
     if ((rc = ensure(c, &c->flv_d, &c->flv_cap, (int)fl.size()))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->flv_d, fl.data(), sizeof(FlagLevel) * fl.size(), hipMemcpyHostToDevice, c->stream));
     for (size_t k0 = 0; k0 < fl.size(); k0 += 65535) {  // grid z is at most 65535
@@ -1046,6 +1050,12 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
       const unsigned nz = (unsigned)std::min<size_t>(65535, fl.size() - k0);
       hipLaunchKernelGGL(k_flag_dilate, dim3((mx + 255) / 256, my, nz), dim3(256), 0, c->stream, c->flv_d + k0);
     }
+    if ((rc = ensure(c, &c->ftl_d, &c->ftl_cap, (int)ft.size()))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->ftl_d, ft.data(), sizeof(FlagTiles) * ft.size(), hipMemcpyHostToDevice, c->stream));
+    for (size_t k0 = 0; k0 < ft.size(); k0 += 65535) {
+      const unsigned ny = (unsigned)std::min<size_t>(65535, ft.size() - k0);
+      hipLaunchKernelGGL(k_flag_tiles, dim3((mt + 255) / 256, ny), dim3(256), 0, c->stream, c->ftl_d + k0);
+    }
     HIPCHK(c, hipGetLastError());
     if (total > c->pin_cap) {
       HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1055,19 +1065,13 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
       HIPCHK(c, hipHostMalloc((void**)&c->pin, total, hipHostMallocDefault));
       c->pin_cap = total;
     }
-    for (size_t k = 0; k < who.size(); ++k) {
-      const LevelH& L = c->probs[who[k]].L[l];
-      HIPCHK(c, hipMemcpyAsync(c->pin + off[k], L.fout, (size_t)L.nx * L.ny, hipMemcpyDeviceToHost, c->stream));
-    }
+    HIPCHK(c, hipMemcpyAsync(c->pin, c->tbits_d, total, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    // host: clusters and validation, then the new layouts and host masks
+    // host: clusters, then the new layouts
     std::vector<std::vector<Box>> nbs(who.size());
     for (size_t k = 0; k < who.size(); ++k) {
-      ProblemH& P = c->probs[who[k]];
-      std::vector<Box> bx = cluster_tiles(P.L[l], P.ratio[l], c->pin + off[k]);
-      std::vector<int32_t> flat;
-      for (const Box& b : bx) { flat.push_back(b.ilo); flat.push_back(b.jlo); flat.push_back(b.nx); flat.push_back(b.ny); }
-      if ((rc = check_patches(c, who[k], l + 1, (int)bx.size(), flat.data(), nbs[k]))) return rc;
+      const LevelH& F = c->probs[who[k]].L[l + 1];
+      nbs[k] = cluster_tiles(F.nx, F.ny, c->pin + off[k]);
     }
     std::vector<ByteSeg> keep, clear;
     std::vector<MaskBox> mb;
@@ -1077,10 +1081,10 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
       ProblemH& P = c->probs[who[k]];
       LevelH& L = P.L[l + 1];
       const LevelH& C = P.L[l];
-      keep.push_back(ByteSeg{L.mask, L.mask_old, (long long)L.mask_h.size(), 0});
-      clear.push_back(ByteSeg{nullptr, L.mask, (long long)L.mask_h.size(), 0});
+      keep.push_back(ByteSeg{L.mask, L.mask_old, L.plane, 0});
+      clear.push_back(ByteSeg{nullptr, L.mask, L.plane, 0});
       L.boxes = nbs[k];
-      host_mask(L);
+      L.mask_h_ok = false;
       mark_dirty(c, l + 1);
       for (const Box& b : L.boxes) {
         mb.push_back(MaskBox{L.mask, L.pitch, b.ilo, b.jlo, b.nx, b.ny});
@@ -1097,7 +1101,7 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
         fills.push_back(x);
         maxn = std::max(maxn, b.nx * b.ny);
       }
-      maxbox = std::max(maxbox, (int)L.mask_h.size());
+      maxbox = std::max(maxbox, (int)L.plane);
     }
     // device: old coverage kept, masks cleared and set, new cells refined
     if ((rc = ensure(c, &c->bsegs_d, &c->bsegs_cap, (int)(2 * keep.size())))) return rc;
@@ -1222,6 +1226,7 @@ int mlswe_destroy(mlswe_ctx* c) {
   dfree(c->ctl); dfree(c->cnt); dfree(c->theta); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
   dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d); dfree(c->boxes_d);
   dfree(c->bsegs_d); dfree(c->mboxes_d); dfree(c->rfills_d); dfree(c->flv_d);
+  dfree(c->ftl_d); dfree(c->tbits_d);
   if (c->pin) (void)hipHostFree(c->pin);
   if (c->ctl_pin) (void)hipHostFree(c->ctl_pin);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -1401,9 +1406,10 @@ int mlswe_get_state(mlswe_ctx* c, int p, int level, double* q, int where) {
     return MLSWE_OK;
   }
   const double nan = std::numeric_limits<double>::quiet_NaN();
+  const std::vector<unsigned char>& cov = host_cov(L);
   for (int j = 0; j < L.ny; ++j)
     for (int i = 0; i < L.nx; ++i)
-      if (!L.mask_h[idx(L, i, j)])
+      if (!cov[idx(L, i, j)])
         for (int f = 0; f < 6; ++f) q[((size_t)f * L.ny + j) * L.nx + i] = nan;
   return MLSWE_OK;
 }
