@@ -365,13 +365,38 @@ int build_launch(mlswe_ctx* c, int l) {
       }
     }
   };
-  LL.rows_x = pick(0, c->tune.x_rows, [&](int r, std::vector<int>& d) { patch_rows(0, r, d); });
-  LL.rows_y = pick(1, c->tune.y_rows, [&](int r, std::vector<int>& d) { patch_rows(1, r, d); });
   // run tiles serve levels where some problem has several patches; their rows
-  // follow the same rule over the run blocks
+  // follow the same rule over the run blocks.  The patch tiles of such a level
+  // serve only plain launches and persistent schedules: their rows come from
+  // the cheaper rule of halving 32 (x) / 128 (y) while the tiles would not fill
+  // the device (x: four rounds of three waves per SIMD, y: one round of two).
   LL.use_runs = false;
+  size_t npatch = 0;
   for (const ProblemH& P : c->probs)
-    if (l < P.nlev && P.L[l].boxes.size() > 1) LL.use_runs = true;
+    if (l < P.nlev) {
+      if (P.L[l].boxes.size() > 1) LL.use_runs = true;
+      npatch += P.L[l].boxes.size();
+    }
+  auto halve = [&](int axis, int tuned) {
+    if (tuned > 0) return tuned;
+    int rows = axis == 0 ? 32 : 128;
+    const long long want = (axis == 0 ? 48LL : 8LL) * c->ncu;
+    std::vector<int> d;
+    while (rows > (axis == 0 ? 4 : 8)) {
+      d.clear();
+      patch_rows(axis, rows, d);
+      if ((long long)d.size() >= want) break;
+      rows /= 2;
+    }
+    return rows;
+  };
+  if (LL.use_runs) {
+    LL.rows_x = halve(0, c->tune.x_rows);
+    LL.rows_y = halve(1, c->tune.y_rows);
+  } else {
+    LL.rows_x = pick(0, c->tune.x_rows, [&](int r, std::vector<int>& d) { patch_rows(0, r, d); });
+    LL.rows_y = pick(1, c->tune.y_rows, [&](int r, std::vector<int>& d) { patch_rows(1, r, d); });
+  }
   auto run_rows = [&](int axis, int rows, std::vector<int>& d) {
     for (const ProblemH& P : c->probs)
       if (l < P.nlev && !P.L[l].boxes.empty()) run_blocks(P.L[l], axis, rows, 0, nullptr, nullptr, &d);
@@ -386,6 +411,11 @@ int build_launch(mlswe_ctx* c, int l) {
   std::vector<CoarsenPatch> cp[4];
   std::vector<LevelInfo> li;
   LL.patch_prob.clear(); LL.xr.clear(); LL.yr.clear();
+  for (int par = 0; par < 2; ++par) pd[par].reserve(npatch + c->probs.size());
+  for (int k = 0; k < 4; ++k) { fp[k].reserve(npatch); cp[k].reserve(npatch); }
+  LL.patch_prob.reserve(npatch); LL.xr.reserve(npatch); LL.yr.reserve(npatch);
+  xt.reserve(8 * npatch); yt.reserve(4 * npatch);
+  li.reserve(c->probs.size());
   LL.fill_first.assign(c->probs.size(), -1);
   LL.fill_count.assign(c->probs.size(), 0);
   LL.li_first.assign(c->probs.size(), -1);
@@ -431,32 +461,37 @@ int build_launch(mlswe_ctx* c, int l) {
       }
       LL.xr.push_back({x0, (int)xt.size() - x0});
       LL.yr.push_back({y0, (int)yt.size() - y0});
+      // fill and coarsen descriptors for the four buffer parities (fine, coarse)
+      FillPatch f;
+      std::memset(&f, 0, sizeof f);
+      f.B = L.B; f.mask = L.mask;
+      f.theta = c->theta + l;
+      f.cnt = c->cnt + P.cnt;
+      f.pitch = L.pitch; f.plane = L.plane;
+      f.nx = L.nx; f.ny = L.ny;
+      f.ilo = b.ilo; f.jlo = b.jlo; f.bnx = b.nx; f.bny = b.ny;
+      f.P = P.P;
+      CoarsenPatch cc;
+      std::memset(&cc, 0, sizeof cc);
+      const LevelH* Cl = l > 0 ? &P.L[l - 1] : nullptr;
+      if (Cl) {
+        f.Bc = Cl->B;
+        f.cpitch = Cl->pitch; f.cplane = Cl->plane; f.ncx = Cl->nx; f.ncy = Cl->ny;
+        f.r = P.ratio[l - 1];
+        f.coarse_none = 0;
+        cc.fpitch = L.pitch; cc.fplane = L.plane; cc.cpitch = Cl->pitch; cc.cplane = Cl->plane;
+        cc.ilo = b.ilo; cc.jlo = b.jlo; cc.bnx = b.nx; cc.bny = b.ny; cc.r = P.ratio[l - 1];
+        cc.P = P.P;
+      } else {
+        f.coarse_none = 1;
+        f.r = 1;
+      }
       for (int fpar = 0; fpar < 2; ++fpar)
         for (int cpar = 0; cpar < 2; ++cpar) {
-          FillPatch f;
-          std::memset(&f, 0, sizeof f);
-          f.q = L.q[fpar]; f.B = L.B; f.mask = L.mask;
-          f.theta = c->theta + l;
-          f.cnt = c->cnt + P.cnt;
-          f.pitch = L.pitch; f.plane = L.plane;
-          f.nx = L.nx; f.ny = L.ny;
-          f.ilo = b.ilo; f.jlo = b.jlo; f.bnx = b.nx; f.bny = b.ny;
-          f.P = P.P;
-          CoarsenPatch cc;
-          std::memset(&cc, 0, sizeof cc);
-          if (l > 0) {
-            const LevelH& Cl = P.L[l - 1];
-            f.qco = Cl.q[1 - cpar]; f.qcn = Cl.q[cpar]; f.Bc = Cl.B;
-            f.cpitch = Cl.pitch; f.cplane = Cl.plane; f.ncx = Cl.nx; f.ncy = Cl.ny;
-            f.r = P.ratio[l - 1];
-            f.coarse_none = 0;
-            cc.qf = L.q[fpar]; cc.qc = Cl.q[cpar];
-            cc.fpitch = L.pitch; cc.fplane = L.plane; cc.cpitch = Cl.pitch; cc.cplane = Cl.plane;
-            cc.ilo = b.ilo; cc.jlo = b.jlo; cc.bnx = b.nx; cc.bny = b.ny; cc.r = P.ratio[l - 1];
-            cc.P = P.P;
-          } else {
-            f.coarse_none = 1;
-            f.r = 1;
+          f.q = L.q[fpar];
+          if (Cl) {
+            f.qco = Cl->q[1 - cpar]; f.qcn = Cl->q[cpar];
+            cc.qf = L.q[fpar]; cc.qc = Cl->q[cpar];
           }
           fp[fpar * 2 + cpar].push_back(f);
           cp[fpar * 2 + cpar].push_back(cc);
