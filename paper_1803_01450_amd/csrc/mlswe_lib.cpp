@@ -97,6 +97,8 @@ struct LevelLaunch {
   CoarsenPatch* cp[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<int> fill_first;               // per problem: first fill entry (or -1) and count
   std::vector<int> fill_count;
+  std::vector<int> crs_first, crs_count;     // per problem: coarsen entries (row chunks of patches)
+  int ncrs = 0, cap_cp = 0;
   LevelInfo* li = nullptr;                   // ctl / dx / dy of every problem having the level; four
                                              // copies (x ranges of patch / run tiles, times y ranges)
   int nli = 0;
@@ -418,6 +420,8 @@ int build_launch(mlswe_ctx* c, int l) {
   li.reserve(c->probs.size());
   LL.fill_first.assign(c->probs.size(), -1);
   LL.fill_count.assign(c->probs.size(), 0);
+  LL.crs_first.assign(c->probs.size(), -1);
+  LL.crs_count.assign(c->probs.size(), 0);
   LL.li_first.assign(c->probs.size(), -1);
   for (size_t pi = 0; pi < c->probs.size(); ++pi) {
     ProblemH& P = c->probs[pi];
@@ -431,6 +435,7 @@ int build_launch(mlswe_ctx* c, int l) {
     if (L.boxes.empty()) continue;
     LL.fill_first[pi] = (int)fp[0].size();
     LL.fill_count[pi] = (int)L.boxes.size();
+    LL.crs_first[pi] = (int)cp[0].size();
     for (const Box& b : L.boxes) {
       const int id = (int)pd[0].size();
       for (int par = 0; par < 2; ++par) {
@@ -489,14 +494,26 @@ int build_launch(mlswe_ctx* c, int l) {
       for (int fpar = 0; fpar < 2; ++fpar)
         for (int cpar = 0; cpar < 2; ++cpar) {
           f.q = L.q[fpar];
-          if (Cl) {
-            f.qco = Cl->q[1 - cpar]; f.qcn = Cl->q[cpar];
-            cc.qf = L.q[fpar]; cc.qc = Cl->q[cpar];
-          }
+          if (Cl) { f.qco = Cl->q[1 - cpar]; f.qcn = Cl->q[cpar]; }
           fp[fpar * 2 + cpar].push_back(f);
-          cp[fpar * 2 + cpar].push_back(cc);
         }
+      // coarsening in chunks of whole coarse rows, about 256 coarse cells each,
+      // so that every block of its launch has work
+      if (Cl) {
+        const int r = P.ratio[l - 1], cnx = b.nx / r, cny = b.ny / r;
+        const int rows = std::max(1, 256 / std::max(1, cnx));
+        for (int j = 0; j < cny; j += rows) {
+          cc.jlo = b.jlo + j * r;
+          cc.bny = std::min(rows, cny - j) * r;
+          for (int fpar = 0; fpar < 2; ++fpar)
+            for (int cpar = 0; cpar < 2; ++cpar) {
+              cc.qf = L.q[fpar]; cc.qc = Cl->q[cpar];
+              cp[fpar * 2 + cpar].push_back(cc);
+            }
+        }
+      }
     }
+    LL.crs_count[pi] = (int)cp[0].size() - LL.crs_first[pi];
     li.back().nx = (int)xt.size() - li.back().x0;
     li.back().ny = (int)yt.size() - li.back().y0;
   }
@@ -555,13 +572,15 @@ int build_launch(mlswe_ctx* c, int l) {
   if ((rc = ensure(c, &LL.pd[1], &cap_pd1, npd))) return rc;
   if ((rc = ensure(c, &LL.xt, &LL.cap_xt, LL.nxt))) return rc;
   if ((rc = ensure(c, &LL.yt, &LL.cap_yt, LL.nyt))) return rc;
+  LL.ncrs = (int)cp[0].size();
   int capf[4] = {LL.cap_fp, LL.cap_fp, LL.cap_fp, LL.cap_fp};
-  int capc[4] = {LL.cap_fp, LL.cap_fp, LL.cap_fp, LL.cap_fp};
+  int capc[4] = {LL.cap_cp, LL.cap_cp, LL.cap_cp, LL.cap_cp};
   for (int k = 0; k < 4; ++k) {
     if ((rc = ensure(c, &LL.fp[k], &capf[k], LL.nptch))) return rc;
-    if ((rc = ensure(c, &LL.cp[k], &capc[k], LL.nptch))) return rc;
+    if ((rc = ensure(c, &LL.cp[k], &capc[k], std::max(1, LL.ncrs)))) return rc;
   }
   LL.cap_fp = capf[0];
+  LL.cap_cp = capc[0];
   if ((rc = ensure(c, &LL.li, &LL.cap_li, 4 * LL.nli))) return rc;
   if ((rc = ensure(c, &LL.parts, &LL.cap_parts, LL.nxt + LL.nyt))) return rc;
   if (LL.nptch) {
@@ -571,7 +590,8 @@ int build_launch(mlswe_ctx* c, int l) {
     HIPCHK(c, hipMemcpyAsync(LL.yt, yt.data(), sizeof(YTile) * LL.nyt, hipMemcpyHostToDevice, c->stream));
     for (int k = 0; k < 4; ++k) {
       HIPCHK(c, hipMemcpyAsync(LL.fp[k], fp[k].data(), sizeof(FillPatch) * LL.nptch, hipMemcpyHostToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(LL.cp[k], cp[k].data(), sizeof(CoarsenPatch) * LL.nptch, hipMemcpyHostToDevice, c->stream));
+      if (LL.ncrs)
+        HIPCHK(c, hipMemcpyAsync(LL.cp[k], cp[k].data(), sizeof(CoarsenPatch) * LL.ncrs, hipMemcpyHostToDevice, c->stream));
     }
   }
   if (LL.nli)
@@ -801,16 +821,20 @@ int coarsen_level(mlswe_ctx* c, int lf, int p0, int p1) {
   LevelLaunch& LL = c->launch[lf];
   int first = -1, count = 0, maxc = 0;
   for (int p = p0; p < p1; ++p) {
-    if (LL.fill_first[p] < 0) continue;
-    if (first < 0) first = LL.fill_first[p];
-    count = LL.fill_first[p] + LL.fill_count[p] - first;
+    if (LL.crs_first[p] < 0 || LL.crs_count[p] == 0) continue;
+    if (first < 0) first = LL.crs_first[p];
+    count = LL.crs_first[p] + LL.crs_count[p] - first;
     const int r = c->probs[p].ratio[lf - 1];
-    for (const Box& b : c->probs[p].L[lf].boxes) maxc = std::max(maxc, (b.nx / r) * (b.ny / r));
+    for (const Box& b : c->probs[p].L[lf].boxes) {
+      const int cnx = b.nx / r, rows = std::max(1, 256 / std::max(1, cnx));
+      maxc = std::max(maxc, cnx * std::min(rows, b.ny / r));
+    }
   }
   if (count == 0) return MLSWE_OK;
   const int fpar = c->probs[p0].L[lf].cur, cpar = c->probs[p0].L[lf - 1].cur;
-  hipLaunchKernelGGL(k_coarsen, dim3((maxc + 255) / 256, count), dim3(256), 0, c->stream,
-                     LL.cp[fpar * 2 + cpar] + first);
+  for (int k0 = 0; k0 < count; k0 += 65535)  // grid y is at most 65535
+    hipLaunchKernelGGL(k_coarsen, dim3((maxc + 255) / 256, (unsigned)std::min(65535, count - k0)), dim3(256), 0,
+                       c->stream, LL.cp[fpar * 2 + cpar] + first + k0);
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
@@ -1636,18 +1660,25 @@ int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt
     for (int l = 1; l < P.nlev; ++l) {
       LevelH& L = P.L[l];
       for (const Box& b : L.boxes) {
-        const long long off = idx(L, b.ilo, b.jlo);
-        double* q = L.q[L.cur] + off;
-        double* k = L.bk + off;
-        add(to_bk ? q : k, to_bk ? k : q, L.pitch, L.plane, b.nx, b.ny, 6);
+        // pieces of whole rows, about 4096 doubles each over the six fields
+        const int rows = std::max(1, 4096 / (6 * b.nx));
+        for (int j = b.jlo; j < b.jlo + b.ny; j += rows) {
+          const long long off = idx(L, b.ilo, j);
+          double* q = L.q[L.cur] + off;
+          double* k = L.bk + off;
+          add(to_bk ? q : k, to_bk ? k : q, L.pitch, L.plane, b.nx, std::min(rows, b.jlo + b.ny - j), 6);
+        }
       }
     }
   }
   int rc;
   if ((rc = ensure(c, &c->boxes_d, &c->boxes_cap, (int)boxes.size()))) return rc;
   HIPCHK(c, hipMemcpyAsync(c->boxes_d, boxes.data(), sizeof(CopyBox) * boxes.size(), hipMemcpyHostToDevice, c->stream));
-  const unsigned gx = (unsigned)std::min<long long>(64, (longest + 255) / 256);
-  hipLaunchKernelGGL(k_copy_boxes, dim3(gx, (unsigned)boxes.size()), dim3(256), 0, c->stream, c->boxes_d);
+  // a block per piece of up to 4096 doubles (sixteen per thread)
+  const unsigned gx = (unsigned)std::min<long long>(64, (longest + 4095) / 4096);
+  for (size_t k0 = 0; k0 < boxes.size(); k0 += 65535)  // grid y is at most 65535
+    hipLaunchKernelGGL(k_copy_boxes, dim3(gx, (unsigned)std::min<size_t>(65535, boxes.size() - k0)), dim3(256), 0,
+                       c->stream, c->boxes_d + k0);
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
