@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--amr-steps", type=int, default=16)
     ap.add_argument("--adjoint-steps", type=int, default=400)
-    ap.add_argument("--only", choices=("batch", "amr", "adjoint"), default=None,
+    ap.add_argument("--only", choices=("batch", "amr", "adjoint", "shelf"), default=None,
                     help="run only this extra measurement and print its JSON (for profiling)")
     ap.add_argument("--modes", default="plain,batched,graph",
                     help="launch modes of the batch / AMR measurements")
@@ -141,6 +141,64 @@ def bench_amr(steps, stream, modes=("plain", "batched", "graph")):
     ratios(out, modes)
     out["coarse_steps"] = steps
     return out
+
+
+def bench_shelf(stream, mode_name="batched"):
+    """The paper's demonstration (plane wave onto a shelf, Sec. 4; invented
+    parameters): the finest grid everywhere against three levels (ratios 2 and
+    4, regrid every 4 coarse steps), both run to the same simulated time.
+    Reports the AMR run's share of cell updates and of wall time, beside the
+    paper's 7.20 % and 9.57 % (a CPU run, context only)."""
+    import numpy as np
+    from paper_1803_01450_amd import inputs
+    from paper_1803_01450_amd.binding import Solver, BATCHED, GRAPH
+    mode = {"batched": BATCHED, "graph": GRAPH}[mode_name]
+    c = inputs.shelf_wave()
+    T = c["T"]
+
+    def uniform():
+        S = Solver(stream=stream)
+        p = S.define(c["nfx"], c["nfy"], c["dxf"], c["dxf"], c["r"])
+        S.set_bathymetry(p, c["Bf"])
+        S.set_state(p, 0, c["qf"])
+        S.synchronize()
+        t0 = time.perf_counter()
+        t = 0.0
+        while t < T:
+            S.advance(25, mode=mode)
+            t = S.counters(p)["t"]
+        sec = time.perf_counter() - t0
+        upd = sum(S.counters(p)["updates"])
+        S.close()
+        return {"seconds": sec, "t": t, "cell_updates": upd, "cells": c["nfx"] * c["nfy"]}
+
+    def amr():
+        S = Solver(stream=stream)
+        p = S.define(c["n0x"], c["n0y"], c["dx0"], c["dx0"], c["r"], c["ratios"])
+        S.set_bathymetry(p, c["Bf"])
+        S.set_state(p, 0, c["q0"])
+        S.synchronize()
+        t0 = time.perf_counter()
+        t = 0.0
+        while t < T:
+            S.advance(c["regrid_every"], c["regrid_every"], [c["tau"]], mode=mode)
+            t = S.counters(p)["t"]
+        sec = time.perf_counter() - t0
+        cnt = S.counters(p)
+        out = {"seconds": sec, "t": t, "cell_updates": sum(cnt["updates"]), "updates_per_level": cnt["updates"],
+               "finest_patches": int(len(S.patches(p, 2)))}
+        S.close()
+        return out
+
+    print("bench: shelf demonstration, uniform and AMR (%s)" % mode_name, file=sys.stderr, flush=True)
+    uniform(); amr()  # warm-up (clocks, code objects)
+    u, a = uniform(), amr()
+    # per unit of simulated time (the runs stop within one call of T)
+    uf = (a["cell_updates"] / a["t"]) / (u["cell_updates"] / u["t"])
+    tf = (a["seconds"] / a["t"]) / (u["seconds"] / u["t"])
+    return {"uniform": u, "amr": a, "update_fraction": uf, "time_fraction": tf,
+            "uniform_rate": u["cell_updates"] / u["seconds"], "amr_rate": a["cell_updates"] / a["seconds"],
+            "paper_cpu": {"update_fraction": 0.0720, "time_fraction": 0.0957}, "T": T, "mode": mode_name}
 
 
 def bench_adjoint(nsteps, stream):
@@ -255,6 +313,8 @@ def main():
             res = bench_batch(args.batch_problems, args.batch_steps, st, modes)
         elif args.only == "amr":
             res = bench_amr(args.amr_steps, st, modes)
+        elif args.only == "shelf":
+            res = bench_shelf(st)
         else:
             res = bench_adjoint(args.adjoint_steps, st)
         print(json.dumps({args.only: res}))
@@ -364,6 +424,7 @@ def main():
         out["batch"] = bench_batch(args.batch_problems, args.batch_steps, st)
         out["amr"] = bench_amr(args.amr_steps, st)
         out["adjoint"] = bench_adjoint(args.adjoint_steps, st)
+        out["shelf_demo"] = bench_shelf(st)
         out["batched_vs_plain"] = out["batch"]["batched_vs_plain"]
         out["adjoint_fwd"] = out["adjoint"]["adjoint_fwd"]
     print(json.dumps(out))

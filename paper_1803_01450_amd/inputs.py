@@ -139,6 +139,41 @@ def amr_shoreline(n0=256, L=400e3, ratios=(2, 4), seed=SEED0 + 2):
                 level0_boxes=boxes, regrid_every=4, nsteps=200)
 
 
+def shelf_wave(n0=256, ratios=(2, 4), Lx=2.0, Ly=1.0, amp=0.02, width=0.01, g=9.81):
+    """The paper's demonstration workload (Sec. 4) in scaled units, with invented
+    parameters (its set-up is not in the text): sea level 0, deep floor -1, a
+    shelf at -0.25 from x = 0.625 Lx on (a discontinuous jump), the internal
+    interface at -0.125 (depths that averaging keeps exact), and a right-going
+    plane wave on eta1 (Gaussian in x,
+    uniform in y, amplitude `amp`, width `width` Lx, centre 0.25 Lx) whose layers
+    move at eta1 sqrt(g / 1), the long-wave speed over unit depth.  Returns the
+    finest-grid bathymetry and state (the uniform run) and the level-0 state of
+    the AMR run; level 0 is n0 x n0 / 2 cells."""
+    nfac = int(np.prod(ratios))
+    n0y = int(round(n0 * Ly / Lx))
+    nfx, nfy = n0 * nfac, n0y * nfac
+    dxf = Lx / nfx
+    xs = 0.625 * Lx  # on a level-0 cell boundary
+
+    def state(x, B):
+        eta1 = np.tile(amp * np.exp(-((x - 0.25 * Lx) ** 2) / (2.0 * (width * Lx) ** 2)), (B.shape[0], 1))
+        q = state_from_surfaces(eta1, np.full(B.shape, -0.125), B)
+        u = eta1 * np.sqrt(g / 1.0)
+        q[1] = q[0] * u
+        q[4] = q[3] * u
+        return q
+
+    xf = centres(nfx, Lx)
+    Bf = np.tile(np.where(xf < xs, -1.0, -0.25), (nfy, 1))
+    qf = state(xf, Bf)
+    B0 = block_mean(Bf, nfac)  # the hierarchy's level-0 bathymetry
+    q0 = state(centres(n0, Lx), B0)
+    # time for the wave to reach the break and run 0.15 Lx onto the shelf
+    T = float((xs - 0.25 * Lx) / np.sqrt(g) + 0.15 * Lx / np.sqrt(0.25 * g))
+    return dict(n0x=n0, n0y=n0y, nfx=nfx, nfy=nfy, dx0=Lx / n0, dxf=dxf, ratios=tuple(ratios), Bf=Bf, qf=qf,
+                B0=B0, q0=q0, r=0.95, T=T, tau=[0.05, 0.05], regrid_every=4)
+
+
 def batch_sizes(nprob=512, seed=SEED0 + 4):
     rng = np.random.default_rng(seed)
     n = np.exp(rng.uniform(np.log(48), np.log(512), nprob))
