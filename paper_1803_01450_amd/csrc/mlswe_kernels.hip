@@ -80,7 +80,7 @@ __device__ __forceinline__ bool refine_cell_into(const FillPatch& F, int i, int 
 // pass 0: in-domain frame cells not covered by a patch of the level are refined
 // from the coarser level; pass 1: frame cells outside the domain mirror the
 // in-domain cells across the walls (normal momentum negated).
-__global__ __launch_bounds__(256) void k_ghost_fill(const FillPatch* __restrict__ fills, int pass) {
+__global__ __launch_bounds__(256) void k_ghost_fill(const FillPatch* __restrict__ fills, int pass, double theta) {
   const FillPatch& F = fills[blockIdx.y];
   const int ring = 4 * (F.bnx + 4) + 4 * F.bny;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_ghost_fill(const FillPatch* __restrict_
   if (pass == 0) {
     if (!indom || F.coarse_none) return;
     if (F.mask[cidx(F.pitch, i, j)]) return;
-    bool rep = refine_cell_into(F, i, j, *F.theta, F.q, F.plane);
+    bool rep = refine_cell_into(F, i, j, theta, F.q, F.plane);
     if (rep && F.cnt) atomicAdd(&F.cnt->repair, 1ull);
     return;
   }
@@ -391,7 +391,6 @@ __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int n
   }
 }
 
-__global__ void k_set_theta(double* th, double v) { *th = v; }
 
 // Cells of a level-wide copy [6][ny][nx] that no patch covers read NaN.
 __global__ __launch_bounds__(256) void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask,

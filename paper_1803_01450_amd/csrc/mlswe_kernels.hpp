@@ -67,7 +67,6 @@ struct FillPatch {
   const double* qco;          // coarse state at the start of its step
   const double* qcn;          // coarse state at the end of its step
   const double* Bc;
-  const double* theta;        // time fraction (device)
   Counters* cnt;
   long long pitch, plane, cpitch, cplane;
   int nx, ny, ncx, ncy;
@@ -221,7 +220,7 @@ __global__ void k_sweep_x_fast(const PatchDev* __restrict__ patches, const XTile
 __global__ void k_sweep_y_fast(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
                                int sched, unsigned* ticket, TilePart* parts);
 __global__ void k_zero_u32(unsigned* p, int n);
-__global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass);
+__global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass, double theta);
 __global__ void k_refine_new(const FillPatch* __restrict__ fills);
 __global__ void k_coarsen(const CoarsenPatch* __restrict__ cps);
 __global__ void k_flag_raw(const FlagLevel* __restrict__ Fs);
@@ -231,7 +230,6 @@ __global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo*
                                 double cflmax);
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
 __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial);
-__global__ void k_set_theta(double* th, double v);
 __global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);
 // A contiguous run of doubles to copy (one row range of one field plane).
 // A box of nf fields copied between two arrays of the same layout: element

@@ -117,7 +117,6 @@ struct mlswe_ctx {
   int ctl_cap = 0;
   Counters* cnt = nullptr;
   int cnt_cap = 0;
-  double* theta = nullptr;  // [MAXLEV] time fraction used by the ghost fill of each level
   ProbDt* pdt = nullptr;
   int pdt_cap = 0;
   bool pdt_dirty = true;
@@ -470,7 +469,6 @@ int build_launch(mlswe_ctx* c, int l) {
       FillPatch f;
       std::memset(&f, 0, sizeof f);
       f.B = L.B; f.mask = L.mask;
-      f.theta = c->theta + l;
       f.cnt = c->cnt + P.cnt;
       f.pitch = L.pitch; f.plane = L.plane;
       f.nx = L.nx; f.ny = L.ny;
@@ -731,11 +729,10 @@ int launch_fill(mlswe_ctx* c, int l, int p0, int p1, double theta) {
   if (count == 0) return MLSWE_OK;
   const FillPatch* f = LL.fp[fpar * 2 + cpar] + first;
   if (l > 0) {
-    hipLaunchKernelGGL(k_set_theta, dim3(1), dim3(1), 0, c->stream, c->theta + l, theta);
-    hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 0);
+    hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 0, theta);
     HIPCHK(c, hipGetLastError());
   }
-  hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 1);
+  hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 1, theta);
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
@@ -1252,13 +1249,6 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
   c->tune.grid_x = 1;
   c->tune.grid_y = 1;
   if (dalloc(c, (void**)&c->tickets, 2 * sizeof(unsigned)) != MLSWE_OK) { delete c; return MLSWE_ENOMEM; }
-  int rc = dalloc(c, (void**)&c->theta, sizeof(double) * MAXLEV);
-  if (rc) { delete c; return rc; }
-  if (hipMemsetAsync(c->theta, 0, sizeof(double) * MAXLEV, c->stream) != hipSuccess) {
-    dfree(c->theta);
-    delete c;
-    return MLSWE_EDEVICE;
-  }
   *out = c;
   return MLSWE_OK;
 }
@@ -1282,7 +1272,7 @@ int mlswe_destroy(mlswe_ctx* c) {
     dfree(LL.pd[0]); dfree(LL.pd[1]); dfree(LL.xt); dfree(LL.yt); dfree(LL.li); dfree(LL.parts);
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
   }
-  dfree(c->ctl); dfree(c->cnt); dfree(c->theta); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
+  dfree(c->ctl); dfree(c->cnt); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
   dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d); dfree(c->boxes_d);
   dfree(c->bsegs_d); dfree(c->mboxes_d); dfree(c->rfills_d); dfree(c->flv_d);
   dfree(c->ftl_d); dfree(c->tbits_d);
