@@ -144,7 +144,7 @@ def bench_amr(steps, stream, modes=("plain", "batched", "graph")):
 
 
 def bench_shelf(stream, mode_name="batched"):
-    """The paper's demonstration (plane wave onto a shelf, Sec. 4; invented
+    """The paper's demonstration (plane wave onto a shelf, Sec. 3; invented
     parameters): the finest grid everywhere against three levels (ratios 2 and
     4, regrid every 4 coarse steps), both run to the same simulated time.
     Reports the AMR run's share of cell updates and of wall time, beside the

@@ -140,7 +140,7 @@ def amr_shoreline(n0=256, L=400e3, ratios=(2, 4), seed=SEED0 + 2):
 
 
 def shelf_wave(n0=256, ratios=(2, 4), Lx=2.0, Ly=1.0, amp=0.02, width=0.01, g=9.81):
-    """The paper's demonstration workload (Sec. 4) in scaled units, with invented
+    """The paper's demonstration workload (Sec. 3) in scaled units, with invented
     parameters (its set-up is not in the text): sea level 0, deep floor -1, a
     shelf at -0.25 from x = 0.625 Lx on (a discontinuous jump), the internal
     interface at -0.125 (depths that averaging keeps exact), and a right-going

@@ -1,4 +1,4 @@
-"""The demonstration workload of the paper's Sec. 4 (plane wave from deep water
+"""The demonstration workload of the paper's Sec. 3 (plane wave from deep water
 onto a discontinuous shelf, scaled units, invented parameters) at a small size:
 three levels (ratios 2 and 4), regrid every 4 coarse steps, against the oracle
 (patch layouts and update counts exact, dts within 1e-12, states within 1e-9),
