@@ -90,6 +90,11 @@ struct LevelLaunch {
   std::vector<std::pair<int, int>> xrun, yrun;  // per problem: run tile ranges
   int rows_x = 0, rows_y = 0;                // rows per sweep wave in the current tiles
   int rows_xr = 0, rows_yr = 0;              // the same for the run tiles
+  // the layout size at the last evaluation of the tile-height model and its
+  // choices (patch x / y, run x / y), kept while the layout stays similar
+  long long model_cells = -1, model_patches = 0;
+  bool model_runs = false;
+  int model_rows[4] = {0, 0, 0, 0};
   TilePart* parts = nullptr;                 // per tile: x tiles, then y tiles
   int cap_parts = 0;
   int max_info_tiles = 0;                    // most tiles of one problem on the level
@@ -391,19 +396,40 @@ int build_launch(mlswe_ctx* c, int l) {
     }
     return rows;
   };
-  if (LL.use_runs) {
-    LL.rows_x = halve(0, c->tune.x_rows);
-    LL.rows_y = halve(1, c->tune.y_rows);
-  } else {
-    LL.rows_x = pick(0, c->tune.x_rows, [&](int r, std::vector<int>& d) { patch_rows(0, r, d); });
-    LL.rows_y = pick(1, c->tune.y_rows, [&](int r, std::vector<int>& d) { patch_rows(1, r, d); });
+  // the model's choices are kept while the level's cells and patch count stay
+  // within a quarter of those it was last evaluated on (a regrid moves the
+  // patches, the best heights change only with the layout's scale)
+  long long cells = 0;
+  for (const ProblemH& P : c->probs)
+    if (l < P.nlev)
+      for (const Box& b : P.L[l].boxes) cells += (long long)b.nx * b.ny;
+  const bool similar = LL.model_cells > 0 && LL.model_runs == LL.use_runs &&
+                       4 * std::llabs(cells - LL.model_cells) <= LL.model_cells &&
+                       4 * std::llabs((long long)npatch - LL.model_patches) <= LL.model_patches;
+  if (!similar) {
+    LL.model_cells = cells;
+    LL.model_patches = (long long)npatch;
+    LL.model_runs = LL.use_runs;
+    if (LL.use_runs) {
+      LL.model_rows[0] = halve(0, 0);
+      LL.model_rows[1] = halve(1, 0);
+    } else {
+      LL.model_rows[0] = pick(0, 0, [&](int r, std::vector<int>& d) { patch_rows(0, r, d); });
+      LL.model_rows[1] = pick(1, 0, [&](int r, std::vector<int>& d) { patch_rows(1, r, d); });
+    }
   }
+  LL.rows_x = c->tune.x_rows > 0 ? c->tune.x_rows : LL.model_rows[0];
+  LL.rows_y = c->tune.y_rows > 0 ? c->tune.y_rows : LL.model_rows[1];
   auto run_rows = [&](int axis, int rows, std::vector<int>& d) {
     for (const ProblemH& P : c->probs)
       if (l < P.nlev && !P.L[l].boxes.empty()) run_blocks(P.L[l], axis, rows, 0, nullptr, nullptr, &d);
   };
-  LL.rows_xr = LL.use_runs ? pick(0, c->tune.x_rows, [&](int r, std::vector<int>& d) { run_rows(0, r, d); }) : 0;
-  LL.rows_yr = LL.use_runs ? pick(1, c->tune.y_rows, [&](int r, std::vector<int>& d) { run_rows(1, r, d); }) : 0;
+  if (!similar && LL.use_runs) {
+    LL.model_rows[2] = pick(0, 0, [&](int r, std::vector<int>& d) { run_rows(0, r, d); });
+    LL.model_rows[3] = pick(1, 0, [&](int r, std::vector<int>& d) { run_rows(1, r, d); });
+  }
+  LL.rows_xr = LL.use_runs ? (c->tune.x_rows > 0 ? c->tune.x_rows : LL.model_rows[2]) : 0;
+  LL.rows_yr = LL.use_runs ? (c->tune.y_rows > 0 ? c->tune.y_rows : LL.model_rows[3]) : 0;
   const int xrows = LL.rows_x, yrows = LL.rows_y;
   std::vector<PatchDev> pd[2];
   std::vector<XTile> xt;
