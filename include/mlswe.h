@@ -61,11 +61,15 @@ typedef struct mlswe_config {
   int pad_;
 } mlswe_config;
 
-/* Launch shape of the two sweep kernels.  rows: rows of a patch per x-sweep
- * wave / per y-sweep wave (a y wave marches its rows with the last edge in
- * registers); 0 chooses them per level: 32 (x) and 128 (y), halved while the
- * level's tiles over all problems would not fill the device, down to 4 and 8.  sched: 0 one wave per tile, 1 persistent waves striding over
- * the tile list, 2 persistent waves taking tiles from an atomic ticket.
+/* Launch shape of the two sweep kernels.  rows: rows per x-sweep wave / per
+ * y-sweep wave (a y wave marches its rows with the last edge in registers);
+ * 0 chooses them per level and sweep among 4-32 (x) and 8-128 (y) by a model
+ * of the level's tiles finishing on the device's wave slots.  Batched launches
+ * with sched 0 on levels where a problem has several patches sweep the union
+ * of each problem's patches in fixed blocks; other launches sweep each patch's
+ * own tiles (the results are the same bit for bit).  sched: 0 one wave per
+ * tile, 1 persistent waves striding over the tile list, 2 persistent waves
+ * taking tiles from an atomic ticket.
  * grid: persistent blocks of four waves per compute unit.  fast: 1 selects the
  * build of the sweeps with Newton-refined hardware reciprocals and reciprocal
  * square roots and fused multiply-adds (FP64 throughout, a few ulps per
