@@ -176,8 +176,10 @@ int mlswe_regrid(mlswe_ctx* ctx, int p, const double* tau, int nbuf);
  * regrid_every steps (0 = never; tau is [n_problems][8]), dt from the previous
  * step's largest speeds (first step: from the state), each level l > 0 takes
  * r_{l-1} substeps per step of level l-1 and is then averaged onto it (Sec. 2).
- * mode MLSWE_PLAIN launches the sweeps per patch; MLSWE_BATCHED launches one
- * x-sweep and one y-sweep per level substep over the patches of all problems;
+ * The regrid treats all problems in one pass in every mode.  mode MLSWE_PLAIN
+ * then steps one problem at a time and launches the sweeps per patch;
+ * MLSWE_BATCHED launches one x-sweep and one y-sweep per level substep over the
+ * patches of all problems;
  * MLSWE_GRAPH does the same and replays each coarse step from a captured
  * hipGraph (captured on first use, again after a regrid; the first step of a
  * run, which derives dt from the state, runs uncaptured).

@@ -373,9 +373,9 @@ int build_launch(mlswe_ctx* c, int l) {
   };
   // run tiles serve levels where some problem has several patches; their rows
   // follow the same rule over the run blocks.  The patch tiles of such a level
-  // serve only plain launches and persistent schedules: their rows come from
-  // the cheaper rule of halving 32 (x) / 128 (y) while the tiles would not fill
-  // the device (x: four rounds of three waves per SIMD, y: one round of two).
+  // serve only plain launches (one patch per launch, a few waves each) and
+  // persistent schedules (balanced by the schedule): both do best with the
+  // shortest tiles, 4 (x) and 8 (y) rows.
   LL.use_runs = false;
   size_t npatch = 0;
   for (const ProblemH& P : c->probs)
@@ -383,19 +383,6 @@ int build_launch(mlswe_ctx* c, int l) {
       if (P.L[l].boxes.size() > 1) LL.use_runs = true;
       npatch += P.L[l].boxes.size();
     }
-  auto halve = [&](int axis, int tuned) {
-    if (tuned > 0) return tuned;
-    int rows = axis == 0 ? 32 : 128;
-    const long long want = (axis == 0 ? 48LL : 8LL) * c->ncu;
-    std::vector<int> d;
-    while (rows > (axis == 0 ? 4 : 8)) {
-      d.clear();
-      patch_rows(axis, rows, d);
-      if ((long long)d.size() >= want) break;
-      rows /= 2;
-    }
-    return rows;
-  };
   // the model's choices are kept while the level's cells and patch count stay
   // within a quarter of those it was last evaluated on (a regrid moves the
   // patches, the best heights change only with the layout's scale)
@@ -411,8 +398,8 @@ int build_launch(mlswe_ctx* c, int l) {
     LL.model_patches = (long long)npatch;
     LL.model_runs = LL.use_runs;
     if (LL.use_runs) {
-      LL.model_rows[0] = halve(0, 0);
-      LL.model_rows[1] = halve(1, 0);
+      LL.model_rows[0] = 4;
+      LL.model_rows[1] = 8;
     } else {
       LL.model_rows[0] = pick(0, 0, [&](int r, std::vector<int>& d) { patch_rows(0, r, d); });
       LL.model_rows[1] = pick(1, 0, [&](int r, std::vector<int>& d) { patch_rows(1, r, d); });
@@ -1810,30 +1797,32 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
       for (int l = 0; l + 1 < c->probs[p].nlev; ++l)
         if (c->probs[p].ratio[l] != c->probs[0].ratio[l]) return fail(c, MLSWE_EINVAL, "batched ratios differ");
     }
-  // groups of problems advanced together: all (batched, graph) or one at a time (plain)
+  // every coarse step: the regrid of all problems (one pass, the problems are
+  // independent), then the step of the problems together (batched, graph) or
+  // one problem at a time with one launch per patch (plain)
   const int ngroups = together ? 1 : np;
-  for (int gi = 0; gi < ngroups; ++gi) {
-    const int p0 = together ? 0 : gi, p1 = together ? np : gi + 1;
-    for (int n = 0; n < nsteps; ++n) {
-      int rc;
-      if (regrid_every > 0 && n % regrid_every == 0)
-        if ((rc = regrid_group(c, p0, p1, tau, nbuf))) return rc;
-      if ((rc = build_pdt(c))) return rc;
+  for (int n = 0; n < nsteps; ++n) {
+    int rc;
+    if (regrid_every > 0 && n % regrid_every == 0)
+      if ((rc = regrid_group(c, 0, np, tau, nbuf))) return rc;
+    if ((rc = build_pdt(c))) return rc;
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const int p0 = together ? 0 : gi, p1 = together ? np : gi + 1;
       if ((rc = step_with_retry(c, p0, p1, mode))) return rc;
-      if (dts_out || c->timing) {
-        if ((rc = collect_events(c))) return rc;
-      }
-      if (dts_out) {
-        std::vector<LevelCtl> h;
-        if ((rc = read_ctls(c, p0, p1, h))) return rc;
-        for (int p = p0; p < p1; ++p) dts_out[(size_t)p * nsteps + n] = h[c->probs[p].ctl0 - c->probs[p0].ctl0].dt;
-      }
     }
-    int status = 0;
-    int rc = read_status(c, p0, p1, &status);
-    if (rc) return rc;
-    if (status & STATUS_CFL) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
+    if (dts_out || c->timing) {
+      if ((rc = collect_events(c))) return rc;
+    }
+    if (dts_out) {
+      std::vector<LevelCtl> h;
+      if ((rc = read_ctls(c, 0, np, h))) return rc;
+      for (int p = 0; p < np; ++p) dts_out[(size_t)p * nsteps + n] = h[c->probs[p].ctl0].dt;
+    }
   }
+  int status = 0;
+  int rc = read_status(c, 0, np, &status);
+  if (rc) return rc;
+  if (status & STATUS_CFL) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
   return MLSWE_OK;
 }
 
