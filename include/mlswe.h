@@ -89,7 +89,7 @@ typedef struct mlswe_counters {
   int64_t repair;          /* wet-ordering repairs (top layer dry over a wet bottom layer) */
   double clip1, clip2;     /* mass removed from layers 1 and 2 by clipping */
   double t;                /* simulated time of the problem */
-  int status;              /* sticky device status bits (1: Courant above cfl_max) */
+  int status;              /* sticky device status bits (1: Courant above cfl_max, 2: non-finite state) */
   int64_t rejected;        /* coarse steps undone and retaken (Courant above cfl_max) */
 } mlswe_counters;
 
@@ -151,7 +151,8 @@ int mlswe_get_state(mlswe_ctx* ctx, int p, int level, double* q, int where);
  * speeds.  dt: host array [n_problems] of substeps, or NULL to use the
  * device-resident dt.  smax_out (nullable, host) receives [n_problems][2]
  * largest x / y speeds and synchronises.  Errors: MLSWE_EINVAL, MLSWE_ESTATE,
- * MLSWE_ECFL (checked only when smax_out is given). */
+ * MLSWE_ENAN (a non-finite state after the x-sweep) and MLSWE_ECFL, both
+ * checked only when smax_out is given. */
 int mlswe_step_level(mlswe_ctx* ctx, int level, const double* dt, double theta, double* smax_out);
 
 /* Averages the fine level onto the coarser one for all six fields (Sec. 2.2,
@@ -184,7 +185,9 @@ int mlswe_regrid(mlswe_ctx* ctx, int p, const double* tau, int nbuf);
  * hipGraph (captured on first use, again after a regrid; the first step of a
  * run, which derives dt from the state, runs uncaptured).
  * dts_out (nullable, host [n_problems][n_coarse_steps]) receives the coarse
- * steps.  Errors: MLSWE_EINVAL, MLSWE_ESTATE, MLSWE_ECFL. */
+ * steps.  Errors: MLSWE_EINVAL, MLSWE_ESTATE, MLSWE_ECFL (Courant number above
+ * cfl_max after the allowed retakes), MLSWE_ENAN (a non-finite Courant
+ * number). */
 int mlswe_advance(mlswe_ctx* ctx, int n_coarse_steps, int regrid_every, const double* tau, int nbuf,
                   int mode, double* dts_out);
 

@@ -361,9 +361,13 @@ __device__ __forceinline__ void correction_flux(const EdgeW& W, const double coe
 struct FixCount {
   int nclip, repair;
   double clip1, clip2;
+  int nonfinite;  // a cell left the fix-up with a non-finite value
 };
 
 // Dry-state fix-up: clip thin layers (bottom first), restore the wet ordering.
+// CHECK: also note a non-finite value in the wave's cells (the x-sweep, which
+// every step passes through, carries the check).
+template <bool CHECK = false>
 __device__ __forceinline__ void fixup(const PhysParams& P, double q[6], bool count, FixCount& K) {
   if (q[3] < P.hdry) {
     if (count && q[3] != 0.0) { K.nclip++; K.clip2 += q[3]; }
@@ -376,6 +380,11 @@ __device__ __forceinline__ void fixup(const PhysParams& P, double q[6], bool cou
   if (q[0] == 0.0 && q[3] > 0.0) {
     if (count) { K.repair++; K.clip2 += q[3]; }
     q[3] = 0.0; q[4] = 0.0; q[5] = 0.0;
+  }
+  if (CHECK) {
+    // NaN or infinity in some field of some lane of the wave (kept wave-wide)
+    const double sum = ((q[0] + q[1]) + (q[2] + q[3])) + (q[4] + q[5]);
+    K.nonfinite |= __builtin_amdgcn_ballot_w64(sum - sum != 0.0) != 0ull ? 1 : 0;
   }
 }
 

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_coarsen(const CoarsenPatch* __restrict_
       for (int aa = 0; aa < r; ++aa) s = s + C.qf[c * C.fplane + cidx(C.fpitch, r * I + aa, r * J + bb)];
     v[c] = s * inv;
   }
-  FixCount K = {0, 0, 0.0, 0.0};
+  FixCount K = {0, 0, 0.0, 0.0, 0};
   fixup(C.P, v, false, K);
   const long long d = cidx(C.cpitch, I, J);
 #pragma unroll
@@ -227,11 +227,11 @@ __global__ __launch_bounds__(256) void k_flag_tiles(const FlagTiles* __restrict_
 __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos,
                                                         const TilePart* parts, double cflmax) {
   __shared__ double red_d[4][16];
-  __shared__ unsigned long long red_u[3][16];
+  __shared__ unsigned long long red_u[4][16];
   const LevelInfo I = infos[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double sx = 0.0, sy = 0.0, c1 = 0.0, c2 = 0.0;
-  unsigned long long h = 0, nc = 0, rp = 0;
+  unsigned long long h = 0, nc = 0, rp = 0, nf = 0;
   // four independent loads in flight per pass (the passes are latency bound)
   const int ntot = I.nx + I.ny, step = blockDim.x;
   for (int k0 = threadIdx.x; k0 < ntot; k0 += 4 * step) {
@@ -252,6 +252,7 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
       h += T[u].hyp;
       nc += T[u].nclip;
       rp += T[u].repair;
+      nf += T[u].nonfinite;
     }
   }
   sx = wave_max(sx);
@@ -261,9 +262,10 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
   h = wave_usum(h);
   nc = wave_usum(nc);
   rp = wave_usum(rp);
+  nf = wave_usum(nf);
   if (lane == 0) {
     red_d[0][wave] = sx; red_d[1][wave] = sy; red_d[2][wave] = c1; red_d[3][wave] = c2;
-    red_u[0][wave] = h; red_u[1][wave] = nc; red_u[2][wave] = rp;
+    red_u[0][wave] = h; red_u[1][wave] = nc; red_u[2][wave] = rp; red_u[3][wave] = nf;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -271,13 +273,14 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
     sx = red_d[0][w] > sx ? red_d[0][w] : sx;
     sy = red_d[1][w] > sy ? red_d[1][w] : sy;
     c1 += red_d[2][w]; c2 += red_d[3][w];
-    h += red_u[0][w]; nc += red_u[1][w]; rp += red_u[2][w];
+    h += red_u[0][w]; nc += red_u[1][w]; rp += red_u[2][w]; nf += red_u[3][w];
   }
   LevelCtl& C = ctls[I.ctl];
   const double ax = sx / I.dx, ay = sy / I.dy;
   const double courant = C.dt * (ax > ay ? ax : ay);
   if (courant > C.cmax || courant != courant) C.cmax = courant;
   if (!(courant <= cflmax)) C.status |= STATUS_CFL;
+  if (nf) C.status |= STATUS_NAN;
   const unsigned long long bx = (unsigned long long)__double_as_longlong(sx);
   const unsigned long long by = (unsigned long long)__double_as_longlong(sy);
   C.last_smax[0] = bx;

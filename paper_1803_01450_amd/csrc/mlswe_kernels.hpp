@@ -113,7 +113,7 @@ struct FlagTiles {
 // the substep, so no two waves update the same word.
 struct TilePart {
   double smax, clip1, clip2;
-  unsigned hyp, nclip, repair, pad;
+  unsigned hyp, nclip, repair, nonfinite;
 };
 
 // One problem on one level: its control block and counters, spacings, and the

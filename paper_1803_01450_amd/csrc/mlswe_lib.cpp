@@ -1504,6 +1504,7 @@ int mlswe_step_level(mlswe_ctx* c, int level, const double* dt, double theta, do
       smax_out[2 * p + 1] = __builtin_bit_cast(double, (long long)h.last_smax[1]);
       status |= h.status;
     }
+    if (status & STATUS_NAN) return fail(c, MLSWE_ENAN, "non-finite state");
     if (status & STATUS_CFL) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
   }
   return MLSWE_OK;
@@ -1743,12 +1744,12 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
       bool nan = false;
       for (int l = 0; l < P.nlev; ++l) {
         const double v = h[P.ctl0 + l].cmax;
-        if (v != v) nan = true;
+        if (v != v || (h[P.ctl0 + l].status & STATUS_NAN)) nan = true;
         else if (v > cm) cm = v;
       }
       const double dtp = h[P.ctl0].dt;
       if (nan || cm > c->cfg.cfl_max) {
-        if (nan) return fail(c, MLSWE_ECFL, "non-finite Courant number in problem %d", p);
+        if (nan) return fail(c, MLSWE_ENAN, "non-finite state or Courant number in problem %d", p);
         any = true;
         dt0[p - p0] = dtp * (c->cfg.cfl_desired / cm);
       } else {
@@ -1822,6 +1823,7 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
   int status = 0;
   int rc = read_status(c, 0, np, &status);
   if (rc) return rc;
+  if (status & STATUS_NAN) return fail(c, MLSWE_ENAN, "non-finite state");
   if (status & STATUS_CFL) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
   return MLSWE_OK;
 }

@@ -93,6 +93,7 @@ __device__ __forceinline__ void flush_part(TilePart* part, double smax, int hyp,
   const int h = wave_isum(hyp);
   const int nc = wave_isum(K.nclip);
   const int rp = wave_isum(K.repair);
+  const int nf = wave_isum(K.nonfinite);
   const double c1 = wave_sum(K.clip1);
   const double c2 = wave_sum(K.clip2);
   if (lane == 0) {
@@ -102,7 +103,7 @@ __device__ __forceinline__ void flush_part(TilePart* part, double smax, int hyp,
     part->hyp = (unsigned)h;
     part->nclip = (unsigned)nc;
     part->repair = (unsigned)rp;
-    part->pad = 0u;
+    part->nonfinite = nf != 0 ? 1u : 0u;
   }
 }
 
