@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--amr-steps", type=int, default=16)
     ap.add_argument("--adjoint-steps", type=int, default=400)
-    ap.add_argument("--only", choices=("batch", "amr", "adjoint", "shelf"), default=None,
+    ap.add_argument("--only", choices=("batch", "amr", "adjoint", "shelf", "layers"), default=None,
                     help="run only this extra measurement and print its JSON (for profiling)")
     ap.add_argument("--modes", default="plain,batched,graph",
                     help="launch modes of the batch / AMR measurements")
@@ -234,6 +234,50 @@ def bench_adjoint(nsteps, stream):
             "steps": nsteps, "cells": 1024 * 1024, "loss": float(loss.item())}
 
 
+def bench_layers(stream, M=4, r=2, n=2048, reps=20):
+    """The general M-layer refine and coarsen: four layers with a shore, 2048^2
+    coarse cells refined to 4096^2 and coarsened back, each launch timed with
+    HIP events on the library's stream.  Algorithmic bytes: refine writes 3M
+    doubles and reads the fine bathymetry per fine cell and reads 3M + 1
+    doubles per coarse cell; coarsen reads 3M doubles per fine cell and writes
+    3M per coarse cell."""
+    import torch
+    from paper_1803_01450_amd import inputs
+    from paper_1803_01450_amd.binding import Solver
+    print("bench: M-layer refine / coarsen, M %d, %d^2 -> %d^2" % (M, n, r * n), file=sys.stderr, flush=True)
+    c = inputs.layered_problem(M, n, n, r)
+    S = Solver(stream=stream)
+    qc = torch.from_numpy(c["qc"]).cuda()
+    Bc = torch.from_numpy(c["Bc"]).cuda()
+    Bf = torch.from_numpy(c["Bf"]).cuda()
+    qf = torch.empty((3 * M, r * n, r * n), dtype=torch.float64, device="cuda")
+    qc2 = torch.empty_like(qc)
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record(st)
+            fn()
+            e1.record(st)
+        torch.cuda.synchronize()
+        return sum(e0.elapsed_time(e1) for e0, e1 in evs) / reps
+
+    ref_ms = timed(lambda: S.refine_layers(qc, Bc, Bf, qf, r))
+    crs_ms = timed(lambda: S.coarsen_layers(qf, qc2, r))
+    nf, ncell = (r * n) ** 2, n * n
+    ref_b = nf * (3 * M + 1) * 8 + ncell * (3 * M + 1) * 8
+    crs_b = nf * 3 * M * 8 + ncell * 3 * M * 8
+    S.close()
+    return {"layers": M, "ratio": r, "coarse_cells": ncell, "fine_cells": nf,
+            "refine": {"avg_ms": ref_ms, "bytes": ref_b, "gbs": ref_b / ref_ms / 1e6,
+                       "frac": ref_b / (ref_ms * 1e-3) / HBM_PEAK, "fine_cells_per_s": nf / (ref_ms * 1e-3)},
+            "coarsen": {"avg_ms": crs_ms, "bytes": crs_b, "gbs": crs_b / crs_ms / 1e6,
+                        "frac": crs_b / (crs_ms * 1e-3) / HBM_PEAK}}
+
+
 # the kernels the timed steps launch (one wave per tile, no branch signature)
 LAUNCHED = {"x_sweep": "k_sweep_x1", "y_sweep": "k_sweep_y1"}
 # the sources the sweep kernels are compiled from
@@ -315,6 +359,8 @@ def main():
             res = bench_amr(args.amr_steps, st, modes)
         elif args.only == "shelf":
             res = bench_shelf(st)
+        elif args.only == "layers":
+            res = bench_layers(st)
         else:
             res = bench_adjoint(args.adjoint_steps, st)
         print(json.dumps({args.only: res}))
@@ -425,6 +471,7 @@ def main():
         out["amr"] = bench_amr(args.amr_steps, st)
         out["adjoint"] = bench_adjoint(args.adjoint_steps, st)
         out["shelf_demo"] = bench_shelf(st)
+        out["layers"] = bench_layers(st)
         out["batched_vs_plain"] = out["batch"]["batched_vs_plain"]
         out["adjoint_fwd"] = out["adjoint"]["adjoint_fwd"]
     print(json.dumps(out))

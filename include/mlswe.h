@@ -260,6 +260,42 @@ int mlswe_gauge_misfit(mlswe_ctx* ctx, int p, const double* q, int i0, int j0, i
  * difference between them sees a smooth map.  Synchronises when reading. */
 int mlswe_branch_signature(mlswe_ctx* ctx, int enable, int p, uint64_t* sig_out);
 
+/* ---------------------------------------------------------------- M layers
+ * The general multilayer refine and coarsen for M = 1..8 layers of one grid
+ * (the solver itself is two-layer).  Arrays are device pointers of the
+ * context's GPU, owned by the caller, field-major FP64 [3M][rows][cols] with
+ * x fastest: h_m, h_m u_m, h_m v_m for layer m = 1 (top) .. M, so M = 2 is the
+ * layout of mlswe_set_state.  The dry tolerance is the context's hdry.  Both
+ * calls are asynchronous on the context's stream unless stated. */
+
+/* Refine (Sec. 2.1: surfaces eta_m = B + h_M + ... + h_m, Eq. 4; effective
+ * bathymetry B-hat_m = B + h_M + ... + h_{m+1}, Eq. 5; minmod slopes, Eq. 10;
+ * bottom layer first, then up through B-hat; wet ordering).  Writes the fine
+ * cells of the box (fi0, fj0, fnx, fny) of the fine index space of ratio r over
+ * the coarse grid qc [3M][nyc][nxc] with bathymetry Bc [nyc][nxc]: qf
+ * [3M][fny][fnx] from the box's fine bathymetry Bf [fny][fnx].  Each child
+ * (a, b) of coarse cell (I, J) takes (eta + sx fa) + sy fb with fa = (2a + 1 -
+ * r) / (2r); slopes are zero at the domain edge and for a layer dry in one of
+ * the three cells of a direction; depths below hdry are dry and every layer
+ * below a dry one is dry (a repair); momenta use the same interpolant and are
+ * zero where the fine layer is dry.  repairs_out (nullable, host) receives the
+ * number of repairs; the call then synchronises.  A box of zero cells does
+ * nothing.  Errors: MLSWE_EINVAL (M or r outside 1..8, the box outside the
+ * fine grid, more than 262140 coarse rows, a null array), MLSWE_EDEVICE. */
+int mlswe_refine_layers(mlswe_ctx* ctx, int M, int r, const double* qc, const double* Bc, int nxc, int nyc, int fi0,
+                        int fj0, int fnx, int fny, const double* Bf, double* qf, int64_t* repairs_out);
+
+/* Coarsen (Sec. 2.2, Eq. 11 over r x r children): the coarse cells of the box
+ * (ci0, cj0, cnx, cny) of the coarse grid qc [3M][nyc][nxc] become the
+ * row-major sum of their children times 1/r^2 for every field, from qf
+ * [3M][r cny][r cnx] (the children of the box, child (a, b) of box cell
+ * (I, J) at column r I + a and row r J + b), then thin layers are dried and
+ * every layer below a dry one too.  Cells of qc outside the box are left
+ * as they are.  Errors: MLSWE_EINVAL (M or r outside 1..8, the box outside the
+ * grid, more than 262140 rows, a null array), MLSWE_EDEVICE. */
+int mlswe_coarsen_layers(mlswe_ctx* ctx, int M, int r, const double* qf, int ci0, int cj0, int cnx, int cny, double* qc,
+                         int nxc, int nyc);
+
 /* The union ("run") tiles a batched substep sweeps for one level of one
  * problem (host only, no GPU needed; for inspection and tests).  The level is
  * nx x ny cells with nbox patch boxes (ilo, jlo, nx, ny; int32, host memory,

@@ -3,6 +3,10 @@
 Every step of the computation runs in the HIP library ``libmlswe.so``; this
 module only converts arrays and codes.  It refuses to run without the library:
 there is no CPU fallback.
+
+Callers that pass torch device tensors initialise torch's GPU runtime
+(``torch.cuda.init()``) before creating a Solver, and give the Solver torch's
+stream so that the library's launches and torch's work are ordered.
 """
 from __future__ import annotations
 
@@ -93,6 +97,8 @@ def lib():
             "mlswe_set_tuning": (I, [P, ctypes.POINTER(Tuning)]),
             "mlswe_autotune": (I, [P, ctypes.c_char_p, I]),
             "mlswe_run_tiles": (I, [I, I, I, I32P, I, I, I32P, I]),
+            "mlswe_refine_layers": (I, [P, I, I, V, V, I, I, I, I, I, I, V, V, ctypes.POINTER(ctypes.c_int64)]),
+            "mlswe_coarsen_layers": (I, [P, I, I, V, I, I, I, I, V, I, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -303,3 +309,35 @@ class Solver:
         n = (ctypes.c_int64 * 2)()
         self._check(self.L.mlswe_kernel_times(self.h, ms, n))
         return [ms[0], ms[1]], [int(n[0]), int(n[1])]
+
+    # ------------------------------------------------------------ M layers
+    def _dev(self, t, shape):
+        if not (hasattr(t, "is_cuda") and t.is_cuda) or not t.is_contiguous() or str(t.dtype) != "torch.float64":
+            raise TypeError("expected a contiguous float64 device tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("shape %s, expected %s" % (tuple(t.shape), tuple(shape)))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def refine_layers(self, qc, Bc, Bf, qf, r, box=None, want_repairs=False):
+        """Fine cells of box (fi0, fj0, fnx, fny) (default: the whole fine grid)
+        refined from the coarse state qc [3M][nyc][nxc] with bathymetry Bc into
+        qf [3M][fny][fnx], fine bathymetry Bf [fny][fnx] (device float64
+        tensors).  Returns the number of wet-ordering repairs if asked."""
+        M = qc.shape[0] // 3
+        nyc, nxc = Bc.shape
+        fi0, fj0, fnx, fny = box if box is not None else (0, 0, r * nxc, r * nyc)
+        n = ctypes.c_int64()
+        self._check(self.L.mlswe_refine_layers(
+            self.h, M, r, self._dev(qc, (3 * M, nyc, nxc)), self._dev(Bc, (nyc, nxc)), nxc, nyc, fi0, fj0, fnx, fny,
+            self._dev(Bf, (fny, fnx)), self._dev(qf, (3 * M, fny, fnx)), ctypes.byref(n) if want_repairs else None))
+        return n.value if want_repairs else None
+
+    def coarsen_layers(self, qf, qc, r, origin=(0, 0)):
+        """Coarse cells of the box at origin (ci0, cj0) of qc [3M][nyc][nxc]
+        from their children qf [3M][r cny][r cnx] (device float64 tensors)."""
+        M = qc.shape[0] // 3
+        _, nyc, nxc = qc.shape
+        cny, cnx = qf.shape[1] // r, qf.shape[2] // r
+        self._check(self.L.mlswe_coarsen_layers(
+            self.h, M, r, self._dev(qf, (3 * M, r * cny, r * cnx)), origin[0], origin[1], cnx, cny,
+            self._dev(qc, (3 * M, nyc, nxc)), nxc, nyc))

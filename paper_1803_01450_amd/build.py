@@ -13,8 +13,10 @@ CSRC = os.path.join(HERE, "csrc")
 SRCS = [(os.path.join(CSRC, "mlswe_kernels.hip"), []),
         (os.path.join(CSRC, "mlswe_sweeps_fast.hip"), ["-ffp-contract=fast"]),
         (os.path.join(CSRC, "mlswe_adjoint.hip"), []),
+        (os.path.join(CSRC, "mlswe_layers.hip"), []),
         (os.path.join(CSRC, "mlswe_lib.cpp"), [])]
 HDRS = [os.path.join(HERE, "csrc", "mlswe_kernels.hpp"), os.path.join(HERE, "csrc", "mlswe_device.hpp"),
+        os.path.join(HERE, "csrc", "mlswe_layers.hpp"),
         os.path.join(ROOT, "include", "mlswe.h")]
 ARCH = os.environ.get("MLSWE_ARCH", "gfx950")
 

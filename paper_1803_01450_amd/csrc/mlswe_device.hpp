@@ -382,9 +382,10 @@ __device__ __forceinline__ void fixup(const PhysParams& P, double q[6], bool cou
     q[3] = 0.0; q[4] = 0.0; q[5] = 0.0;
   }
   if (CHECK) {
-    // NaN or infinity in some field of some lane of the wave (kept wave-wide)
-    const double sum = ((q[0] + q[1]) + (q[2] + q[3])) + (q[4] + q[5]);
-    K.nonfinite |= __builtin_amdgcn_ballot_w64(sum - sum != 0.0) != 0ull ? 1 : 0;
+    // NaN or infinity in a depth of some lane of the wave (kept wave-wide).  A
+    // non-finite momentum reaches the depths through the fluxes of the next
+    // sweep along it (the normal momentum is the depth's flux).
+    K.nonfinite |= __builtin_amdgcn_ballot_w64(!__builtin_isfinite(q[0] + q[3])) != 0ull ? 1 : 0;
   }
 }
 

@@ -17,6 +17,7 @@
 
 #include "../../include/mlswe.h"
 #include "mlswe_kernels.hpp"
+#include "mlswe_layers.hpp"
 
 using namespace mlswe;
 
@@ -178,6 +179,8 @@ struct mlswe_ctx {
   int ftl_cap = 0;
   unsigned char* tbits_d = nullptr;
   int tbits_cap = 0;
+  unsigned long long* lrep_d = nullptr;  // repair counter of the M-layer refine
+  int lrep_cap = 0;
 };
 
 namespace {
@@ -1288,7 +1291,7 @@ int mlswe_destroy(mlswe_ctx* c) {
   dfree(c->ctl); dfree(c->cnt); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
   dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d); dfree(c->boxes_d);
   dfree(c->bsegs_d); dfree(c->mboxes_d); dfree(c->rfills_d); dfree(c->flv_d);
-  dfree(c->ftl_d); dfree(c->tbits_d);
+  dfree(c->ftl_d); dfree(c->tbits_d); dfree(c->lrep_d);
   if (c->pin) (void)hipHostFree(c->pin);
   if (c->ctl_pin) (void)hipHostFree(c->ctl_pin);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -1534,6 +1537,71 @@ int mlswe_regrid(mlswe_ctx* c, int p, const double* tau, int nbuf) {
   if (!c) return MLSWE_EINVAL;
   if (!valid_prob(c, p) || !tau || nbuf < 0) return fail(c, MLSWE_EINVAL, "bad args");
   return regrid_impl(c, p, tau, nbuf);
+}
+
+int mlswe_refine_layers(mlswe_ctx* c, int M, int r, const double* qc, const double* Bc, int nxc, int nyc, int fi0,
+                        int fj0, int fnx, int fny, const double* Bf, double* qf, int64_t* repairs_out) {
+  if (!c) return MLSWE_EINVAL;
+  if (M < 1 || M > LAYERS_MAX) return fail(c, MLSWE_EINVAL, "layers %d outside 1..%d", M, LAYERS_MAX);
+  if (r < 1 || r > 8) return fail(c, MLSWE_EINVAL, "ratio %d outside 1..8", r);
+  if (nxc < 1 || nyc < 1 || fi0 < 0 || fj0 < 0 || fnx < 0 || fny < 0 ||
+      (long long)fi0 + fnx > (long long)r * nxc || (long long)fj0 + fny > (long long)r * nyc)
+    return fail(c, MLSWE_EINVAL, "fine box (%d, %d, %d, %d) outside the %d x %d coarse grid at ratio %d", fi0, fj0,
+                fnx, fny, nxc, nyc, r);
+  if ((long long)nxc * nyc * 3 * M > (1ll << 40) || (long long)fnx * fny * 3 * M > (1ll << 40))
+    return fail(c, MLSWE_EINVAL, "grid too large");
+  const long long nI = fnx ? (fi0 + fnx - 1) / r - fi0 / r + 1 : 0;
+  const long long nJ = fny ? (fj0 + fny - 1) / r - fj0 / r + 1 : 0;
+  if ((nJ + 3) / 4 > 65535) return fail(c, MLSWE_EINVAL, "more than 262140 coarse rows");
+  if (repairs_out) *repairs_out = 0;
+  if (nI == 0 || nJ == 0) return MLSWE_OK;
+  if (!qc || !Bc || !Bf || !qf) return fail(c, MLSWE_EINVAL, "null array");
+  LayersRefine A;
+  A.qc = qc; A.Bc = Bc; A.Bf = Bf; A.qf = qf;
+  A.repairs = nullptr;
+  A.cplane = (long long)nxc * nyc;
+  A.fplane = (long long)fnx * fny;
+  A.nxc = nxc; A.nyc = nyc; A.r = r;
+  A.fi0 = fi0; A.fj0 = fj0; A.fnx = fnx; A.fny = fny;
+  A.I0 = fi0 / r; A.J0 = fj0 / r; A.nI = (int)nI; A.nJ = (int)nJ;
+  A.hdry = c->cfg.hdry;
+  if (repairs_out) {
+    int rc = ensure(c, &c->lrep_d, &c->lrep_cap, 1);
+    if (rc) return rc;
+    HIPCHK(c, hipMemsetAsync(c->lrep_d, 0, sizeof(unsigned long long), c->stream));
+    A.repairs = c->lrep_d;
+  }
+  HIPCHK(c, launch_refine_layers(M, A, c->stream));
+  if (repairs_out) {
+    unsigned long long n = 0;
+    HIPCHK(c, hipMemcpyAsync(&n, c->lrep_d, sizeof n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *repairs_out = (int64_t)n;
+  }
+  return MLSWE_OK;
+}
+
+int mlswe_coarsen_layers(mlswe_ctx* c, int M, int r, const double* qf, int ci0, int cj0, int cnx, int cny, double* qc,
+                         int nxc, int nyc) {
+  if (!c) return MLSWE_EINVAL;
+  if (M < 1 || M > LAYERS_MAX) return fail(c, MLSWE_EINVAL, "layers %d outside 1..%d", M, LAYERS_MAX);
+  if (r < 1 || r > 8) return fail(c, MLSWE_EINVAL, "ratio %d outside 1..8", r);
+  if (nxc < 1 || nyc < 1 || ci0 < 0 || cj0 < 0 || cnx < 0 || cny < 0 || (long long)ci0 + cnx > nxc ||
+      (long long)cj0 + cny > nyc)
+    return fail(c, MLSWE_EINVAL, "coarse box (%d, %d, %d, %d) outside the %d x %d grid", ci0, cj0, cnx, cny, nxc, nyc);
+  if ((long long)nxc * nyc * 3 * M > (1ll << 40) || (long long)cnx * cny * r * r * 3 * M > (1ll << 40))
+    return fail(c, MLSWE_EINVAL, "grid too large");
+  if ((cny + 3) / 4 > 65535) return fail(c, MLSWE_EINVAL, "more than 262140 coarse rows");
+  if (cnx == 0 || cny == 0) return MLSWE_OK;
+  if (!qf || !qc) return fail(c, MLSWE_EINVAL, "null array");
+  LayersCoarsen A;
+  A.qf = qf; A.qc = qc;
+  A.cplane = (long long)nxc * nyc;
+  A.fplane = (long long)cnx * cny * r * r;
+  A.nxc = nxc; A.r = r; A.ci0 = ci0; A.cj0 = cj0; A.cnx = cnx; A.cny = cny;
+  A.hdry = c->cfg.hdry;
+  HIPCHK(c, launch_coarsen_layers(M, A, c->stream));
+  return MLSWE_OK;
 }
 
 }  // extern "C"

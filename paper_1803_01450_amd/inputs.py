@@ -228,3 +228,39 @@ def adjoint_problem(n=1024, L=102.4e3, seed=SEED0 + 5):
     tg = 0.05 * np.sin(2 * np.pi * tk / 23.0) + 0.01 * rng.standard_normal((nsamp, gn, gn))
     return dict(n=n, L=L, dx=dx, B=B, eta1=eta1, eta2=-50.0, r=0.95,
                 gauge=(gi0, gj0, gn), nsteps=400, every=10, ckpt=20, targets=tg)
+
+
+def layered_problem(M, nxc, nyc, r, seed=SEED0 + 6, L=100e3):
+    """M-layer coarse grid (nxc x nyc) with a shore: the fine bathymetry (ratio
+    r) rises along x from -1000 m to +40 m with smooth bumps of +-40 m; the
+    coarse bathymetry is its r x r block mean.  Layer surfaces sit at
+    -900 (m - 1) / M m plus smooth +-2 m perturbations (layer 1 on top), so the
+    lower layers end one after another towards the shore.  Depths from the
+    bottom up (thin ones dry, every layer below a dry one dry), momenta smooth
+    random in +-2 m^2/s per metre of depth.  Returns dict(qc [3M][nyc][nxc], Bc,
+    Bf [r nyc][r nxc])."""
+    rng = np.random.default_rng(seed + 97 * M + r)
+    nxf, nyf = r * nxc, r * nyc
+    x = centres(nxf, L)
+    ramp = -1000.0 + 1040.0 * (x / L)
+    Bf = ramp[None, :] + smooth_field(rng, nxf, L, 8, -40.0, 40.0, ny=nyf, Ly=L * nyc / nxc)
+    Bc = block_mean(Bf, r)
+    h = np.zeros((M + 1, nyc, nxc))
+    eta = [None] + [(-900.0 * (m - 1) / M) + smooth_field(rng, nxc, L, 6, -2.0, 2.0, ny=nyc, Ly=L * nyc / nxc)
+                    for m in range(1, M + 1)]
+    below = Bc.copy()
+    for m in range(M, 0, -1):
+        hm = np.maximum(eta[m] - below, 0.0)
+        hm = np.where(hm < HDRY, 0.0, hm)
+        h[m] = hm
+        below = below + hm
+    dry = np.zeros((nyc, nxc), dtype=bool)
+    for m in range(1, M + 1):
+        h[m] = np.where(dry, 0.0, h[m])
+        dry |= h[m] == 0.0
+    qc = np.zeros((3 * M, nyc, nxc))
+    for m in range(1, M + 1):
+        qc[3 * (m - 1)] = h[m]
+        qc[3 * (m - 1) + 1] = h[m] * smooth_field(rng, nxc, L, 4, -2.0, 2.0, ny=nyc, Ly=L * nyc / nxc)
+        qc[3 * (m - 1) + 2] = h[m] * smooth_field(rng, nxc, L, 4, -2.0, 2.0, ny=nyc, Ly=L * nyc / nxc)
+    return dict(qc=qc, Bc=Bc, Bf=Bf)

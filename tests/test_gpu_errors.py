@@ -3,7 +3,7 @@ cell set to NaN on the host before the run) must end a run with MLSWE_ENAN in
 every launch mode, in a batch as well (the other problems' flags stay clear),
 and in a fixed-dt substep that asks for the wave speeds.  The wave-speed
 maximum alone can miss a NaN (a comparison with NaN is false), so the x-sweep
-checks the updated cells themselves."""
+checks the depths of the cells it updates."""
 import sys
 
 import numpy as np
@@ -25,15 +25,18 @@ def poisoned(c, field=1, i=20, j=30):
     return q
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
-def test_nan_state_ends_run(mode):
+@pytest.mark.parametrize("mode,field", [(0, 1), (1, 2), (2, 3)])
+def test_nan_state_ends_run(mode, field):
+    """A NaN depth or normal momentum is seen by the first x-sweep; a NaN
+    transverse momentum reaches the depths in the y-sweep and is seen by the
+    next step's x-sweep."""
     from paper_1803_01450_amd import binding
-    say("case: NaN in one cell, 64x64 with a fine patch, advance, mode", mode)
+    say("case: NaN in field %d of one cell, 64x64 with a fine patch, advance, mode %d" % (field, mode))
     c = inputs.fixed_small()
     S = binding.Solver()
     p = S.define(64, 64, c["dx"], c["dx"], c["r"], (2,))
     S.set_bathymetry(p, c["Bf"])
-    S.set_state(p, 0, poisoned(c))
+    S.set_state(p, 0, poisoned(c, field=field))
     S.refine(p, 1, [(16, 16, 32, 32)])
     with pytest.raises(binding.MlsweError) as e:
         S.advance(3, 0, None, mode=mode)
