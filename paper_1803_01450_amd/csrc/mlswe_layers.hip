@@ -16,6 +16,8 @@
 //
 // Coarsen: one lane per coarse cell; the row-major sum of its children times
 // 1/r^2 for every field, then the same fix-up (thin layers dry, wet ordering).
+// For even r the children move in 16-byte pairs (loads for coarsen, stores
+// for refine) where the layout allows it.
 #include <hip/hip_runtime.h>
 
 #include "mlswe_layers.hpp"
@@ -29,7 +31,52 @@ __device__ __forceinline__ double minmod2(double a, double b) {
   return 0.0;
 }
 
+// Per-layer interpolation data of one coarse cell (register arrays).
 template <int M>
+struct LayerSlopes {
+  double e[M], sex[M], sey[M], u[M], sux[M], suy[M], v[M], svx[M], svy[M];
+  bool wc[M];
+};
+
+// Depths of one child at fractions (fa, fb) over fine bathymetry Bf: from the
+// bottom layer up through the effective bathymetry, thin ones dry, then the
+// wet ordering (repairs counted).
+template <int M>
+__device__ __forceinline__ void child_depths(const LayerSlopes<M>& S, double fa, double fb, double Bf, double hdry,
+                                             double h[M], unsigned& rep) {
+  double Bhat = Bf;
+#pragma unroll
+  for (int m = M - 1; m >= 0; --m) {
+    const double ef = (S.e[m] + S.sex[m] * fa) + S.sey[m] * fb;
+    double hm = S.wc[m] ? ef - Bhat : 0.0;
+    if (hm < hdry) hm = 0.0;
+    h[m] = hm;
+    Bhat = Bhat + hm;
+  }
+  bool dry_above = false;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    if (dry_above && h[m] > 0.0) { h[m] = 0.0; ++rep; }
+    if (h[m] == 0.0) dry_above = true;
+  }
+}
+
+// Momenta of layer m of a child: the limited interpolant where the fine layer
+// is wet, else zero.
+template <int M>
+__device__ __forceinline__ double mom_u(const LayerSlopes<M>& S, int m, double fa, double fb, double h) {
+  return h > 0.0 ? (S.u[m] + S.sux[m] * fa) + S.suy[m] * fb : 0.0;
+}
+template <int M>
+__device__ __forceinline__ double mom_v(const LayerSlopes<M>& S, int m, double fa, double fb, double h) {
+  return h > 0.0 ? (S.v[m] + S.svx[m] * fa) + S.svy[m] * fb : 0.0;
+}
+
+// PAIRS: r even and every pair of children (a, a + 1), a even, lies on a
+// 16-byte boundary of the fine box (even box origin and width, 16-byte aligned
+// arrays): each pair is written with one 16-byte store per field, so the
+// lanes of a wave fill a contiguous span of the fine row with each store.
+template <int M, bool PAIRS>
 __global__ __launch_bounds__(256) void k_refine_layers(LayersRefine A) {
   const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
   const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -42,8 +89,7 @@ __global__ __launch_bounds__(256) void k_refine_layers(LayersRefine A) {
     // an absent neighbour reads the centre; its slope is then zero anyway
     const long long kl = inx ? k0 - 1 : k0, kr = inx ? k0 + 1 : k0;
     const long long kd = iny ? k0 - A.nxc : k0, ku = iny ? k0 + A.nxc : k0;
-    double e[M], sex[M], sey[M], u[M], sux[M], suy[M], v[M], svx[M], svy[M];
-    bool wc[M];
+    LayerSlopes<M> S;
     double s0 = A.Bc[k0], sl = A.Bc[kl], sr = A.Bc[kr], sd = A.Bc[kd], su = A.Bc[ku];
 #pragma unroll
     for (int m = M - 1; m >= 0; --m) {  // layer m + 1, bottom layer first
@@ -53,54 +99,62 @@ __global__ __launch_bounds__(256) void k_refine_layers(LayersRefine A) {
       const bool w0 = h0 >= A.hdry;
       const bool okx = inx && hl >= A.hdry && w0 && hr >= A.hdry;
       const bool oky = iny && hd >= A.hdry && w0 && hu >= A.hdry;
-      wc[m] = w0;
-      e[m] = s0;
-      sex[m] = okx ? minmod2(s0 - sl, sr - s0) : 0.0;
-      sey[m] = oky ? minmod2(s0 - sd, su - s0) : 0.0;
+      S.wc[m] = w0;
+      S.e[m] = s0;
+      S.sex[m] = okx ? minmod2(s0 - sl, sr - s0) : 0.0;
+      S.sey[m] = oky ? minmod2(s0 - sd, su - s0) : 0.0;
       const double* pu = h + A.cplane;
       const double u0 = pu[k0];
-      u[m] = u0;
-      sux[m] = okx ? minmod2(u0 - pu[kl], pu[kr] - u0) : 0.0;
-      suy[m] = oky ? minmod2(u0 - pu[kd], pu[ku] - u0) : 0.0;
+      S.u[m] = u0;
+      S.sux[m] = okx ? minmod2(u0 - pu[kl], pu[kr] - u0) : 0.0;
+      S.suy[m] = oky ? minmod2(u0 - pu[kd], pu[ku] - u0) : 0.0;
       const double* pv = pu + A.cplane;
       const double v0 = pv[k0];
-      v[m] = v0;
-      svx[m] = okx ? minmod2(v0 - pv[kl], pv[kr] - v0) : 0.0;
-      svy[m] = oky ? minmod2(v0 - pv[kd], pv[ku] - v0) : 0.0;
+      S.v[m] = v0;
+      S.svx[m] = okx ? minmod2(v0 - pv[kl], pv[kr] - v0) : 0.0;
+      S.svy[m] = oky ? minmod2(v0 - pv[kd], pv[ku] - v0) : 0.0;
     }
     const int r = A.r;
     for (int b = 0; b < r; ++b) {
       const int fj = r * J + b - A.fj0;
       if (fj < 0 || fj >= A.fny) continue;
       const double fb = double(2 * b + 1 - r) / double(2 * r);
-      for (int a = 0; a < r; ++a) {
-        const int fi = r * I + a - A.fi0;
-        if (fi < 0 || fi >= A.fnx) continue;
-        const double fa = double(2 * a + 1 - r) / double(2 * r);
-        const long long kf = (long long)fj * A.fnx + fi;
-        double h[M];
-        double Bhat = A.Bf[kf];
+      if (PAIRS) {
+        for (int a = 0; a < r; a += 2) {
+          const int fi = r * I + a - A.fi0;  // even; the pair lies wholly inside or outside the box
+          if (fi < 0 || fi >= A.fnx) continue;
+          const double fa0 = double(2 * a + 1 - r) / double(2 * r);
+          const double fa1 = double(2 * a + 3 - r) / double(2 * r);
+          const long long kf = (long long)fj * A.fnx + fi;
+          const double2 B2 = *reinterpret_cast<const double2*>(A.Bf + kf);
+          double h0[M], h1[M];
+          child_depths<M>(S, fa0, fb, B2.x, A.hdry, h0, rep);
+          child_depths<M>(S, fa1, fb, B2.y, A.hdry, h1, rep);
 #pragma unroll
-        for (int m = M - 1; m >= 0; --m) {
-          const double ef = (e[m] + sex[m] * fa) + sey[m] * fb;
-          double hm = wc[m] ? ef - Bhat : 0.0;
-          if (hm < A.hdry) hm = 0.0;
-          h[m] = hm;
-          Bhat = Bhat + hm;
+          for (int m = 0; m < M; ++m) {
+            double* o = A.qf + 3 * m * A.fplane + kf;
+            *reinterpret_cast<double2*>(o) = make_double2(h0[m], h1[m]);
+            *reinterpret_cast<double2*>(o + A.fplane) =
+                make_double2(mom_u<M>(S, m, fa0, fb, h0[m]), mom_u<M>(S, m, fa1, fb, h1[m]));
+            *reinterpret_cast<double2*>(o + 2 * A.fplane) =
+                make_double2(mom_v<M>(S, m, fa0, fb, h0[m]), mom_v<M>(S, m, fa1, fb, h1[m]));
+          }
         }
-        bool dry_above = false;
+      } else {
+        for (int a = 0; a < r; ++a) {
+          const int fi = r * I + a - A.fi0;
+          if (fi < 0 || fi >= A.fnx) continue;
+          const double fa = double(2 * a + 1 - r) / double(2 * r);
+          const long long kf = (long long)fj * A.fnx + fi;
+          double h[M];
+          child_depths<M>(S, fa, fb, A.Bf[kf], A.hdry, h, rep);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-          if (dry_above && h[m] > 0.0) { h[m] = 0.0; ++rep; }
-          if (h[m] == 0.0) dry_above = true;
-        }
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          double* o = A.qf + 3 * m * A.fplane + kf;
-          const bool wet = h[m] > 0.0;
-          o[0] = h[m];
-          o[A.fplane] = wet ? (u[m] + sux[m] * fa) + suy[m] * fb : 0.0;
-          o[2 * A.fplane] = wet ? (v[m] + svx[m] * fa) + svy[m] * fb : 0.0;
+          for (int m = 0; m < M; ++m) {
+            double* o = A.qf + 3 * m * A.fplane + kf;
+            o[0] = h[m];
+            o[A.fplane] = mom_u<M>(S, m, fa, fb, h[m]);
+            o[2 * A.fplane] = mom_v<M>(S, m, fa, fb, h[m]);
+          }
         }
       }
     }
@@ -111,7 +165,9 @@ __global__ __launch_bounds__(256) void k_refine_layers(LayersRefine A) {
   }
 }
 
-template <int M>
+// PAIRS: r even and a 16-byte aligned fine array: children read two at a time
+// (16-byte loads, contiguous across the lanes), summed in the same order.
+template <int M, bool PAIRS>
 __global__ __launch_bounds__(256) void k_coarsen_layers(LayersCoarsen A) {
   const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
   const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -124,8 +180,17 @@ __global__ __launch_bounds__(256) void k_coarsen_layers(LayersCoarsen A) {
   for (int f = 0; f < 3 * M; ++f) {
     const double* p = A.qf + f * A.fplane + (long long)r * gy * fnx + (long long)r * gx;
     double s = 0.0;
-    for (int bb = 0; bb < r; ++bb)
-      for (int aa = 0; aa < r; ++aa) s = s + p[bb * fnx + aa];
+    for (int bb = 0; bb < r; ++bb) {
+      if (PAIRS) {
+        for (int aa = 0; aa < r; aa += 2) {
+          const double2 v = *reinterpret_cast<const double2*>(p + bb * fnx + aa);
+          s = s + v.x;
+          s = s + v.y;
+        }
+      } else {
+        for (int aa = 0; aa < r; ++aa) s = s + p[bb * fnx + aa];
+      }
+    }
     q[f] = s * inv;
   }
 #pragma unroll
@@ -144,13 +209,23 @@ __global__ __launch_bounds__(256) void k_coarsen_layers(LayersCoarsen A) {
 
 template <int M>
 hipError_t refine_m(const LayersRefine& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_layers<M>, dim3((A.nI + 63) / 64, (A.nJ + 3) / 4), dim3(256), 0, s, A);
+  const dim3 grid((A.nI + 63) / 64, (A.nJ + 3) / 4);
+  const bool pairs = A.r % 2 == 0 && A.fi0 % 2 == 0 && A.fnx % 2 == 0 &&
+                     (reinterpret_cast<uintptr_t>(A.qf) & 15) == 0 && (reinterpret_cast<uintptr_t>(A.Bf) & 15) == 0;
+  if (pairs)
+    hipLaunchKernelGGL((k_refine_layers<M, true>), grid, dim3(256), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_refine_layers<M, false>), grid, dim3(256), 0, s, A);
   return hipGetLastError();
 }
 
 template <int M>
 hipError_t coarsen_m(const LayersCoarsen& A, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarsen_layers<M>, dim3((A.cnx + 63) / 64, (A.cny + 3) / 4), dim3(256), 0, s, A);
+  const dim3 grid((A.cnx + 63) / 64, (A.cny + 3) / 4);
+  if (A.r % 2 == 0 && (reinterpret_cast<uintptr_t>(A.qf) & 15) == 0)
+    hipLaunchKernelGGL((k_coarsen_layers<M, true>), grid, dim3(256), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_coarsen_layers<M, false>), grid, dim3(256), 0, s, A);
   return hipGetLastError();
 }
 
