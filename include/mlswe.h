@@ -140,7 +140,9 @@ int mlswe_get_patches(mlswe_ctx* ctx, int p, int level, int cap, int32_t* boxes,
 
 /* Level-wide state q[6][ny_l][nx_l] into / out of the level's current buffer.
  * get_state writes NaN where no patch covers a cell (for a device destination
- * the copy is queued on the context's stream; for a host one it synchronises).
+ * the copy is queued on the context's stream; for a host one it synchronises);
+ * set_state zeroes such cells of levels > 0 (their values are never used, so a
+ * get_state result can be handed back as it is).
  * Errors: MLSWE_EINVAL. */
 int mlswe_set_state(mlswe_ctx* ctx, int p, int level, const double* q, int where);
 int mlswe_get_state(mlswe_ctx* ctx, int p, int level, double* q, int where);
@@ -190,6 +192,20 @@ int mlswe_regrid(mlswe_ctx* ctx, int p, const double* tau, int nbuf);
  * number). */
 int mlswe_advance(mlswe_ctx* ctx, int n_coarse_steps, int regrid_every, const double* tau, int nbuf,
                   int mode, double* dts_out);
+
+/* Time-stepping state of problem p, for checkpoint and resume: out / in
+ * [2 + 2 n_levels] holds t, 1 if the next coarse step takes its dt from the
+ * largest speeds of the last one (0: from the state, as for a fresh problem),
+ * and each level's largest x and y speeds over the last coarse step.  With
+ * every level's patches (mlswe_set_patches, coarsest first) and state
+ * (mlswe_set_state) restored into a new context, setting it continues the run
+ * bit for bit (regrids fall on the same steps if the restart step is a
+ * multiple of regrid_every).  In a batched advance, a problem without speeds
+ * makes every problem of the batch take the next dt from its state.  Both
+ * synchronise.  Errors: MLSWE_EINVAL (flag other than 0 or 1, t NaN, a speed
+ * negative or not finite). */
+int mlswe_get_step_state(mlswe_ctx* ctx, int p, double* out);
+int mlswe_set_step_state(mlswe_ctx* ctx, int p, const double* in);
 
 /* Reads / sets the sweeps' launch shape (setting rebuilds the launch data). */
 int mlswe_get_tuning(mlswe_ctx* ctx, mlswe_tuning* out);

@@ -64,6 +64,8 @@ def lib():
         for name in ["ora_set_bathymetry"]:
             getattr(L, name).argtypes = [_P, _DP]
         L.ora_get_bathymetry.argtypes = [_P, _I, _DP]
+        L.ora_get_step_state.argtypes = [_P, _DP]
+        L.ora_set_step_state.argtypes = [_P, _DP]
         L.ora_set_state.argtypes = [_P, _I, _DP]
         L.ora_get_state.argtypes = [_P, _I, _DP]
         L.ora_level_shape.argtypes = [_P, _I, _IP, _IP, _DP, _DP]
@@ -287,6 +289,18 @@ class Hierarchy:
 
     def next_dt(self):
         return lib().ora_next_dt(self.h)
+
+    def step_state(self):
+        """[t, speeds-known flag, per level largest x / y speeds of the last
+        coarse step]: what a resumed run needs besides states and patches."""
+        out = np.zeros(2 + 2 * self.nlev)
+        lib().ora_get_step_state(self.h, _dp(out))
+        return out
+
+    def set_step_state(self, v):
+        v = _f64(v)
+        assert v.shape == (2 + 2 * self.nlev,)
+        lib().ora_set_step_state(self.h, _dp(v))
 
     def counters(self):
         c = np.zeros(15)

@@ -651,6 +651,24 @@ int ora_advance(void* h, int nsteps, int regrid_every, const double* tau, int nb
 
 double ora_next_dt(void* h) { return next_dt(*static_cast<Hier*>(h)); }
 
+// Time-stepping state for checkpoint and resume: t, whether the next coarse
+// step takes its dt from the last step's speeds (else from the state), and each
+// level's largest x / y speeds over the last coarse step.  out / in:
+// [2 + 2 * nlev].
+void ora_get_step_state(void* h, double* out) {
+  Hier* H = static_cast<Hier*>(h);
+  out[0] = H->t;
+  out[1] = H->have_smax ? 1.0 : 0.0;
+  for (int l = 0; l < H->nlev; ++l) { out[2 + 2 * l] = H->L[l].smax[0]; out[3 + 2 * l] = H->L[l].smax[1]; }
+}
+
+void ora_set_step_state(void* h, const double* in) {
+  Hier* H = static_cast<Hier*>(h);
+  H->t = in[0];
+  H->have_smax = in[1] != 0.0;
+  for (int l = 0; l < H->nlev; ++l) { H->L[l].smax[0] = in[2 + 2 * l]; H->L[l].smax[1] = in[3 + 2 * l]; }
+}
+
 // [hyp, nclip, repair, clip1, clip2, t, updates level 0..7, rejected steps]
 void ora_counters(void* h, double* out) {
   Hier* H = static_cast<Hier*>(h);

@@ -97,6 +97,8 @@ def lib():
             "mlswe_set_tuning": (I, [P, ctypes.POINTER(Tuning)]),
             "mlswe_autotune": (I, [P, ctypes.c_char_p, I]),
             "mlswe_run_tiles": (I, [I, I, I, I32P, I, I, I32P, I]),
+            "mlswe_get_step_state": (I, [P, I, DP]),
+            "mlswe_set_step_state": (I, [P, I, DP]),
             "mlswe_refine_layers": (I, [P, I, I, V, V, I, I, I, I, I, I, V, V, ctypes.POINTER(ctypes.c_int64)]),
             "mlswe_coarsen_layers": (I, [P, I, I, V, I, I, I, I, V, I, I]),
         }
@@ -309,6 +311,21 @@ class Solver:
         n = (ctypes.c_int64 * 2)()
         self._check(self.L.mlswe_kernel_times(self.h, ms, n))
         return [ms[0], ms[1]], [int(n[0]), int(n[1])]
+
+    # ------------------------------------------------------------ checkpoint / resume
+    def step_state(self, p):
+        """[t, speeds-known flag, per level largest x / y speeds of the last
+        coarse step] of problem p."""
+        n = len(self.shapes[p])
+        out = np.zeros(2 + 2 * n)
+        self._check(self.L.mlswe_get_step_state(self.h, p, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def set_step_state(self, p, v):
+        v = _f64(v)
+        if v.shape != (2 + 2 * len(self.shapes[p]),):
+            raise ValueError("expected %d values" % (2 + 2 * len(self.shapes[p])))
+        self._check(self.L.mlswe_set_step_state(self.h, p, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     # ------------------------------------------------------------ M layers
     def _dev(self, t, shape):

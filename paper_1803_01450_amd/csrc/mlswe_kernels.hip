@@ -408,6 +408,20 @@ __global__ __launch_bounds__(256) void k_nan_uncovered(double* q, const unsigned
   for (int f = 0; f < 6; ++f) q[f * pu + t] = nan;
 }
 
+// Cells of a level that no patch covers set to zero (all six fields) in the
+// level's own buffer: values handed in there are never used, and a non-finite
+// one would otherwise reach the non-finite check of the union-tile x-sweep.
+__global__ __launch_bounds__(256) void k_zero_uncovered(double* q, const unsigned char* __restrict__ mask,
+                                                        long long pitch, long long plane, int nx, int ny) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nx * ny) return;
+  const int i = (int)(t % nx), j = (int)(t / nx);
+  const long long k = cidx(pitch, i, j);
+  if (mask[k]) return;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) q[f * plane + k] = 0.0;
+}
+
 // Byte runs in one launch (block row y: run y), copied or filled.
 __global__ __launch_bounds__(256) void k_byte_segs(const ByteSeg* __restrict__ segs) {
   const ByteSeg S = segs[blockIdx.y];

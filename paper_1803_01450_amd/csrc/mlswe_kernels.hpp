@@ -231,6 +231,8 @@ __global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo*
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
 __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial);
 __global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);
+__global__ void k_zero_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, long long plane,
+                                 int nx, int ny);
 // A contiguous run of doubles to copy (one row range of one field plane).
 // A box of nf fields copied between two arrays of the same layout: element
 // (f, a, b) at f * plane + b * pitch + a from the box origins src / dst.  A

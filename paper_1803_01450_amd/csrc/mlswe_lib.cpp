@@ -1453,7 +1453,51 @@ int mlswe_set_state(mlswe_ctx* c, int p, int level, const double* q, int where) 
   LevelH& L = P.L[level];
   int rc = copy_state(c, L, L.cur, q, where, true, nullptr);
   if (rc) return rc;
+  if (level > 0) {
+    const long long pu = (long long)L.nx * L.ny;
+    hipLaunchKernelGGL(k_zero_uncovered, dim3((unsigned)((pu + 255) / 256)), dim3(256), 0, c->stream, L.q[L.cur],
+                       L.mask, L.pitch, L.plane, L.nx, L.ny);
+    HIPCHK(c, hipGetLastError());
+  }
   P.state = true;
+  return MLSWE_OK;
+}
+
+int mlswe_get_step_state(mlswe_ctx* c, int p, double* out) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || !out) return fail(c, MLSWE_EINVAL, "bad args");
+  const ProblemH& P = c->probs[p];
+  std::vector<LevelCtl> h((size_t)P.nlev);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->ctl + P.ctl0, sizeof(LevelCtl) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out[0] = h[0].t;
+  out[1] = P.have_dt ? 1.0 : 0.0;
+  for (int l = 0; l < P.nlev; ++l) {
+    out[2 + 2 * l] = __builtin_bit_cast(double, (long long)h[l].acc_smax[0]);
+    out[3 + 2 * l] = __builtin_bit_cast(double, (long long)h[l].acc_smax[1]);
+  }
+  return MLSWE_OK;
+}
+
+int mlswe_set_step_state(mlswe_ctx* c, int p, const double* in) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || !in) return fail(c, MLSWE_EINVAL, "bad args");
+  ProblemH& P = c->probs[p];
+  if (!(in[0] == in[0]) || (in[1] != 0.0 && in[1] != 1.0)) return fail(c, MLSWE_EINVAL, "bad time or flag");
+  for (int l = 0; l < 2 * P.nlev; ++l)
+    if (!(in[2 + l] >= 0.0) || std::signbit(in[2 + l]) || in[2 + l] == std::numeric_limits<double>::infinity())
+      return fail(c, MLSWE_EINVAL, "speed %g of level %d is not finite and non-negative", in[2 + l], l / 2);
+  std::vector<LevelCtl> h((size_t)P.nlev);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->ctl + P.ctl0, sizeof(LevelCtl) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  h[0].t = in[0];
+  for (int l = 0; l < P.nlev; ++l) {
+    h[l].acc_smax[0] = (unsigned long long)__builtin_bit_cast(long long, in[2 + 2 * l]);
+    h[l].acc_smax[1] = (unsigned long long)__builtin_bit_cast(long long, in[3 + 2 * l]);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->ctl + P.ctl0, h.data(), sizeof(LevelCtl) * h.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  P.have_dt = in[1] != 0.0;
   return MLSWE_OK;
 }
 
@@ -1620,7 +1664,10 @@ int build_all(mlswe_ctx* c) {
 // One coarse step of problems [p0, p1): dt rule, then the subcycled recursion.
 int coarse_step(mlswe_ctx* c, int p0, int p1, bool batched) {
   int rc;
-  const bool initial = !c->probs[p0].have_dt;
+  // the dt comes from the state for every problem of the range if one of them
+  // has no speeds of a last step (a fresh or re-initialised problem)
+  bool initial = false;
+  for (int p = p0; p < p1; ++p) initial = initial || !c->probs[p].have_dt;
   if ((rc = next_dt(c, p0, p1, initial))) return rc;
   for (int p = p0; p < p1; ++p) c->probs[p].have_dt = true;
   return adv(c, 0, p0, p1, 0.0, batched);
@@ -1787,7 +1834,9 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
     }
     if ((rc = copy_step_start(c, p0, p1, true, nctl, ncnt))) return rc;
   }
-  if (mode == MLSWE_GRAPH && c->probs[p0].have_dt && !c->timing)
+  bool all_dt = true;
+  for (int p = p0; p < p1; ++p) all_dt = all_dt && c->probs[p].have_dt;
+  if (mode == MLSWE_GRAPH && all_dt && !c->timing)
     rc = graph_step(c, p0, p1);
   else
     rc = coarse_step(c, p0, p1, together);
