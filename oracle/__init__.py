@@ -65,6 +65,7 @@ def lib():
             getattr(L, name).argtypes = [_P, _DP]
         L.ora_get_bathymetry.argtypes = [_P, _I, _DP]
         L.ora_get_step_state.argtypes = [_P, _DP]
+        L.ora_set_reflux.argtypes = [_P, _I]
         L.ora_set_step_state.argtypes = [_P, _DP]
         L.ora_set_state.argtypes = [_P, _I, _DP]
         L.ora_get_state.argtypes = [_P, _I, _DP]
@@ -289,6 +290,10 @@ class Hierarchy:
 
     def next_dt(self):
         return lib().ora_next_dt(self.h)
+
+    def set_reflux(self, on=True):
+        """Mass flux correction at coarse-fine edges (off by default)."""
+        lib().ora_set_reflux(self.h, 1 if on else 0)
 
     def step_state(self):
         """[t, speeds-known flag, per level largest x / y speeds of the last

@@ -33,6 +33,7 @@ struct Level {
   std::vector<Box> boxes;
   std::vector<uint8_t> mask;  // 1 where an interior cell is covered by a patch
   double smax[2] = {0, 0};    // largest speeds seen during the last coarse step
+  std::vector<double> mflux;  // [8][plane]: edge mass fluxes of the last step (flux correction)
 };
 
 struct Hier {
@@ -48,6 +49,7 @@ struct Hier {
   double cmax = 0.0;     // largest substep Courant number of the current coarse step
   int retries = 8;       // rejected coarse steps are retaken at most this often
   int64_t rejected = 0;  // coarse steps rejected so far
+  bool reflux = false;   // mass flux correction at coarse-fine edges
 };
 
 // ---------------------------------------------------------------- refine (Sec. 2.1)
@@ -246,9 +248,14 @@ static int step_level(Hier& H, int l, double dt, double th, double smax[2]) {
   smax[0] = 0.0; smax[1] = 0.0;
   const double* q = L.q[L.cur].data();
   double* qo = L.q[1 - L.cur].data();
+  double* mf = nullptr;
+  if (H.reflux) {
+    L.mflux.assign(8 * L.G.plane(), 0.0);
+    mf = L.mflux.data();
+  }
   for (const Box& b : L.boxes) {
     double s[2];
-    step_box(H.P, L.G, q, L.B.data(), b, L.dx, L.dy, dt, qo, s, H.C);
+    step_box(H.P, L.G, q, L.B.data(), b, L.dx, L.dy, dt, qo, s, H.C, mf);
     smax[0] = std::max(smax[0], s[0]);
     smax[1] = std::max(smax[1], s[1]);
     H.updates[l] += int64_t(b.nx) * b.ny;
@@ -447,10 +454,101 @@ static double next_dt(const Hier& H) {
   return best;
 }
 
+// ---------------------------------------------------------------- flux correction
+// Mass flux correction at coarse-fine edges (the paper is silent; optional).  A
+// coarse cell O of level l outside the finer level, with a face neighbour N
+// covered by it, took the coarse mass flux Gc through the face O|N in its own
+// update; the fine cells along that face took the fine fluxes of the r fine
+// faces in each of the r fine substeps.  After coarsening, O's depths get
+// nu_c (Gc - (sum of the fine fluxes) / r^2), added when O lies left of (below)
+// the face and subtracted when it lies right of (above) it, so each layer's
+// mass on the composite grid changes only through the domain walls.  Faces in
+// the order +x, -x, +y, -y; the fine fluxes of a substep summed along the face
+// first, then added to the running sum.
+struct RefluxCell {
+  int i, j, dirs;  // dirs bit d: face neighbour in direction d is covered by the finer level
+  double gc[4][2], acc[4][2];
+};
+
+static std::vector<RefluxCell> reflux_begin(const Hier& H, int l) {
+  const Level& L = H.L[l];
+  const Level& F = H.L[l + 1];
+  const int r = H.ratio[l];
+  const size_t pl = L.G.plane();
+  auto fine = [&](int I, int J) {
+    return I >= 0 && J >= 0 && I < L.G.nx && J < L.G.ny && F.mask[F.G.idx(r * I, r * J)] != 0;
+  };
+  static const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
+  static const int plane_of[4] = {2, 0, 6, 4};  // O's flux through the face: right, left, upper, lower
+  std::vector<RefluxCell> out;
+  for (int j = 0; j < L.G.ny; ++j)
+    for (int i = 0; i < L.G.nx; ++i) {
+      const size_t id = L.G.idx(i, j);
+      if (!L.mask[id] || fine(i, j)) continue;
+      RefluxCell c{};
+      c.i = i; c.j = j; c.dirs = 0;
+      for (int d = 0; d < 4; ++d) {
+        if (!fine(i + di[d], j + dj[d])) continue;
+        c.dirs |= 1 << d;
+        for (int m = 0; m < 2; ++m) {
+          c.gc[d][m] = L.mflux[(plane_of[d] + m) * pl + id];
+          c.acc[d][m] = 0.0;
+        }
+      }
+      if (c.dirs) out.push_back(c);
+    }
+  return out;
+}
+
+// After a fine substep: add the fine fluxes through each recorded face.
+static void reflux_accumulate(const Hier& H, int l, std::vector<RefluxCell>& cells) {
+  const Level& F = H.L[l + 1];
+  const int r = H.ratio[l];
+  const size_t pl = F.G.plane();
+  static const int plane_of[4] = {0, 2, 4, 6};  // the fine cells' flux through the face: left, right, lower, upper
+  for (RefluxCell& c : cells)
+    for (int d = 0; d < 4; ++d) {
+      if (!(c.dirs >> d & 1)) continue;
+      for (int m = 0; m < 2; ++m) {
+        double s = 0.0;
+        for (int k = 0; k < r; ++k) {
+          int fi, fj;
+          if (d == 0) { fi = r * (c.i + 1); fj = r * c.j + k; }
+          else if (d == 1) { fi = r * c.i - 1; fj = r * c.j + k; }
+          else if (d == 2) { fi = r * c.i + k; fj = r * (c.j + 1); }
+          else { fi = r * c.i + k; fj = r * c.j - 1; }
+          const double g = F.mflux[(plane_of[d] + m) * pl + F.G.idx(fi, fj)];
+          s = k == 0 ? g : s + g;
+        }
+        c.acc[d][m] = c.acc[d][m] + s;
+      }
+    }
+}
+
+static void reflux_apply(Hier& H, int l, const std::vector<RefluxCell>& cells, double dt) {
+  Level& L = H.L[l];
+  const int r = H.ratio[l];
+  const double inv = 1.0 / double(r * r);
+  const double nux = dt / L.dx, nuy = dt / L.dy;
+  double* q = L.q[L.cur].data();
+  const size_t pl = L.G.plane();
+  for (const RefluxCell& c : cells) {
+    const size_t id = L.G.idx(c.i, c.j);
+    for (int d = 0; d < 4; ++d) {
+      if (!(c.dirs >> d & 1)) continue;
+      const double nu = d < 2 ? nux : nuy;
+      for (int m = 0; m < 2; ++m) {
+        const double corr = nu * (c.gc[d][m] - c.acc[d][m] * inv);
+        double& h = q[(m == 0 ? F_H1 : F_H2) * pl + id];
+        h = (d % 2 == 0) ? h + corr : h - corr;
+      }
+    }
+  }
+}
+
 // Subcycled recursion: fill and step level l, then r substeps of level l+1 (time
-// ratio equal to the space ratio), then average level l+1 back onto level l.
-// Subcycled recursion: fill and step level l, then r substeps of level l+1 (time
-// ratio equal to the space ratio), then average level l+1 back onto level l.
+// ratio equal to the space ratio), then average level l+1 back onto level l
+// (and, with the flux correction on, correct the coarse cells beside it).
 // A substep above the Courant limit does not stop the step: the whole coarse
 // step is completed and judged by its largest substep Courant number.
 static int adv(Hier& H, int l, double dt, double th) {
@@ -460,11 +558,15 @@ static int adv(Hier& H, int l, double dt, double th) {
   if (l + 1 < H.nlev && !H.L[l + 1].boxes.empty()) {
     const int r = H.ratio[l];
     const double dtf = dt / double(r);
+    std::vector<RefluxCell> rf;
+    if (H.reflux) rf = reflux_begin(H, l);
     for (int k = 0; k < r; ++k) {
       rc = adv(H, l + 1, dtf, double(k) / double(r));
       if (rc && rc != E_CFL) return rc;
+      if (H.reflux) reflux_accumulate(H, l, rf);
     }
     coarsen(H, l + 1);
+    if (H.reflux) reflux_apply(H, l, rf, dt);
   }
   return OK;
 }
@@ -650,6 +752,8 @@ int ora_advance(void* h, int nsteps, int regrid_every, const double* tau, int nb
 }
 
 double ora_next_dt(void* h) { return next_dt(*static_cast<Hier*>(h)); }
+
+void ora_set_reflux(void* h, int on) { static_cast<Hier*>(h)->reflux = on != 0; }
 
 // Time-stepping state for checkpoint and resume: t, whether the next coarse
 // step takes its dt from the last step's speeds (else from the state), and each

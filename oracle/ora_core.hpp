@@ -388,9 +388,12 @@ template <class T> void fixup(const Params& P, T* q, bool count, Counters& C) {
 // line[k][0..5] is the state in local order (h1 m1 t1 h2 m2 t2) for k = -2..n+1
 // (stored at index k+2), Bl[k+2] the bathymetry.  Writes out[k][6] for k = 0..n-1
 // (fix-up applied) and returns the largest wave speed at edges 0..n.
+// g4 (optional, [n][4]): for each cell the depth parts (layers 1, 2) of the terms
+// its update takes from its left edge (A+dQ - F) and from its right edge
+// (A-dQ + F), for the mass fluxes of a flux correction at coarse-fine edges.
 template <class T>
 double sweep_line(const Params& P, int n, const T* line, const T* Bl, T nu, T* out, bool interior,
-                  Counters& C) {
+                  Counters& C, T* g4 = nullptr) {
   std::vector<CellV<T>> cells(n + 4);
   for (int k = 0; k < n + 4; ++k) cells[k] = make_cell(P, line + 6 * k, Bl[k]);
   // edges e = -1..n+1 at index e+1; edge e lies between cells e-1 and e
@@ -420,6 +423,10 @@ double sweep_line(const Params& P, int n, const T* line, const T* Bl, T nu, T* o
       T gl = ap[6 * k + c] - F[6 * k + c];
       T gr = am[6 * (k + 1) + c] + F[6 * (k + 1) + c];
       o[c] = fma_(mnu, gl + gr, q[c]);
+      if (g4 && (c == 0 || c == 3)) {
+        g4[4 * k + (c == 0 ? 0 : 1)] = gl;
+        g4[4 * k + (c == 0 ? 2 : 3)] = gr;
+      }
     }
     fixup(P, o, interior, C);
   }
@@ -452,12 +459,16 @@ inline void mirror_src(const Grid& G, int i, int j, int& si, int& sj, bool& fx, 
 // x-sweep of a box: the box rows and the two frame rows on each side, each
 // line fixed up; writes the intermediate state qs (six planes of
 // nx x (ny + 4), rows jlo-2 .. jlo+ny+1, columns ilo .. ilo+nx-1).
+// mflux (optional, [8][plane] over the level): for every interior cell of the
+// box, the mass flux of each layer through its left and right edges as its
+// update sees it (normal momentum minus the left-edge term, plus the right-edge
+// term): planes 0-1 left edge, 2-3 right edge (layers 1, 2).
 template <class T>
 double x_pass(const Params& P, const Grid& G, const T* q, const T* B, const Box& bx, T nux, T* qs,
-              Counters& C) {
+              Counters& C, T* mflux = nullptr) {
   const size_t pl = G.plane();
   const int nx = bx.nx, ny = bx.ny;
-  std::vector<T> line(6 * (nx + 4)), Bl(nx + 4), out(6 * nx);
+  std::vector<T> line(6 * (nx + 4)), Bl(nx + 4), out(6 * nx), g4(4 * nx);
   double smax = 0.0;
   for (int jj = -2; jj < ny + 2; ++jj) {
     int j = bx.jlo + jj;
@@ -467,8 +478,18 @@ double x_pass(const Params& P, const Grid& G, const T* q, const T* B, const Box&
       Bl[k + 2] = B[G.idx(i, j)];
     }
     bool interior = (jj >= 0 && jj < ny);
-    double s = sweep_line(P, nx, line.data(), Bl.data(), nux, out.data(), interior, C);
+    double s = sweep_line(P, nx, line.data(), Bl.data(), nux, out.data(), interior, C,
+                          mflux && interior ? g4.data() : nullptr);
     if (interior && s > smax) smax = s;
+    if (mflux && interior)
+      for (int k = 0; k < nx; ++k) {
+        const size_t id = G.idx(bx.ilo + k, j);
+        const T m1 = line[6 * (k + 2) + 1], m2 = line[6 * (k + 2) + 4];
+        mflux[0 * pl + id] = m1 - g4[4 * k + 0];
+        mflux[1 * pl + id] = m2 - g4[4 * k + 1];
+        mflux[2 * pl + id] = m1 + g4[4 * k + 2];
+        mflux[3 * pl + id] = m2 + g4[4 * k + 3];
+      }
     for (int k = 0; k < nx; ++k)
       for (int c = 0; c < 6; ++c)
         qs[(size_t(c) * (ny + 4) + (jj + 2)) * nx + k] = out[6 * k + c];
@@ -479,13 +500,14 @@ double x_pass(const Params& P, const Grid& G, const T* q, const T* B, const Box&
 // y-sweep of a box over the intermediate state: columns in the y orientation
 // (normal momentum hv, transverse hu), each fixed up; writes the box interior
 // of qo.
+// mflux as for x_pass, planes 4-5 lower edge, 6-7 upper edge.
 template <class T>
 double y_pass(const Params& P, const Grid& G, const T* qs, const T* B, const Box& bx, T nuy, T* qo,
-              Counters& C) {
+              Counters& C, T* mflux = nullptr) {
   const size_t pl = G.plane();
   const int nx = bx.nx, ny = bx.ny;
   static const int ymap[6] = {0, 2, 1, 3, 5, 4};
-  std::vector<T> linev(6 * (ny + 4)), Bv(ny + 4), outv(6 * ny);
+  std::vector<T> linev(6 * (ny + 4)), Bv(ny + 4), outv(6 * ny), g4(4 * ny);
   double smax = 0.0;
   for (int k = 0; k < nx; ++k) {
     int i = bx.ilo + k;
@@ -494,8 +516,18 @@ double y_pass(const Params& P, const Grid& G, const T* qs, const T* B, const Box
         linev[6 * (jj + 2) + c] = qs[(size_t(ymap[c]) * (ny + 4) + (jj + 2)) * nx + k];
       Bv[jj + 2] = B[G.idx(i, bx.jlo + jj)];
     }
-    double s = sweep_line(P, ny, linev.data(), Bv.data(), nuy, outv.data(), true, C);
+    double s = sweep_line(P, ny, linev.data(), Bv.data(), nuy, outv.data(), true, C,
+                          mflux ? g4.data() : nullptr);
     if (s > smax) smax = s;
+    if (mflux)
+      for (int jj = 0; jj < ny; ++jj) {
+        const size_t id = G.idx(i, bx.jlo + jj);
+        const T m1 = linev[6 * (jj + 2) + 1], m2 = linev[6 * (jj + 2) + 4];
+        mflux[4 * pl + id] = m1 - g4[4 * jj + 0];
+        mflux[5 * pl + id] = m2 - g4[4 * jj + 1];
+        mflux[6 * pl + id] = m1 + g4[4 * jj + 2];
+        mflux[7 * pl + id] = m2 + g4[4 * jj + 3];
+      }
     for (int jj = 0; jj < ny; ++jj)
       for (int c = 0; c < 6; ++c)
         qo[size_t(ymap[c]) * pl + G.idx(i, bx.jlo + jj)] = outv[6 * jj + c];
@@ -508,10 +540,10 @@ double y_pass(const Params& P, const Grid& G, const T* qs, const T* B, const Box
 // and the two frame rows on each side, fix-up, y-sweep, fix-up.
 template <class T>
 void step_box(const Params& P, const Grid& G, const T* q, const T* B, const Box& bx, double dx,
-              double dy, double dt, T* qo, double smax[2], Counters& C) {
+              double dy, double dt, T* qo, double smax[2], Counters& C, T* mflux = nullptr) {
   std::vector<T> qs(size_t(6) * size_t(bx.nx) * size_t(bx.ny + 4));
-  smax[0] = x_pass(P, G, q, B, bx, T(dt / dx), qs.data(), C);
-  smax[1] = y_pass(P, G, qs.data(), B, bx, T(dt / dy), qo, C);
+  smax[0] = x_pass(P, G, q, B, bx, T(dt / dx), qs.data(), C, mflux);
+  smax[1] = y_pass(P, G, qs.data(), B, bx, T(dt / dy), qo, C, mflux);
 }
 
 // Reflecting-wall fill of every frame cell of a single-box level.
