@@ -58,7 +58,13 @@ typedef struct mlswe_config {
                          cfl_max is undone and retaken with dt scaled by
                          cfl_desired / that number, at most this often; -1 = never
                          (the step then fails with MLSWE_ECFL), 0 = the default 8 */
-  int pad_;
+  int reflux;         /* 1: mass flux correction at coarse-fine edges (the paper has
+                         none): after a level's fine substeps and coarsening, each
+                         coarse cell beside a fine patch has the coarse mass flux
+                         through the shared face replaced by the fine fluxes summed
+                         over the face's fine faces and substeps (divided by r^2),
+                         so each layer's mass on the composite grid changes only by
+                         clipping; 0 (default): off */
 } mlswe_config;
 
 /* Launch shape of the two sweep kernels.  rows: rows per x-sweep wave / per

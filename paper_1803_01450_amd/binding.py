@@ -30,7 +30,7 @@ class Config(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("hdry", ctypes.c_double), ("kmin", ctypes.c_double),
                 ("cfl_desired", ctypes.c_double), ("cfl_max", ctypes.c_double),
                 ("y_rows", ctypes.c_int), ("x_rows", ctypes.c_int),
-                ("max_device_bytes", ctypes.c_int64), ("max_retries", ctypes.c_int), ("pad_", ctypes.c_int)]
+                ("max_device_bytes", ctypes.c_int64), ("max_retries", ctypes.c_int), ("reflux", ctypes.c_int)]
 
 
 class CountersC(ctypes.Structure):
@@ -144,9 +144,9 @@ class Solver:
     """One library context (one GPU stream) holding any number of problems."""
 
     def __init__(self, g=9.81, hdry=1e-3, kmin=1e-6, cfl=0.9, cfl_max=1.0, y_rows=0, x_rows=0,
-                 max_device_bytes=0, stream=None, max_retries=0):
+                 max_device_bytes=0, stream=None, max_retries=0, reflux=False):
         self.L = lib()
-        cfg = Config(g, hdry, kmin, cfl, cfl_max, y_rows, x_rows, max_device_bytes, max_retries, 0)
+        cfg = Config(g, hdry, kmin, cfl, cfl_max, y_rows, x_rows, max_device_bytes, max_retries, 1 if reflux else 0)
         h = ctypes.c_void_p()
         rc = self.L.mlswe_create(ctypes.byref(cfg), stream, ctypes.byref(h))
         if rc:

@@ -408,6 +408,130 @@ __global__ __launch_bounds__(256) void k_nan_uncovered(double* q, const unsigned
   for (int f = 0; f < 6; ++f) q[f * pu + t] = nan;
 }
 
+// ---------------------------------------------------------------- flux correction
+// A cell of the sweeps' line from a level buffer: x lines take (h, hu, hv) per
+// layer, y lines (h, hv, hu), as the sweeps load them.
+__device__ __forceinline__ CellX line_cell(const PhysParams& P, const double* q, const double* B, long long plane,
+                                           long long k, bool ydir) {
+  const double h1 = q[k], a1 = q[plane + k], b1 = q[2 * plane + k];
+  const double h2 = q[3 * plane + k], a2 = q[4 * plane + k], b2 = q[5 * plane + k];
+  return ydir ? load_cell(P, h1, b1, a1, h2, b2, a2, B[k]) : load_cell(P, h1, a1, b1, h2, a2, b2, B[k]);
+}
+
+// Depth parts (layers 1, 2) of the terms the sweeps give the cell before a face
+// (A-dQ + F) and the cell after it (A+dQ - F), from the four cells around the
+// face (the face lies between c[1] and c[2]).
+__device__ __forceinline__ void face_terms(const PhysParams& P, const CellX* c, double nu, double gr[2],
+                                           double gl[2]) {
+  EdgeW Wm, W, Wp;
+  riemann(P, c[0], c[1], Wm);
+  riemann(P, c[1], c[2], W);
+  riemann(P, c[2], c[3], Wp);
+  double coef[6], F[6], am[6], ap[6];
+#pragma unroll
+  for (int p = 0; p < 6; ++p) coef[p] = corr_coef(W, p, wdot(W, W, p), wdot(Wm, W, p), wdot(W, Wp, p), nu);
+  correction_flux(W, coef, F);
+  fluctuations(W, am, ap);
+  gr[0] = am[0] + F[0];
+  gr[1] = am[3] + F[3];
+  gl[0] = ap[0] - F[0];
+  gl[1] = ap[3] - F[3];
+}
+
+// Coarse face fluxes of each record's cell O after a level-l substep (x faces
+// from the x-sweep's input, y faces from the x-swept state), running sums
+// cleared.  The flux is O's normal momentum plus (face after O) or minus (face
+// before O) O's term from that face.
+__global__ __launch_bounds__(64) void k_reflux_coarse(const RefluxCell* __restrict__ rcs, int n, int parity) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const RefluxCell& R = rcs[t];
+  const long long o = cidx(R.cpitch, R.i, R.j);
+  const double dt = R.cctl->dt;
+  for (int d = 0; d < 4; ++d) {
+    if (!((R.dirs >> d) & 1)) continue;
+    const bool ydir = d >= 2, plus = (d & 1) == 0;
+    const long long st = ydir ? R.cpitch : 1;
+    const double* q = ydir ? R.cqs : R.cq[parity];
+    const double nu = dt / (ydir ? R.cdy : R.cdx);
+    const long long k0 = plus ? o - st : o - 2 * st;
+    CellX c[4];
+    for (int u = 0; u < 4; ++u) c[u] = line_cell(R.P, q, R.cB, R.cplane, k0 + u * st, ydir);
+    double gr[2], gl[2];
+    face_terms(R.P, c, nu, gr, gl);
+    const int mf = ydir ? 2 : 1;
+    for (int m = 0; m < 2; ++m) {
+      const double mo = q[(3 * m + mf) * R.cplane + o];
+      R.reg[2 * d + m] = plus ? mo + gr[m] : mo - gl[m];
+      R.reg[8 + 2 * d + m] = 0.0;
+    }
+  }
+}
+
+// After a level-(l+1) substep: the fine fluxes through the r fine faces along
+// each recorded face (the fine cell beside the face: its normal momentum minus
+// its term from a face before it, plus its term from a face after it), summed
+// along the face and added to the running sums.
+__global__ __launch_bounds__(64) void k_reflux_fine(const RefluxCell* __restrict__ rcs, int n, int parity) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const RefluxCell& R = rcs[t];
+  const double dt = R.fctl->dt;
+  const int r = R.r;
+  for (int d = 0; d < 4; ++d) {
+    if (!((R.dirs >> d) & 1)) continue;
+    const bool ydir = d >= 2, plus = (d & 1) == 0;
+    const long long st = ydir ? R.fpitch : 1;
+    const double* q = ydir ? R.fqs : R.fq[parity];
+    const double nu = dt / (ydir ? R.fdy : R.fdx);
+    const int mf = ydir ? 2 : 1;
+    double sum[2] = {0.0, 0.0};
+    for (int k = 0; k < r; ++k) {
+      int fi, fj;
+      if (d == 0) { fi = r * (R.i + 1); fj = r * R.j + k; }
+      else if (d == 1) { fi = r * R.i - 1; fj = r * R.j + k; }
+      else if (d == 2) { fi = r * R.i + k; fj = r * (R.j + 1); }
+      else { fi = r * R.i + k; fj = r * R.j - 1; }
+      const long long f = cidx(R.fpitch, fi, fj);
+      const long long k0 = plus ? f - 2 * st : f - st;
+      CellX c[4];
+      for (int u = 0; u < 4; ++u) c[u] = line_cell(R.P, q, R.fB, R.fplane, k0 + u * st, ydir);
+      double gr[2], gl[2];
+      face_terms(R.P, c, nu, gr, gl);
+      for (int m = 0; m < 2; ++m) {
+        const double mF = q[(3 * m + mf) * R.fplane + f];
+        const double g = plus ? mF - gl[m] : mF + gr[m];
+        sum[m] = k == 0 ? g : sum[m] + g;
+      }
+    }
+    for (int m = 0; m < 2; ++m) R.reg[8 + 2 * d + m] = R.reg[8 + 2 * d + m] + sum[m];
+  }
+}
+
+// After coarsening: nu_c (gc - acc / r^2) added to (faces after O) or
+// subtracted from (faces before O) O's depths, faces in the order +x, -x, +y, -y.
+__global__ __launch_bounds__(64) void k_reflux_apply(const RefluxCell* __restrict__ rcs, int n, int parity) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const RefluxCell& R = rcs[t];
+  const long long o = cidx(R.cpitch, R.i, R.j);
+  const double dt = R.cctl->dt;
+  const double inv = 1.0 / double(R.r * R.r);
+  const double nux = dt / R.cdx, nuy = dt / R.cdy;
+  double* q = R.cq[parity];
+  double h[2] = {q[o], q[3 * R.cplane + o]};
+  for (int d = 0; d < 4; ++d) {
+    if (!((R.dirs >> d) & 1)) continue;
+    const double nu = d < 2 ? nux : nuy;
+    for (int m = 0; m < 2; ++m) {
+      const double corr = nu * (R.reg[2 * d + m] - R.reg[8 + 2 * d + m] * inv);
+      h[m] = (d & 1) == 0 ? h[m] + corr : h[m] - corr;
+    }
+  }
+  q[o] = h[0];
+  q[3 * R.cplane + o] = h[1];
+}
+
 // Cells of a level that no patch covers set to zero (all six fields) in the
 // level's own buffer: values handed in there are never used, and a non-finite
 // one would otherwise reach the non-finite check of the union-tile x-sweep.

@@ -223,6 +223,30 @@ __global__ void k_zero_u32(unsigned* p, int n);
 __global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass, double theta);
 __global__ void k_refine_new(const FillPatch* __restrict__ fills);
 __global__ void k_coarsen(const CoarsenPatch* __restrict__ cps);
+
+// Mass flux correction at coarse-fine edges: one record per coarse cell O
+// (level l, outside level l + 1) with face neighbours covered by level l + 1.
+// dirs bit d: the neighbour in direction d (+x, -x, +y, -y) is covered.  reg
+// holds, per direction and layer, the coarse face flux (gc) and the running
+// sum over fine substeps of the fine face fluxes along the face (acc).
+struct RefluxCell {
+  double* cq[2];          // level l buffers by parity
+  const double* cqs;      // level l x-swept state
+  const double* cB;
+  const double* fq[2];    // level l + 1 buffers by parity
+  const double* fqs;
+  const double* fB;
+  const LevelCtl* cctl;
+  const LevelCtl* fctl;
+  double* reg;            // [4][2] gc, then [4][2] acc
+  long long cpitch, cplane, fpitch, fplane;
+  int i, j, dirs, r;
+  double cdx, cdy, fdx, fdy;
+  PhysParams P;
+};
+__global__ void k_reflux_coarse(const RefluxCell* __restrict__ rc, int n, int parity);
+__global__ void k_reflux_fine(const RefluxCell* __restrict__ rc, int n, int parity);
+__global__ void k_reflux_apply(const RefluxCell* __restrict__ rc, int n, int parity);
 __global__ void k_flag_raw(const FlagLevel* __restrict__ Fs);
 __global__ void k_flag_dilate(const FlagLevel* __restrict__ Fs);
 __global__ void k_flag_tiles(const FlagTiles* __restrict__ Ts);

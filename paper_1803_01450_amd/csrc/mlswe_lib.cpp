@@ -110,6 +110,12 @@ struct LevelLaunch {
   int nli = 0;
   std::vector<int> li_first;
   int cap_pd = 0, cap_xt = 0, cap_yt = 0, cap_fp = 0, cap_li = 0;
+  // flux correction (config reflux): records of the coarser level's cells
+  // beside this level's patches, per problem contiguous, and their registers
+  RefluxCell* rfx = nullptr;
+  double* rfx_reg = nullptr;
+  int nrfx = 0, cap_rfx = 0, cap_rfx_reg = 0;
+  std::vector<int> rfx_first, rfx_count;
 };
 
 }  // namespace
@@ -334,6 +340,67 @@ long long tile_makespan(const std::vector<int>& rows, int extra, long long slots
     end = std::max(end, (long long)done);
   }
   return end;
+}
+
+// Flux-correction records of level l (>= 1): every interior cell O of level
+// l - 1 outside level l with a face neighbour covered by level l, per problem.
+int build_reflux(mlswe_ctx* c, int l, std::vector<RefluxCell>& out) {
+  LevelLaunch& LL = c->launch[l];
+  const int np = (int)c->probs.size();
+  LL.rfx_first.assign(np, 0);
+  LL.rfx_count.assign(np, 0);
+  out.clear();
+  for (int p = 0; p < np; ++p) {
+    ProblemH& P = c->probs[p];
+    LL.rfx_first[p] = (int)out.size();
+    if (l >= P.nlev || P.L[l].boxes.empty()) continue;
+    LevelH& Lc = P.L[l - 1];
+    LevelH& Lf = P.L[l];
+    const int r = P.ratio[l - 1];
+    const int nx = Lc.nx, ny = Lc.ny;
+    std::vector<unsigned char> inc((size_t)nx * ny, 0), fin((size_t)nx * ny, 0);
+    for (const Box& b : Lc.boxes)
+      for (int j = b.jlo; j < b.jlo + b.ny; ++j)
+        for (int i = b.ilo; i < b.ilo + b.nx; ++i) inc[(size_t)j * nx + i] = 1;
+    for (const Box& b : Lf.boxes)
+      for (int j = b.jlo / r; j < (b.jlo + b.ny) / r; ++j)
+        for (int i = b.ilo / r; i < (b.ilo + b.nx) / r; ++i) fin[(size_t)j * nx + i] = 1;
+    std::vector<int> at((size_t)nx * ny, -1);
+    const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};  // O = N + (di, dj) for direction d
+    for (const Box& b : Lf.boxes) {
+      const int I0 = b.ilo / r, I1 = (b.ilo + b.nx) / r - 1, J0 = b.jlo / r, J1 = (b.jlo + b.ny) / r - 1;
+      for (int d = 0; d < 4; ++d) {
+        const int n = d < 2 ? J1 - J0 + 1 : I1 - I0 + 1;
+        for (int k = 0; k < n; ++k) {
+          // N on the box side facing O
+          const int Ni = d == 0 ? I0 : d == 1 ? I1 : I0 + k;
+          const int Nj = d < 2 ? J0 + k : d == 2 ? J0 : J1;
+          const int Oi = Ni + di[d], Oj = Nj + dj[d];
+          if (Oi < 0 || Oj < 0 || Oi >= nx || Oj >= ny) continue;
+          const size_t o = (size_t)Oj * nx + Oi;
+          if (!inc[o] || fin[o]) continue;
+          if (at[o] < 0) {
+            RefluxCell R;
+            std::memset(&R, 0, sizeof R);
+            R.cq[0] = Lc.q[0]; R.cq[1] = Lc.q[1]; R.cqs = Lc.qs; R.cB = Lc.B;
+            R.fq[0] = Lf.q[0]; R.fq[1] = Lf.q[1]; R.fqs = Lf.qs; R.fB = Lf.B;
+            R.cctl = c->ctl + P.ctl0 + (l - 1);
+            R.fctl = c->ctl + P.ctl0 + l;
+            R.cpitch = Lc.pitch; R.cplane = Lc.plane; R.fpitch = Lf.pitch; R.fplane = Lf.plane;
+            R.i = Oi; R.j = Oj; R.dirs = 0; R.r = r;
+            R.cdx = Lc.dx; R.cdy = Lc.dy; R.fdx = Lf.dx; R.fdy = Lf.dy;
+            R.P = P.P;
+            at[o] = (int)out.size();
+            out.push_back(R);
+          }
+          out[at[o]].dirs |= 1 << d;
+        }
+      }
+    }
+    LL.rfx_count[p] = (int)out.size() - LL.rfx_first[p];
+  }
+  LL.nrfx = (int)out.size();
+  return MLSWE_OK;
 }
 
 int build_launch(mlswe_ctx* c, int l) {
@@ -610,6 +677,15 @@ int build_launch(mlswe_ctx* c, int l) {
   }
   if (LL.nli)
     HIPCHK(c, hipMemcpyAsync(LL.li, li4.data(), sizeof(LevelInfo) * li4.size(), hipMemcpyHostToDevice, c->stream));
+  std::vector<RefluxCell> rfx;
+  if (c->cfg.reflux && l >= 1) {
+    if ((rc = build_reflux(c, l, rfx))) return rc;
+    if ((rc = ensure(c, &LL.rfx, &LL.cap_rfx, std::max(1, LL.nrfx)))) return rc;
+    if ((rc = ensure(c, &LL.rfx_reg, &LL.cap_rfx_reg, 16 * std::max(1, LL.nrfx)))) return rc;
+    for (int k = 0; k < LL.nrfx; ++k) rfx[k].reg = LL.rfx_reg + 16 * (size_t)k;
+    if (LL.nrfx)
+      HIPCHK(c, hipMemcpyAsync(LL.rfx, rfx.data(), sizeof(RefluxCell) * LL.nrfx, hipMemcpyHostToDevice, c->stream));
+  }
   // host vectors must outlive the asynchronous copies
   HIPCHK(c, hipStreamSynchronize(c->stream));
   LL.dirty = false;
@@ -770,6 +846,35 @@ int launch_after(mlswe_ctx* c, int l, int p0, int p1, int runs) {
   return MLSWE_OK;
 }
 
+// Flux-correction launch over the records of level lf for problems [p0, p1):
+// which 0 coarse face fluxes (after a level lf - 1 substep), 1 fine face fluxes
+// (after a level lf substep), 2 the correction (after coarsening level lf).
+int launch_reflux(mlswe_ctx* c, int lf, int p0, int p1, int which, int parity) {
+  if (!c->cfg.reflux || lf < 1 || lf >= MAXLEV) return MLSWE_OK;
+  bool has = false;  // no problem of the range has level lf: nothing to build or launch
+  for (int p = p0; p < p1; ++p) has = has || lf < c->probs[p].nlev;
+  if (!has) return MLSWE_OK;
+  int rc;
+  if ((rc = build_launch(c, lf))) return rc;
+  LevelLaunch& LL = c->launch[lf];
+  int first = -1, count = 0;
+  for (int p = p0; p < p1 && p < (int)LL.rfx_first.size(); ++p) {
+    if (LL.rfx_count[p] == 0) continue;
+    if (first < 0) first = LL.rfx_first[p];
+    count = LL.rfx_first[p] + LL.rfx_count[p] - first;
+  }
+  if (count == 0) return MLSWE_OK;
+  const dim3 grid((unsigned)((count + 63) / 64)), block(64);
+  if (which == 0)
+    hipLaunchKernelGGL(k_reflux_coarse, grid, block, 0, c->stream, LL.rfx + first, count, parity);
+  else if (which == 1)
+    hipLaunchKernelGGL(k_reflux_fine, grid, block, 0, c->stream, LL.rfx + first, count, parity);
+  else
+    hipLaunchKernelGGL(k_reflux_apply, grid, block, 0, c->stream, LL.rfx + first, count, parity);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
 // One substep of level l for problems [p0, p1): fill, sweeps, buffer flip.
 int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
   int rc;
@@ -818,6 +923,12 @@ int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
           return rc;
     }
   }
+  if (c->cfg.reflux) {
+    // face fluxes from this substep's sweep inputs (still intact): as the coarse
+    // side of the finer level's faces, and as the fine side of this level's
+    if (l + 1 < MAXLEV && (rc = launch_reflux(c, l + 1, p0, p1, 0, parity))) return rc;
+    if (l >= 1 && (rc = launch_reflux(c, l, p0, p1, 1, parity))) return rc;
+  }
   for (int p = p0; p < p1; ++p) {
     ProblemH& P = c->probs[p];
     if (l >= P.nlev) continue;
@@ -828,7 +939,9 @@ int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
   return launch_after(c, l, p0, p1, runs);
 }
 
-int coarsen_level(mlswe_ctx* c, int lf, int p0, int p1) {
+// apply_reflux: the coarsening ends a coarse level's substep inside a coarse
+// step, so the flux correction (if on) follows it.
+int coarsen_level(mlswe_ctx* c, int lf, int p0, int p1, bool apply_reflux = false) {
   int rc;
   if ((rc = build_launch(c, lf))) return rc;
   LevelLaunch& LL = c->launch[lf];
@@ -849,7 +962,7 @@ int coarsen_level(mlswe_ctx* c, int lf, int p0, int p1) {
     hipLaunchKernelGGL(k_coarsen, dim3((maxc + 255) / 256, (unsigned)std::min(65535, count - k0)), dim3(256), 0,
                        c->stream, LL.cp[fpar * 2 + cpar] + first + k0);
   HIPCHK(c, hipGetLastError());
-  return MLSWE_OK;
+  return apply_reflux ? launch_reflux(c, lf, p0, p1, 2, cpar) : MLSWE_OK;
 }
 
 bool level_active(const mlswe_ctx* c, int l, int p0, int p1) {
@@ -866,7 +979,7 @@ int adv(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
     const int r = P0.ratio[l];
     for (int k = 0; k < r; ++k)
       if ((rc = adv(c, l + 1, p0, p1, double(k) / double(r), batched))) return rc;
-    if ((rc = coarsen_level(c, l + 1, p0, p1))) return rc;
+    if ((rc = coarsen_level(c, l + 1, p0, p1, true))) return rc;
   }
   return MLSWE_OK;
 }
@@ -1249,7 +1362,7 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
   if (cfg) d = *cfg;
   if (d.max_retries == 0) d.max_retries = 8;
   if (!(d.g > 0) || !(d.hdry > 0) || !(d.kmin > 0) || !(d.cfl_desired > 0) || !(d.cfl_max >= d.cfl_desired) ||
-      d.y_rows < 0 || d.x_rows < 0) {
+      d.y_rows < 0 || d.x_rows < 0 || (d.reflux != 0 && d.reflux != 1)) {
     delete c;
     return MLSWE_EINVAL;
   }
@@ -1287,6 +1400,7 @@ int mlswe_destroy(mlswe_ctx* c) {
   for (LevelLaunch& LL : c->launch) {
     dfree(LL.pd[0]); dfree(LL.pd[1]); dfree(LL.xt); dfree(LL.yt); dfree(LL.li); dfree(LL.parts);
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
+    dfree(LL.rfx); dfree(LL.rfx_reg);
   }
   dfree(c->ctl); dfree(c->cnt); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
   dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d); dfree(c->boxes_d);
