@@ -115,20 +115,21 @@ def bench_batch(nprob, steps, stream, modes=("plain", "batched", "graph")):
     return out
 
 
-def bench_amr(steps, stream, modes=("plain", "batched", "graph")):
+def bench_amr(steps, stream, modes=("plain", "batched", "graph", "reflux")):
     """Three levels (ratios 2 and 4) over 400 km with shorelines, 16 level-0
-    patches of 64^2, regrid every 4 coarse steps."""
+    patches of 64^2, regrid every 4 coarse steps.  "reflux": batched launches
+    with the mass flux correction at coarse-fine edges."""
     import numpy as np
     from paper_1803_01450_amd import inputs
     from paper_1803_01450_amd.binding import Solver, PLAIN, BATCHED, GRAPH
     c = inputs.amr_shoreline()
     tau = [[2e-6, 4e-6]]
     out = {}
-    for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH)):
+    for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH), ("reflux", BATCHED)):
         if name not in modes:
             continue
         print("bench: AMR 3 levels, %s" % name, file=sys.stderr, flush=True)
-        S = Solver(stream=stream)
+        S = Solver(stream=stream, reflux=name == "reflux")
         p = S.define(c["n0"], c["n0"], c["dx0"], c["dx0"], c["r"], c["ratios"])
         S.set_bathymetry(p, c["Bf"])
         S.set_patches(p, 0, c["level0_boxes"])
@@ -139,6 +140,8 @@ def bench_amr(steps, stream, modes=("plain", "batched", "graph")):
                      "finest_patches": int(len(S.patches(p, 2)))}
         S.close()
     ratios(out, modes)
+    if "reflux" in out and "batched" in out:
+        out["reflux_time_ratio"] = out["reflux"]["seconds"] / out["batched"]["seconds"]
     out["coarse_steps"] = steps
     return out
 

@@ -440,71 +440,78 @@ __device__ __forceinline__ void face_terms(const PhysParams& P, const CellX* c, 
 
 // Coarse face fluxes of each record's cell O after a level-l substep (x faces
 // from the x-sweep's input, y faces from the x-swept state), running sums
-// cleared.  The flux is O's normal momentum plus (face after O) or minus (face
-// before O) O's term from that face.
+// cleared; one thread per (record, direction).  The flux is O's normal
+// momentum plus (face after O) or minus (face before O) O's term from that face.
 __global__ __launch_bounds__(64) void k_reflux_coarse(const RefluxCell* __restrict__ rcs, int n, int parity) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const RefluxCell& R = rcs[t];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4LL * n) return;
+  const RefluxCell& R = rcs[t >> 2];
+  const int d = (int)(t & 3);
+  if (!((R.dirs >> d) & 1)) return;
   const long long o = cidx(R.cpitch, R.i, R.j);
-  const double dt = R.cctl->dt;
-  for (int d = 0; d < 4; ++d) {
-    if (!((R.dirs >> d) & 1)) continue;
-    const bool ydir = d >= 2, plus = (d & 1) == 0;
-    const long long st = ydir ? R.cpitch : 1;
-    const double* q = ydir ? R.cqs : R.cq[parity];
-    const double nu = dt / (ydir ? R.cdy : R.cdx);
-    const long long k0 = plus ? o - st : o - 2 * st;
-    CellX c[4];
-    for (int u = 0; u < 4; ++u) c[u] = line_cell(R.P, q, R.cB, R.cplane, k0 + u * st, ydir);
-    double gr[2], gl[2];
-    face_terms(R.P, c, nu, gr, gl);
-    const int mf = ydir ? 2 : 1;
-    for (int m = 0; m < 2; ++m) {
-      const double mo = q[(3 * m + mf) * R.cplane + o];
-      R.reg[2 * d + m] = plus ? mo + gr[m] : mo - gl[m];
-      R.reg[8 + 2 * d + m] = 0.0;
-    }
+  const bool ydir = d >= 2, plus = (d & 1) == 0;
+  const long long st = ydir ? R.cpitch : 1;
+  const double* q = ydir ? R.cqs : R.cq[parity];
+  const double nu = R.cctl->dt / (ydir ? R.cdy : R.cdx);
+  const long long k0 = plus ? o - st : o - 2 * st;
+  CellX c[4];
+  for (int u = 0; u < 4; ++u) c[u] = line_cell(R.P, q, R.cB, R.cplane, k0 + u * st, ydir);
+  double gr[2], gl[2];
+  face_terms(R.P, c, nu, gr, gl);
+  const int mf = ydir ? 2 : 1;
+  for (int m = 0; m < 2; ++m) {
+    const double mo = q[(3 * m + mf) * R.cplane + o];
+    R.reg[2 * d + m] = plus ? mo + gr[m] : mo - gl[m];
+    R.reg[8 + 2 * d + m] = 0.0;
   }
 }
 
-// After a level-(l+1) substep: the fine fluxes through the r fine faces along
-// each recorded face (the fine cell beside the face: its normal momentum minus
-// its term from a face before it, plus its term from a face after it), summed
-// along the face and added to the running sums.
+// After a level-(l+1) substep: the fine flux through each of the r fine faces
+// along each recorded face (the fine cell beside the face: its normal momentum
+// minus its term from a face before it, plus its term from a face after it),
+// one thread per (record, direction, fine face), into the record's slots.
 __global__ __launch_bounds__(64) void k_reflux_fine(const RefluxCell* __restrict__ rcs, int n, int parity) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 64LL * n) return;
+  const RefluxCell& R = rcs[t >> 6];
+  const int d = (int)((t >> 4) & 3), k = (int)(t & 15);
+  const int r = R.r;
+  if (!((R.dirs >> d) & 1) || k >= r) return;
+  const bool ydir = d >= 2, plus = (d & 1) == 0;
+  const long long st = ydir ? R.fpitch : 1;
+  const double* q = ydir ? R.fqs : R.fq[parity];
+  const double nu = R.fctl->dt / (ydir ? R.fdy : R.fdx);
+  int fi, fj;
+  if (d == 0) { fi = r * (R.i + 1); fj = r * R.j + k; }
+  else if (d == 1) { fi = r * R.i - 1; fj = r * R.j + k; }
+  else if (d == 2) { fi = r * R.i + k; fj = r * (R.j + 1); }
+  else { fi = r * R.i + k; fj = r * R.j - 1; }
+  const long long f = cidx(R.fpitch, fi, fj);
+  const long long k0 = plus ? f - 2 * st : f - st;
+  CellX c[4];
+  for (int u = 0; u < 4; ++u) c[u] = line_cell(R.P, q, R.fB, R.fplane, k0 + u * st, ydir);
+  double gr[2], gl[2];
+  face_terms(R.P, c, nu, gr, gl);
+  const int mf = ydir ? 2 : 1;
+  for (int m = 0; m < 2; ++m) {
+    const double mF = q[(3 * m + mf) * R.fplane + f];
+    R.reg[16 + (d * 16 + k) * 2 + m] = plus ? mF - gl[m] : mF + gr[m];
+  }
+}
+
+// The fine fluxes of a substep summed along each face (in face order) and
+// added to the running sums; one thread per record.
+__global__ __launch_bounds__(64) void k_reflux_fsum(const RefluxCell* __restrict__ rcs, int n) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const RefluxCell& R = rcs[t];
-  const double dt = R.fctl->dt;
-  const int r = R.r;
   for (int d = 0; d < 4; ++d) {
     if (!((R.dirs >> d) & 1)) continue;
-    const bool ydir = d >= 2, plus = (d & 1) == 0;
-    const long long st = ydir ? R.fpitch : 1;
-    const double* q = ydir ? R.fqs : R.fq[parity];
-    const double nu = dt / (ydir ? R.fdy : R.fdx);
-    const int mf = ydir ? 2 : 1;
-    double sum[2] = {0.0, 0.0};
-    for (int k = 0; k < r; ++k) {
-      int fi, fj;
-      if (d == 0) { fi = r * (R.i + 1); fj = r * R.j + k; }
-      else if (d == 1) { fi = r * R.i - 1; fj = r * R.j + k; }
-      else if (d == 2) { fi = r * R.i + k; fj = r * (R.j + 1); }
-      else { fi = r * R.i + k; fj = r * R.j - 1; }
-      const long long f = cidx(R.fpitch, fi, fj);
-      const long long k0 = plus ? f - 2 * st : f - st;
-      CellX c[4];
-      for (int u = 0; u < 4; ++u) c[u] = line_cell(R.P, q, R.fB, R.fplane, k0 + u * st, ydir);
-      double gr[2], gl[2];
-      face_terms(R.P, c, nu, gr, gl);
-      for (int m = 0; m < 2; ++m) {
-        const double mF = q[(3 * m + mf) * R.fplane + f];
-        const double g = plus ? mF - gl[m] : mF + gr[m];
-        sum[m] = k == 0 ? g : sum[m] + g;
-      }
+    for (int m = 0; m < 2; ++m) {
+      double s = R.reg[16 + (d * 16) * 2 + m];
+      for (int k = 1; k < R.r; ++k) s = s + R.reg[16 + (d * 16 + k) * 2 + m];
+      R.reg[8 + 2 * d + m] = R.reg[8 + 2 * d + m] + s;
     }
-    for (int m = 0; m < 2; ++m) R.reg[8 + 2 * d + m] = R.reg[8 + 2 * d + m] + sum[m];
   }
 }
 

@@ -238,7 +238,7 @@ struct RefluxCell {
   const double* fB;
   const LevelCtl* cctl;
   const LevelCtl* fctl;
-  double* reg;            // [4][2] gc, then [4][2] acc
+  double* reg;            // [4][2] gc, [4][2] acc, then [4][16][2] fine face fluxes of a substep
   long long cpitch, cplane, fpitch, fplane;
   int i, j, dirs, r;
   double cdx, cdy, fdx, fdy;
@@ -246,6 +246,8 @@ struct RefluxCell {
 };
 __global__ void k_reflux_coarse(const RefluxCell* __restrict__ rc, int n, int parity);
 __global__ void k_reflux_fine(const RefluxCell* __restrict__ rc, int n, int parity);
+__global__ void k_reflux_fsum(const RefluxCell* __restrict__ rc, int n);
+constexpr int REFLUX_REG = 16 + 128;  // doubles of registers per record (ratios up to 16)
 __global__ void k_reflux_apply(const RefluxCell* __restrict__ rc, int n, int parity);
 __global__ void k_flag_raw(const FlagLevel* __restrict__ Fs);
 __global__ void k_flag_dilate(const FlagLevel* __restrict__ Fs);

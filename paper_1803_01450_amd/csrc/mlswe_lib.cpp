@@ -681,8 +681,8 @@ int build_launch(mlswe_ctx* c, int l) {
   if (c->cfg.reflux && l >= 1) {
     if ((rc = build_reflux(c, l, rfx))) return rc;
     if ((rc = ensure(c, &LL.rfx, &LL.cap_rfx, std::max(1, LL.nrfx)))) return rc;
-    if ((rc = ensure(c, &LL.rfx_reg, &LL.cap_rfx_reg, 16 * std::max(1, LL.nrfx)))) return rc;
-    for (int k = 0; k < LL.nrfx; ++k) rfx[k].reg = LL.rfx_reg + 16 * (size_t)k;
+    if ((rc = ensure(c, &LL.rfx_reg, &LL.cap_rfx_reg, REFLUX_REG * std::max(1, LL.nrfx)))) return rc;
+    for (int k = 0; k < LL.nrfx; ++k) rfx[k].reg = LL.rfx_reg + REFLUX_REG * (size_t)k;
     if (LL.nrfx)
       HIPCHK(c, hipMemcpyAsync(LL.rfx, rfx.data(), sizeof(RefluxCell) * LL.nrfx, hipMemcpyHostToDevice, c->stream));
   }
@@ -864,13 +864,17 @@ int launch_reflux(mlswe_ctx* c, int lf, int p0, int p1, int which, int parity) {
     count = LL.rfx_first[p] + LL.rfx_count[p] - first;
   }
   if (count == 0) return MLSWE_OK;
-  const dim3 grid((unsigned)((count + 63) / 64)), block(64);
-  if (which == 0)
-    hipLaunchKernelGGL(k_reflux_coarse, grid, block, 0, c->stream, LL.rfx + first, count, parity);
-  else if (which == 1)
-    hipLaunchKernelGGL(k_reflux_fine, grid, block, 0, c->stream, LL.rfx + first, count, parity);
-  else
-    hipLaunchKernelGGL(k_reflux_apply, grid, block, 0, c->stream, LL.rfx + first, count, parity);
+  auto blocks_of = [](long long threads) { return dim3((unsigned)((threads + 63) / 64)); };
+  const dim3 block(64);
+  if (which == 0) {
+    hipLaunchKernelGGL(k_reflux_coarse, blocks_of(4LL * count), block, 0, c->stream, LL.rfx + first, count, parity);
+  } else if (which == 1) {
+    hipLaunchKernelGGL(k_reflux_fine, blocks_of(64LL * count), block, 0, c->stream, LL.rfx + first, count, parity);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_reflux_fsum, blocks_of(count), block, 0, c->stream, LL.rfx + first, count);
+  } else {
+    hipLaunchKernelGGL(k_reflux_apply, blocks_of(count), block, 0, c->stream, LL.rfx + first, count, parity);
+  }
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
