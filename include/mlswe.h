@@ -59,7 +59,9 @@ typedef struct mlswe_config {
                          cfl_desired / that number, at most this often; -1 = never
                          (the step then fails with MLSWE_ECFL), 0 = the default 8 */
   int reflux;         /* 1: mass flux correction at coarse-fine edges (the paper has
-                         none): after a level's fine substeps and coarsening, each
+                         none), within mlswe_advance (mlswe_step_level and
+                         mlswe_coarsen called on their own leave it out): after a
+                         level's fine substeps and coarsening, each
                          coarse cell beside a fine patch has the coarse mass flux
                          through the shared face replaced by the fine fluxes summed
                          over the face's fine faces and substeps (divided by r^2),
