@@ -67,6 +67,17 @@ typedef struct mlswe_config {
                          over the face's fine faces and substeps (divided by r^2),
                          so each layer's mass on the composite grid changes only by
                          clipping; 0 (default): off */
+  int dynamic_rt;     /* 1: time-refinement ratios chosen per coarse step (Sec. 2,
+                         text after Eq. 2) from the largest speeds of the last one:
+                         level l takes the fewest substeps per substep of level
+                         l - 1, at most the space ratio, that keep its substep
+                         within cfl_desired of its own speeds and leave every finer
+                         level able to meet its own with full ratios; in a context
+                         of several problems each level takes the largest number
+                         any problem needs (so all launch modes agree); the first
+                         step of a problem uses the space ratios.  0 (default):
+                         time ratio = space ratio */
+  int pad_;
 } mlswe_config;
 
 /* Launch shape of the two sweep kernels.  rows: rows per x-sweep wave / per
@@ -213,6 +224,11 @@ int mlswe_advance(mlswe_ctx* ctx, int n_coarse_steps, int regrid_every, const do
  * synchronise.  Errors: MLSWE_EINVAL (flag other than 0 or 1, t NaN, a speed
  * negative or not finite). */
 int mlswe_get_step_state(mlswe_ctx* ctx, int p, double* out);
+
+/* Time-refinement ratios of problem p's current (last) coarse step: out
+ * [n_levels - 1], level l + 1's substeps per substep of level l (the space
+ * ratios unless mlswe_config.dynamic_rt chose fewer).  Errors: MLSWE_EINVAL. */
+int mlswe_get_time_ratios(mlswe_ctx* ctx, int p, int32_t* out);
 int mlswe_set_step_state(mlswe_ctx* ctx, int p, const double* in);
 
 /* Reads / sets the sweeps' launch shape (setting rebuilds the launch data). */

@@ -66,6 +66,8 @@ def lib():
         L.ora_get_bathymetry.argtypes = [_P, _I, _DP]
         L.ora_get_step_state.argtypes = [_P, _DP]
         L.ora_set_reflux.argtypes = [_P, _I]
+        L.ora_set_dynamic_rt.argtypes = [_P, _I]
+        L.ora_get_rt.argtypes = [_P, _IP]
         L.ora_set_step_state.argtypes = [_P, _DP]
         L.ora_set_state.argtypes = [_P, _I, _DP]
         L.ora_get_state.argtypes = [_P, _I, _DP]
@@ -294,6 +296,17 @@ class Hierarchy:
     def set_reflux(self, on=True):
         """Mass flux correction at coarse-fine edges (off by default)."""
         lib().ora_set_reflux(self.h, 1 if on else 0)
+
+    def set_dynamic_rt(self, on=True):
+        """Time-refinement ratios chosen per coarse step from the last speeds
+        (off by default: each equals the space ratio)."""
+        lib().ora_set_dynamic_rt(self.h, 1 if on else 0)
+
+    def time_ratios(self):
+        """The time ratios of the last coarse step (one per level above 0)."""
+        out = np.zeros(max(1, self.nlev - 1), dtype=np.int32)
+        lib().ora_get_rt(self.h, _ip(out))
+        return out[:self.nlev - 1]
 
     def step_state(self):
         """[t, speeds-known flag, per level largest x / y speeds of the last

@@ -50,6 +50,8 @@ struct Hier {
   int retries = 8;       // rejected coarse steps are retaken at most this often
   int64_t rejected = 0;  // coarse steps rejected so far
   bool reflux = false;   // mass flux correction at coarse-fine edges
+  bool dyn_rt = false;   // time ratios chosen per coarse step from the last speeds
+  int rt[8] = {0};       // substeps of level l + 1 per substep of level l (this coarse step)
 };
 
 // ---------------------------------------------------------------- refine (Sec. 2.1)
@@ -527,8 +529,7 @@ static void reflux_accumulate(const Hier& H, int l, std::vector<RefluxCell>& cel
 
 static void reflux_apply(Hier& H, int l, const std::vector<RefluxCell>& cells, double dt) {
   Level& L = H.L[l];
-  const int r = H.ratio[l];
-  const double inv = 1.0 / double(r * r);
+  const double inv = 1.0 / double(H.ratio[l] * H.rt[l]);  // r fine faces in each of rt substeps
   const double nux = dt / L.dx, nuy = dt / L.dy;
   double* q = L.q[L.cur].data();
   const size_t pl = L.G.plane();
@@ -546,8 +547,43 @@ static void reflux_apply(Hier& H, int l, const std::vector<RefluxCell>& cells, d
   }
 }
 
-// Subcycled recursion: fill and step level l, then r substeps of level l+1 (time
-// ratio equal to the space ratio), then average level l+1 back onto level l
+// ---------------------------------------------------------------- time ratio
+// Time-refinement ratios of a coarse step of length dt (Sec. 2, text after Eq.
+// 2).  By default each equals the space ratio.  With the dynamic choice on and
+// speeds of a last coarse step known, level l (>= 1) takes the fewest substeps
+// per substep of level l - 1, at most the space ratio, that keep its substep
+// within the Courant limit of its own last speeds and leave every finer level
+// able to meet its own with full ratios: with a_l = cfl * min(dx / sx, dy / sy)
+// of the last coarse step (infinite without speeds) and A_l = min(a_l, r_l
+// A_{l+1}) from the finest level up, rt = ceil(dt_{l-1} / A_l) clipped to [1, r].
+static void choose_rt(Hier& H, double dt) {
+  for (int l = 0; l + 1 < H.nlev; ++l) H.rt[l] = H.ratio[l];
+  if (!H.dyn_rt || !H.have_smax) return;
+  const double inf = std::numeric_limits<double>::infinity();
+  double A[8];
+  for (int l = H.nlev - 1; l >= 0; --l) {
+    const Level& L = H.L[l];
+    const double a = L.smax[0] > 0.0 ? L.dx / L.smax[0] : inf;
+    const double b = L.smax[1] > 0.0 ? L.dy / L.smax[1] : inf;
+    const double m = std::min(a, b);
+    const double al = m < inf ? H.cfl * m : inf;
+    A[l] = l + 1 < H.nlev ? std::min(al, double(H.ratio[l]) * A[l + 1]) : al;
+  }
+  double dtp = dt;
+  for (int l = 1; l < H.nlev; ++l) {
+    const double q = dtp / A[l];
+    int k = H.ratio[l - 1];
+    if (q < double(k)) {
+      const double c = std::ceil(q);
+      k = c < 1.0 ? 1 : int(c);
+    }
+    H.rt[l - 1] = k;
+    dtp = dtp / double(k);
+  }
+}
+
+// Subcycled recursion: fill and step level l, then rt substeps of level l+1
+// (the time ratio of this coarse step), then average level l+1 back onto level l
 // (and, with the flux correction on, correct the coarse cells beside it).
 // A substep above the Courant limit does not stop the step: the whole coarse
 // step is completed and judged by its largest substep Courant number.
@@ -556,7 +592,7 @@ static int adv(Hier& H, int l, double dt, double th) {
   int rc = step_level(H, l, dt, th, s);
   if (rc && rc != E_CFL) return rc;
   if (l + 1 < H.nlev && !H.L[l + 1].boxes.empty()) {
-    const int r = H.ratio[l];
+    const int r = H.rt[l];
     const double dtf = dt / double(r);
     std::vector<RefluxCell> rf;
     if (H.reflux) rf = reflux_begin(H, l);
@@ -580,6 +616,7 @@ static int advance(Hier& H, int nsteps, int regrid_every, const double* tau, int
       if (rc) return rc;
     }
     double dt = next_dt(H);
+    choose_rt(H, dt);
     std::vector<std::vector<double>> save(H.nlev);
     std::vector<int> save_cur(H.nlev);
     Counters save_c = H.C;
@@ -627,6 +664,7 @@ void* ora_create(double g, double r, double hdry, double kmin, double cfl, doubl
   for (int l = 0; l < nlev; ++l) {
     if (l > 0) {
       H->ratio[l - 1] = ratios[l - 1];
+      H->rt[l - 1] = ratios[l - 1];
       nx *= ratios[l - 1]; ny *= ratios[l - 1];
       dx = dx / ratios[l - 1]; dy = dy / ratios[l - 1];
     }
@@ -754,6 +792,14 @@ int ora_advance(void* h, int nsteps, int regrid_every, const double* tau, int nb
 double ora_next_dt(void* h) { return next_dt(*static_cast<Hier*>(h)); }
 
 void ora_set_reflux(void* h, int on) { static_cast<Hier*>(h)->reflux = on != 0; }
+
+void ora_set_dynamic_rt(void* h, int on) { static_cast<Hier*>(h)->dyn_rt = on != 0; }
+
+// Time ratios of the last coarse step: out[nlev - 1].
+void ora_get_rt(void* h, int* out) {
+  Hier* H = static_cast<Hier*>(h);
+  for (int l = 0; l + 1 < H->nlev; ++l) out[l] = H->rt[l];
+}
 
 // Time-stepping state for checkpoint and resume: t, whether the next coarse
 // step takes its dt from the last step's speeds (else from the state), and each

@@ -30,7 +30,8 @@ class Config(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("hdry", ctypes.c_double), ("kmin", ctypes.c_double),
                 ("cfl_desired", ctypes.c_double), ("cfl_max", ctypes.c_double),
                 ("y_rows", ctypes.c_int), ("x_rows", ctypes.c_int),
-                ("max_device_bytes", ctypes.c_int64), ("max_retries", ctypes.c_int), ("reflux", ctypes.c_int)]
+                ("max_device_bytes", ctypes.c_int64), ("max_retries", ctypes.c_int), ("reflux", ctypes.c_int),
+                ("dynamic_rt", ctypes.c_int), ("pad_", ctypes.c_int)]
 
 
 class CountersC(ctypes.Structure):
@@ -98,6 +99,7 @@ def lib():
             "mlswe_autotune": (I, [P, ctypes.c_char_p, I]),
             "mlswe_run_tiles": (I, [I, I, I, I32P, I, I, I32P, I]),
             "mlswe_get_step_state": (I, [P, I, DP]),
+            "mlswe_get_time_ratios": (I, [P, I, I32P]),
             "mlswe_set_step_state": (I, [P, I, DP]),
             "mlswe_refine_layers": (I, [P, I, I, V, V, I, I, I, I, I, I, V, V, ctypes.POINTER(ctypes.c_int64)]),
             "mlswe_coarsen_layers": (I, [P, I, I, V, I, I, I, I, V, I, I]),
@@ -144,9 +146,10 @@ class Solver:
     """One library context (one GPU stream) holding any number of problems."""
 
     def __init__(self, g=9.81, hdry=1e-3, kmin=1e-6, cfl=0.9, cfl_max=1.0, y_rows=0, x_rows=0,
-                 max_device_bytes=0, stream=None, max_retries=0, reflux=False):
+                 max_device_bytes=0, stream=None, max_retries=0, reflux=False, dynamic_rt=False):
         self.L = lib()
-        cfg = Config(g, hdry, kmin, cfl, cfl_max, y_rows, x_rows, max_device_bytes, max_retries, 1 if reflux else 0)
+        cfg = Config(g, hdry, kmin, cfl, cfl_max, y_rows, x_rows, max_device_bytes, max_retries, 1 if reflux else 0,
+                     1 if dynamic_rt else 0, 0)
         h = ctypes.c_void_p()
         rc = self.L.mlswe_create(ctypes.byref(cfg), stream, ctypes.byref(h))
         if rc:
@@ -263,6 +266,13 @@ class Solver:
                                   dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_dts else None)
         self._check(rc)
         return dts
+
+    def time_ratios(self, p):
+        """Time ratios of problem p's last coarse step (one per level above 0)."""
+        n = len(self.shapes[p]) - 1
+        out = np.zeros(max(1, n), dtype=np.int32)
+        self._check(self.L.mlswe_get_time_ratios(self.h, p, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out[:n]
 
     def counters(self, p):
         c = CountersC()

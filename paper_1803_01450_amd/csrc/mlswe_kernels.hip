@@ -357,7 +357,7 @@ __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int npr
   double dt = best;
   for (int l = 0; l < D.nlev; ++l) {
     LevelCtl& C = ctls[D.ctl0 + l];
-    if (l > 0) dt = dt / (double)D.ratio[l - 1];
+    if (l > 0) dt = dt / (double)D.rt[l - 1];
     C.dt = dt;
     C.acc_smax[0] = 0ull;
     C.acc_smax[1] = 0ull;
@@ -376,7 +376,7 @@ __global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const d
   double dt = dt0[p];
   for (int l = 0; l < D.nlev; ++l) {
     LevelCtl& C = ctls[D.ctl0 + l];
-    if (l > 0) dt = dt / (double)D.ratio[l - 1];
+    if (l > 0) dt = dt / (double)D.rt[l - 1];
     C.dt = dt;
     C.acc_smax[0] = 0ull;
     C.acc_smax[1] = 0ull;
@@ -515,15 +515,15 @@ __global__ __launch_bounds__(64) void k_reflux_fsum(const RefluxCell* __restrict
   }
 }
 
-// After coarsening: nu_c (gc - acc / r^2) added to (faces after O) or
+// After coarsening: nu_c (gc - acc / (r rt)) added to (faces after O) or
 // subtracted from (faces before O) O's depths, faces in the order +x, -x, +y, -y.
-__global__ __launch_bounds__(64) void k_reflux_apply(const RefluxCell* __restrict__ rcs, int n, int parity) {
+__global__ __launch_bounds__(64) void k_reflux_apply(const RefluxCell* __restrict__ rcs, int n, int parity, int rt) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const RefluxCell& R = rcs[t];
   const long long o = cidx(R.cpitch, R.i, R.j);
   const double dt = R.cctl->dt;
-  const double inv = 1.0 / double(R.r * R.r);
+  const double inv = 1.0 / double(R.r * rt);  // r fine faces in each of rt substeps
   const double nux = dt / R.cdx, nuy = dt / R.cdy;
   double* q = R.cq[parity];
   double h[2] = {q[o], q[3 * R.cplane + o]};

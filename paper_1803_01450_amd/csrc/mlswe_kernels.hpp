@@ -135,7 +135,8 @@ struct SpeedLevel {
 
 struct ProbDt {
   int ctl0, nlev;
-  int ratio[8];
+  int ratio[8];   // space ratios (the dt limit)
+  int rt[8];      // time ratios of the coming coarse step (the levels' substeps)
   int active[8];
   double dx[8], dy[8];
   double* dt_out;
@@ -248,7 +249,7 @@ __global__ void k_reflux_coarse(const RefluxCell* __restrict__ rc, int n, int pa
 __global__ void k_reflux_fine(const RefluxCell* __restrict__ rc, int n, int parity);
 __global__ void k_reflux_fsum(const RefluxCell* __restrict__ rc, int n);
 constexpr int REFLUX_REG = 16 + 128;  // doubles of registers per record (ratios up to 16)
-__global__ void k_reflux_apply(const RefluxCell* __restrict__ rc, int n, int parity);
+__global__ void k_reflux_apply(const RefluxCell* __restrict__ rc, int n, int parity, int rt);
 __global__ void k_flag_raw(const FlagLevel* __restrict__ Fs);
 __global__ void k_flag_dilate(const FlagLevel* __restrict__ Fs);
 __global__ void k_flag_tiles(const FlagTiles* __restrict__ Ts);

@@ -65,6 +65,7 @@ struct ProblemH {
   PhysParams P;
   int nlev = 1;
   int ratio[MAXLEV] = {0};
+  int rt[MAXLEV] = {0};  // time ratios of the current coarse step (the space ratios unless chosen)
   LevelH L[MAXLEV];
   int ctl0 = 0;  // index of level 0's LevelCtl
   int cnt = 0;   // index of the problem's counters
@@ -153,7 +154,7 @@ struct mlswe_ctx {
   hipStream_t cap_stream = nullptr;
   long long generation = 0;      // bumped whenever launch data may have changed
   struct GraphRec {
-    unsigned key;
+    unsigned long long key;
     long long gen;
     int p0, p1;
     hipGraphExec_t exec;
@@ -709,6 +710,7 @@ int build_pdt(mlswe_ctx* c) {
     d.ctl0 = P.ctl0; d.nlev = P.nlev;
     for (int l = 0; l < P.nlev; ++l) {
       d.ratio[l] = P.ratio[l];
+      d.rt[l] = P.rt[l];
       d.active[l] = P.L[l].boxes.empty() ? 0 : 1;
       d.dx[l] = P.L[l].dx; d.dy[l] = P.L[l].dy;
     }
@@ -873,7 +875,8 @@ int launch_reflux(mlswe_ctx* c, int lf, int p0, int p1, int which, int parity) {
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL(k_reflux_fsum, blocks_of(count), block, 0, c->stream, LL.rfx + first, count);
   } else {
-    hipLaunchKernelGGL(k_reflux_apply, blocks_of(count), block, 0, c->stream, LL.rfx + first, count, parity);
+    hipLaunchKernelGGL(k_reflux_apply, blocks_of(count), block, 0, c->stream, LL.rfx + first, count, parity,
+                       c->probs[p0].rt[lf - 1]);
   }
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
@@ -980,7 +983,7 @@ int adv(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
   if ((rc = substep(c, l, p0, p1, theta, batched))) return rc;
   const ProblemH& P0 = c->probs[p0];
   if (l + 1 < P0.nlev && level_active(c, l + 1, p0, p1)) {
-    const int r = P0.ratio[l];
+    const int r = P0.rt[l];
     for (int k = 0; k < r; ++k)
       if ((rc = adv(c, l + 1, p0, p1, double(k) / double(r), batched))) return rc;
     if ((rc = coarsen_level(c, l + 1, p0, p1, true))) return rc;
@@ -1366,7 +1369,8 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
   if (cfg) d = *cfg;
   if (d.max_retries == 0) d.max_retries = 8;
   if (!(d.g > 0) || !(d.hdry > 0) || !(d.kmin > 0) || !(d.cfl_desired > 0) || !(d.cfl_max >= d.cfl_desired) ||
-      d.y_rows < 0 || d.x_rows < 0 || (d.reflux != 0 && d.reflux != 1)) {
+      d.y_rows < 0 || d.x_rows < 0 || (d.reflux != 0 && d.reflux != 1) ||
+      (d.dynamic_rt != 0 && d.dynamic_rt != 1)) {
     delete c;
     return MLSWE_EINVAL;
   }
@@ -1439,6 +1443,7 @@ int mlswe_problem_define(mlswe_ctx* c, int* p_out, double r, int nx0, int ny0, d
   for (int l = 0; l < nlevels; ++l) {
     if (l > 0) {
       P.ratio[l - 1] = ratios[l - 1];
+      P.rt[l - 1] = ratios[l - 1];
       nx *= ratios[l - 1]; ny *= ratios[l - 1];
       dx = dx / ratios[l - 1]; dy = dy / ratios[l - 1];
     }
@@ -1594,6 +1599,13 @@ int mlswe_get_step_state(mlswe_ctx* c, int p, double* out) {
     out[2 + 2 * l] = __builtin_bit_cast(double, (long long)h[l].acc_smax[0]);
     out[3 + 2 * l] = __builtin_bit_cast(double, (long long)h[l].acc_smax[1]);
   }
+  return MLSWE_OK;
+}
+
+int mlswe_get_time_ratios(mlswe_ctx* c, int p, int32_t* out) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || !out) return fail(c, MLSWE_EINVAL, "bad args");
+  for (int l = 0; l + 1 < c->probs[p].nlev; ++l) out[l] = c->probs[p].rt[l];
   return MLSWE_OK;
 }
 
@@ -1770,6 +1782,65 @@ int mlswe_coarsen_layers(mlswe_ctx* c, int M, int r, const double* qf, int ci0, 
 
 namespace {
 
+// Time ratios of the coming coarse step from the largest speeds of the last one
+// (reading of Sec. 2, text after Eq. 2): per problem, with a_l = cfl * min(dx /
+// sx, dy / sy) (infinite without speeds), A_l = min(a_l, r_l A_{l+1}) from the
+// finest level up and dt0 the coming coarse step (the dt rule's value), level
+// l takes ceil(dt_{l-1} / A_l) substeps, clipped to [1, r]; a problem without
+// speeds takes the space ratios.  Each level then takes the largest number any
+// problem takes (clipped to each problem's ratio).
+int choose_time_ratios(mlswe_ctx* c) {
+  const int np = (int)c->probs.size();
+  std::vector<LevelCtl> h;
+  int rc;
+  if ((rc = read_ctls(c, 0, np, h))) return rc;
+  const int base = c->probs[0].ctl0;
+  const double inf = std::numeric_limits<double>::infinity();
+  int RT[MAXLEV] = {0};
+  for (int p = 0; p < np; ++p) {
+    const ProblemH& P = c->probs[p];
+    int k[MAXLEV];
+    for (int l = 0; l + 1 < P.nlev; ++l) k[l] = P.ratio[l];
+    if (P.have_dt) {
+      double a[MAXLEV], A[MAXLEV];
+      double best = inf, fac = 1.0;
+      for (int l = 0; l < P.nlev; ++l) {
+        const LevelCtl& C = h[(size_t)(P.ctl0 - base + l)];
+        if (l > 0) fac *= (double)P.ratio[l - 1];
+        const double sx = __builtin_bit_cast(double, (long long)C.acc_smax[0]);
+        const double sy = __builtin_bit_cast(double, (long long)C.acc_smax[1]);
+        const double ax = sx > 0.0 ? P.L[l].dx / sx : inf;
+        const double ay = sy > 0.0 ? P.L[l].dy / sy : inf;
+        const double m = ax < ay ? ax : ay;
+        a[l] = m < inf ? c->cfg.cfl_desired * m : inf;
+        if (m < inf) { const double v = fac * (c->cfg.cfl_desired * m); best = v < best ? v : best; }
+      }
+      for (int l = P.nlev - 1; l >= 0; --l)
+        A[l] = l + 1 < P.nlev ? std::min(a[l], (double)P.ratio[l] * A[l + 1]) : a[l];
+      double dtp = best;
+      for (int l = 1; l < P.nlev; ++l) {
+        const double q = dtp / A[l];
+        int kk = P.ratio[l - 1];
+        if (q < (double)kk) {
+          const double cq = std::ceil(q);
+          kk = cq < 1.0 ? 1 : (int)cq;
+        }
+        k[l - 1] = kk;
+        dtp = dtp / (double)kk;
+      }
+    }
+    for (int l = 0; l + 1 < P.nlev; ++l) RT[l] = std::max(RT[l], k[l]);
+  }
+  for (int p = 0; p < np; ++p) {
+    ProblemH& P = c->probs[p];
+    for (int l = 0; l + 1 < P.nlev; ++l) {
+      const int v = std::min(RT[l], P.ratio[l]);
+      if (v != P.rt[l]) { P.rt[l] = v; c->pdt_dirty = true; }
+    }
+  }
+  return MLSWE_OK;
+}
+
 int build_all(mlswe_ctx* c) {
   int nl = 0;
   for (const ProblemH& P : c->probs) nl = std::max(nl, P.nlev);
@@ -1799,8 +1870,10 @@ int coarse_step(mlswe_ctx* c, int p0, int p1, bool batched) {
 int graph_step(mlswe_ctx* c, int p0, int p1) {
   int rc;
   const ProblemH& P0 = c->probs[p0];
-  unsigned key = 0;
-  for (int l = 0; l < P0.nlev; ++l) key |= (unsigned)P0.L[l].cur << l;
+  // buffer parities, then the time ratios (the substep structure)
+  unsigned long long key = 0;
+  for (int l = 0; l < P0.nlev; ++l) key |= (unsigned long long)P0.L[l].cur << l;
+  for (int l = 0; l + 1 < P0.nlev; ++l) key |= (unsigned long long)(P0.rt[l] & 31) << (8 + 5 * l);
   for (auto it = c->graphs.begin(); it != c->graphs.end();) {
     if (it->gen != c->generation) {
       (void)hipGraphExecDestroy(it->exec);
@@ -2041,6 +2114,7 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
     int rc;
     if (regrid_every > 0 && n % regrid_every == 0)
       if ((rc = regrid_group(c, 0, np, tau, nbuf))) return rc;
+    if (c->cfg.dynamic_rt && (rc = choose_time_ratios(c))) return rc;
     if ((rc = build_pdt(c))) return rc;
     for (int gi = 0; gi < ngroups; ++gi) {
       const int p0 = together ? 0 : gi, p1 = together ? np : gi + 1;

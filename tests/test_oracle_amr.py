@@ -361,3 +361,56 @@ def test_flux_correction_conserves_mass():
     ring &= ~fine
     changed = diff[0] | diff[3]
     assert changed.any() and not (changed & ~ring).any()
+
+
+def _shallow_patch_run(dyn, reflux=False, steps=4):
+    """Ratio 4, one fine patch over the shallow end of the slope (about 1000 m
+    deep against 4000 m at the deep end)."""
+    c = inputs.fixed_small()
+    H = oracle.Hierarchy(64, 64, c["dx"], c["dx"], ratios=(4,), r=c["r"])
+    H.set_dynamic_rt(dyn)
+    H.set_reflux(reflux)
+    H.set_bathymetry(np.kron(c["B"], np.ones((4, 4)))); H.set_state(0, c["q"])
+    H.set_patches(1, [(208, 32, 32, 64)])
+    rts, dts, speeds = [], [], []
+    for _ in range(steps):
+        speeds.append(H.step_state())
+        rc, d = H.advance(1)
+        assert rc == 0
+        rts.append(int(H.time_ratios()[0])); dts.append(d[0])
+    return H, rts, np.array(dts), speeds, c
+
+
+def test_dynamic_time_ratio():
+    """Fine patch in shallow water, coarse step set by the deep water: the
+    dynamic choice takes 3 fine substeps instead of 4 once speeds are known,
+    each the fewest within the Courant limit of the fine level's own last
+    speeds; dts, clock and rejections are unchanged, fine updates drop by a
+    quarter."""
+    Hf, rf, df, _, c = _shallow_patch_run(False)
+    Hd, rd, dd, sp, _ = _shallow_patch_run(True)
+    assert rf == [4, 4, 4, 4] and rd == [4, 3, 3, 3]
+    assert np.array_equal(df, dd)
+    assert Hd.counters()["rejected"] == 0 and Hd.counters()["t"] == Hf.counters()["t"]
+    assert Hd.counters()["updates"][1] * 4 == Hf.counters()["updates"][1] * 13 // 4
+    dxf = c["dx"] / 4
+    for n in range(1, 4):
+        s = sp[n]  # speeds of the step before step n: [t, flag, sx0, sy0, sx1, sy1]
+        lim = 0.9 * min(dxf / s[4], dxf / s[5])
+        k = rd[n]
+        assert dd[n] / k <= lim and (k == 1 or dd[n] / (k - 1) > lim), (n, k)
+
+
+def test_dynamic_time_ratio_with_flux_correction_conserves_mass():
+    """The flux correction averages the fine fluxes over the substeps actually
+    taken (3 of ratio 4 here): composite mass is still conserved to rounding."""
+    c = inputs.fixed_small()
+    H = oracle.Hierarchy(64, 64, c["dx"], c["dx"], ratios=(4,), r=c["r"])
+    H.set_dynamic_rt(True); H.set_reflux(True)
+    H.set_bathymetry(np.kron(c["B"], np.ones((4, 4)))); H.set_state(0, c["q"])
+    m0 = _composite_mass(H, 1, (4,), c["dx"])
+    H.set_patches(1, [(208, 32, 32, 64)])
+    rc, _ = H.advance(5)
+    assert rc == 0 and int(H.time_ratios()[0]) == 3
+    drift = np.abs(_composite_mass(H, 2, (4,), c["dx"]) - m0) / m0
+    assert np.all(drift <= 1e-14), drift
