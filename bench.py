@@ -115,21 +115,23 @@ def bench_batch(nprob, steps, stream, modes=("plain", "batched", "graph")):
     return out
 
 
-def bench_amr(steps, stream, modes=("plain", "batched", "graph", "reflux")):
+def bench_amr(steps, stream, modes=("plain", "batched", "graph", "reflux", "dynrt")):
     """Three levels (ratios 2 and 4) over 400 km with shorelines, 16 level-0
     patches of 64^2, regrid every 4 coarse steps.  "reflux": batched launches
-    with the mass flux correction at coarse-fine edges."""
+    with the mass flux correction at coarse-fine edges; "dynrt": batched with
+    time ratios chosen per coarse step."""
     import numpy as np
     from paper_1803_01450_amd import inputs
     from paper_1803_01450_amd.binding import Solver, PLAIN, BATCHED, GRAPH
     c = inputs.amr_shoreline()
     tau = [[2e-6, 4e-6]]
     out = {}
-    for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH), ("reflux", BATCHED)):
+    for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH), ("reflux", BATCHED),
+                       ("dynrt", BATCHED)):
         if name not in modes:
             continue
         print("bench: AMR 3 levels, %s" % name, file=sys.stderr, flush=True)
-        S = Solver(stream=stream, reflux=name == "reflux")
+        S = Solver(stream=stream, reflux=name == "reflux", dynamic_rt=name == "dynrt")
         p = S.define(c["n0"], c["n0"], c["dx0"], c["dx0"], c["r"], c["ratios"])
         S.set_bathymetry(p, c["Bf"])
         S.set_patches(p, 0, c["level0_boxes"])
@@ -137,11 +139,14 @@ def bench_amr(steps, stream, modes=("plain", "batched", "graph", "reflux")):
         S.advance(2, 4, tau, mode=mode)
         sec, upd = timed_advance(S, steps, 4, tau, mode)
         out[name] = {"seconds": sec, "cell_updates": upd, "rate": upd / sec,
-                     "finest_patches": int(len(S.patches(p, 2)))}
+                     "finest_patches": int(len(S.patches(p, 2))),
+                     "time_ratios": [int(v) for v in S.time_ratios(p)]}
         S.close()
     ratios(out, modes)
     if "reflux" in out and "batched" in out:
         out["reflux_time_ratio"] = out["reflux"]["seconds"] / out["batched"]["seconds"]
+    if "dynrt" in out and "batched" in out:
+        out["dynrt_time_ratio"] = out["dynrt"]["seconds"] / out["batched"]["seconds"]
     out["coarse_steps"] = steps
     return out
 
@@ -336,8 +341,7 @@ def copy_probe(mib):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)

@@ -10,7 +10,7 @@ level hierarchy and ratios (Sec. 2, Eqs. 1-2), time refinement (Sec. 2), wet
 ordering, surface (not depth) refinement, effective bathymetry and the
 minmod-limited interpolant (Sec. 2.1, Eqs. 3-10), coarsening by averaging
 (Sec. 2.2, Eq. 11).  The solver itself is not written in the paper (Sec. 1 cites
-it); the reading used is documented in the design notes.
+it); the readings used are stated in the comments of ``ora_core.hpp``.
 """
 from __future__ import annotations
 

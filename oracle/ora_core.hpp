@@ -10,8 +10,8 @@
 // Eqs. 3-10), the coarsen operator (Sec. 2.2, Eq. 11) and the level/ratio
 // structure (Sec. 2, Eqs. 1-2).  It does not write the governing equations or the
 // Riemann solver (Sec. 1 only cites the multilayer GeoClaw solver); the readings
-// used here for those parts are the ones listed in the design notes
-// ("Readings of the paper").
+// used for those parts are stated where they are applied below (edge solve,
+// wet/dry edges, limiter, update grouping, fix-up).
 //
 // Every scalar routine is templated on the number type T so that the same code
 // runs in double (parity) and in a forward-mode dual number (adjoint pin).
@@ -207,7 +207,9 @@ void layer_alone(const Params& P, int layer, bool wetL, bool wetR, bool wallIfDr
   W.Z[sS][c0 + 2] = dT - wh * dA;
 }
 
-// Layered f-wave solve at one edge (readings A2/A3 of the design notes).
+// Layered f-wave solve at one edge: the flux-minus-source jump split into four
+// coupled waves (speeds to first order in 1 - r at Roe averages, eigenvectors
+// (1, s, alpha, alpha s)) and two shear waves; wet/dry edges per layer.
 template <class T>
 void riemann(const Params& P, const CellV<T>& L, const CellV<T>& R, Waves<T>& W, Counters& C,
              bool count) {

@@ -7,8 +7,8 @@ see identical inputs.  Everything is drawn from ``numpy.random.default_rng(seed)
 in a fixed order; coordinates are cell centres.
 
 The paper's own demonstration (Sec. 3) is not reproducible (its set-ups are not
-part of the text), so the workloads are synthetic stand-ins with the shapes, sizes
-and value ranges of the configurations listed in the design notes.
+part of the text), so the workloads are synthetic stand-ins; each generator
+below states its shapes, sizes and value ranges.
 """
 from __future__ import annotations
 

@@ -127,7 +127,7 @@ def test_speeds_at_rest_and_quartic_roots():
         eps = (1 - r) * hb1 * h2 / H ** 2
         assert abs(s[3] - lam_e) / lam_e <= 2 * eps
         assert abs(s[2] - lam_i) / lam_i <= 2 * eps
-    # the worked numbers of the design notes: h1 = 200, h2 = 3800, r = 0.95
+    # worked numbers: h1 = 200, h2 = 3800, r = 0.95 give an external speed of 197.855 m/s
     H = 4000.0
     disc = np.sqrt(H * H - 4 * 0.05 * 200 * 3800)
     assert abs(np.sqrt(G * (H + disc) / 2) - 197.855) < 1e-3
