@@ -73,6 +73,17 @@ def timed_advance(S, steps, every, tau, mode):
     return t1 - t0, after - before
 
 
+def phase_breakdown(S, steps, every, tau, mode):
+    """A second pass of the same steps with per-phase HIP-event timing (outside
+    the timed region: the events add gaps): milliseconds per coarse step of
+    each phase, the regrid as host wall time."""
+    S.set_kernel_timing(True)
+    S.advance(steps, every, tau, mode=mode)
+    ph = S.phase_times()
+    S.set_kernel_timing(False)
+    return {k: round(ms / steps, 4) for k, (ms, n) in ph.items()}
+
+
 def ratios(out, modes):
     if "plain" in modes:
         for m in ("batched", "graph"):
@@ -107,6 +118,7 @@ def bench_batch(nprob, steps, stream, modes=("plain", "batched", "graph")):
         out[name] = {"seconds": sec, "cell_updates": upd, "rate": upd / sec}
         if name == "batched":
             out["tuning"] = S.tuning()
+            out["phases_ms_per_coarse_step"] = phase_breakdown(S, steps, 10, tau, mode)
         S.close()
     ratios(out, modes)
     out["problems"] = nprob
@@ -138,6 +150,8 @@ def bench_amr(steps, stream, modes=("plain", "batched", "graph", "reflux", "dynr
         S.set_state(p, 0, c["q0"])
         S.advance(2, 4, tau, mode=mode)
         sec, upd = timed_advance(S, steps, 4, tau, mode)
+        if name == "batched":
+            out["phases_ms_per_coarse_step"] = phase_breakdown(S, steps, 4, tau, mode)
         out[name] = {"seconds": sec, "cell_updates": upd, "rate": upd / sec,
                      "finest_patches": int(len(S.patches(p, 2))),
                      "time_ratios": [int(v) for v in S.time_ratios(p)]}

@@ -256,6 +256,16 @@ int mlswe_synchronize(mlswe_ctx* ctx);
 int mlswe_set_kernel_timing(mlswe_ctx* ctx, int enable);
 int mlswe_kernel_times(mlswe_ctx* ctx, double* ms_out /*[2]*/, int64_t* launches_out /*[2]*/);
 
+/* Phase times since timing was enabled (mlswe_set_kernel_timing), per class:
+ * 0 x-sweep, 1 y-sweep, 2 ghost fill, 3 substep reduction (speeds, Courant
+ * check, counters), 4 coarsening, 5 flux correction, 6 dt rule (HIP events on
+ * the context's stream around each launch group), 7 regrid (host wall time of
+ * the regrid of all problems, its kernels and readbacks included).  Writes up
+ * to cap classes of summed milliseconds and counts and returns the number of
+ * classes (8).  Timing runs graph-mode advances eagerly.  Synchronises.
+ * Errors: MLSWE_EINVAL. */
+int mlswe_phase_times(mlswe_ctx* ctx, double* ms_out, int64_t* counts_out, int cap);
+
 /* ---------------------------------------------------------------- adjoint
  * Differentiation of a fixed-grid run with a frozen dt sequence, for problems
  * with one level whose states keep both layers wet (the solve's reverse is the

@@ -88,6 +88,7 @@ def lib():
             "mlswe_synchronize": (I, [P]),
             "mlswe_set_kernel_timing": (I, [P, I]),
             "mlswe_kernel_times": (I, [P, DP, ctypes.POINTER(ctypes.c_int64)]),
+            "mlswe_phase_times": (I, [P, DP, ctypes.POINTER(ctypes.c_int64), I]),
             "mlswe_run_fixed": (I, [P, I, I, DP]),
             "mlswe_adjoint_step": (I, [P, I, V, V, V, V, D]),
             "mlswe_param_map": (I, [P, I, V, D, V]),
@@ -315,6 +316,18 @@ class Solver:
 
     def set_kernel_timing(self, on=True):
         self._check(self.L.mlswe_set_kernel_timing(self.h, 1 if on else 0))
+
+    PHASES = ("x_sweep", "y_sweep", "ghost_fill", "substep_reduction", "coarsen", "flux_correction", "dt_rule",
+              "regrid")
+
+    def phase_times(self):
+        """{phase: (milliseconds, count)} since timing was enabled."""
+        ms = (ctypes.c_double * 8)()
+        n = (ctypes.c_int64 * 8)()
+        rc = self.L.mlswe_phase_times(self.h, ms, n, 8)
+        if rc < 0:
+            self._check(rc)
+        return {name: (ms[k], int(n[k])) for k, name in enumerate(self.PHASES)}
 
     def kernel_times(self):
         ms = (ctypes.c_double * 2)()

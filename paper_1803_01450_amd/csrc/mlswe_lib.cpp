@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -141,8 +142,10 @@ struct mlswe_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
-  double kms[2] = {0, 0};
-  long long klaunch[2] = {0, 0};
+  // timed classes: 0 x-sweep, 1 y-sweep, 2 ghost fill, 3 substep reduction,
+  // 4 coarsening, 5 flux correction, 6 dt rule, 7 regrid (host wall time)
+  double kms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long klaunch[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double* dt_stage = nullptr;
   int dt_stage_cap = 0;
   int sig_on = 0;
@@ -753,6 +756,21 @@ int collect_events(mlswe_ctx* c) {
   return MLSWE_OK;
 }
 
+// Brackets the launches that fn queues with two events of class cls when timing
+// is on (never inside a graph capture: timing runs the eager path).
+template <class F>
+int timed(mlswe_ctx* c, int cls, F&& fn) {
+  if (!c->timing) return fn();
+  hipEvent_t e0, e1;
+  int rc;
+  if ((rc = ev_begin(c, &e0))) return rc;
+  if ((rc = fn())) return rc;
+  if ((rc = ev_begin(c, &e1))) return rc;
+  c->ev_used.push_back({cls, {e0, e1}});
+  if (c->ev_used.size() > 4096) return collect_events(c);
+  return MLSWE_OK;
+}
+
 // ------------------------------------------------------------ launches
 // Sweeps over tile ranges of level l; rx / ry: the ranges are run tiles.
 int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, int nyt, bool rx = false,
@@ -888,7 +906,7 @@ int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
   if ((rc = build_launch(c, l))) return rc;
   if (l > 0 && (rc = build_launch(c, l - 1))) return rc;
   LevelLaunch& LL = c->launch[l];
-  if ((rc = launch_fill(c, l, p0, p1, theta))) return rc;
+  if ((rc = timed(c, 2, [&] { return launch_fill(c, l, p0, p1, theta); }))) return rc;
   const int parity = c->probs[p0].L[l].cur;
   for (int p = p0; p < p1; ++p)
     if (l < c->probs[p].nlev && c->probs[p].L[l].cur != parity)
@@ -933,8 +951,8 @@ int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
   if (c->cfg.reflux) {
     // face fluxes from this substep's sweep inputs (still intact): as the coarse
     // side of the finer level's faces, and as the fine side of this level's
-    if (l + 1 < MAXLEV && (rc = launch_reflux(c, l + 1, p0, p1, 0, parity))) return rc;
-    if (l >= 1 && (rc = launch_reflux(c, l, p0, p1, 1, parity))) return rc;
+    if (l + 1 < MAXLEV && (rc = timed(c, 5, [&] { return launch_reflux(c, l + 1, p0, p1, 0, parity); }))) return rc;
+    if (l >= 1 && (rc = timed(c, 5, [&] { return launch_reflux(c, l, p0, p1, 1, parity); }))) return rc;
   }
   for (int p = p0; p < p1; ++p) {
     ProblemH& P = c->probs[p];
@@ -943,7 +961,7 @@ int substep(mlswe_ctx* c, int l, int p0, int p1, double theta, bool batched) {
     L.cur = 1 - L.cur;
     for (const Box& bx : L.boxes) P.updates[l] += (long long)bx.nx * bx.ny;
   }
-  return launch_after(c, l, p0, p1, runs);
+  return timed(c, 3, [&] { return launch_after(c, l, p0, p1, runs); });
 }
 
 // apply_reflux: the coarsening ends a coarse level's substep inside a coarse
@@ -965,11 +983,16 @@ int coarsen_level(mlswe_ctx* c, int lf, int p0, int p1, bool apply_reflux = fals
   }
   if (count == 0) return MLSWE_OK;
   const int fpar = c->probs[p0].L[lf].cur, cpar = c->probs[p0].L[lf - 1].cur;
-  for (int k0 = 0; k0 < count; k0 += 65535)  // grid y is at most 65535
-    hipLaunchKernelGGL(k_coarsen, dim3((maxc + 255) / 256, (unsigned)std::min(65535, count - k0)), dim3(256), 0,
-                       c->stream, LL.cp[fpar * 2 + cpar] + first + k0);
-  HIPCHK(c, hipGetLastError());
-  return apply_reflux ? launch_reflux(c, lf, p0, p1, 2, cpar) : MLSWE_OK;
+  rc = timed(c, 4, [&]() -> int {
+    for (int k0 = 0; k0 < count; k0 += 65535)  // grid y is at most 65535
+      hipLaunchKernelGGL(k_coarsen, dim3((maxc + 255) / 256, (unsigned)std::min(65535, count - k0)), dim3(256), 0,
+                         c->stream, LL.cp[fpar * 2 + cpar] + first + k0);
+    HIPCHK(c, hipGetLastError());
+    return MLSWE_OK;
+  });
+  if (rc) return rc;
+  return apply_reflux && c->cfg.reflux ? timed(c, 5, [&] { return launch_reflux(c, lf, p0, p1, 2, cpar); })
+                                       : MLSWE_OK;
 }
 
 bool level_active(const mlswe_ctx* c, int l, int p0, int p1) {
@@ -1015,10 +1038,12 @@ int next_dt(mlswe_ctx* c, int p0, int p1, bool initial) {
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
-  hipLaunchKernelGGL(k_next_dt, dim3((p1 - p0 + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, p1 - p0,
-                     c->cfg.cfl_desired, initial ? 1 : 0);
-  HIPCHK(c, hipGetLastError());
-  return MLSWE_OK;
+  return timed(c, 6, [&]() -> int {
+    hipLaunchKernelGGL(k_next_dt, dim3((p1 - p0 + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, p1 - p0,
+                       c->cfg.cfl_desired, initial ? 1 : 0);
+    HIPCHK(c, hipGetLastError());
+    return MLSWE_OK;
+  });
 }
 
 // Control blocks of problems [p0, p1) (contiguous, problem-major) in one copy.
@@ -2112,8 +2137,14 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
   const int ngroups = together ? 1 : np;
   for (int n = 0; n < nsteps; ++n) {
     int rc;
-    if (regrid_every > 0 && n % regrid_every == 0)
+    if (regrid_every > 0 && n % regrid_every == 0) {
+      const auto t0 = std::chrono::steady_clock::now();
       if ((rc = regrid_group(c, 0, np, tau, nbuf))) return rc;
+      if (c->timing) {
+        c->kms[7] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        c->klaunch[7] += 1;
+      }
+    }
     if (c->cfg.dynamic_rt && (rc = choose_time_ratios(c))) return rc;
     if ((rc = build_pdt(c))) return rc;
     for (int gi = 0; gi < ngroups; ++gi) {
@@ -2172,9 +2203,16 @@ int mlswe_set_kernel_timing(mlswe_ctx* c, int enable) {
   int rc = collect_events(c);
   if (rc) return rc;
   c->timing = enable != 0;
-  c->kms[0] = c->kms[1] = 0.0;
-  c->klaunch[0] = c->klaunch[1] = 0;
+  for (int k = 0; k < 8; ++k) { c->kms[k] = 0.0; c->klaunch[k] = 0; }
   return MLSWE_OK;
+}
+
+int mlswe_phase_times(mlswe_ctx* c, double* ms_out, int64_t* counts_out, int cap) {
+  if (!c || cap < 0 || (cap > 0 && (!ms_out || !counts_out))) return MLSWE_EINVAL;
+  int rc = collect_events(c);
+  if (rc) return rc;
+  for (int k = 0; k < 8 && k < cap; ++k) { ms_out[k] = c->kms[k]; counts_out[k] = c->klaunch[k]; }
+  return 8;
 }
 
 int mlswe_kernel_times(mlswe_ctx* c, double* ms_out, int64_t* launches_out) {
