@@ -64,7 +64,8 @@ typedef struct mlswe_config {
                          level's fine substeps and coarsening, each
                          coarse cell beside a fine patch has the coarse mass flux
                          through the shared face replaced by the fine fluxes summed
-                         over the face's fine faces and substeps (divided by r^2),
+                         over the face's r fine faces and the fine substeps (divided
+                         by r times the number of substeps),
                          so each layer's mass on the composite grid changes only by
                          clipping; 0 (default): off */
   int dynamic_rt;     /* 1: time-refinement ratios chosen per coarse step (Sec. 2,
