@@ -67,6 +67,10 @@ struct ProblemH {
   int nlev = 1;
   int ratio[MAXLEV] = {0};
   int rt[MAXLEV] = {0};  // time ratios of the current coarse step (the space ratios unless chosen)
+  // largest speeds of the last coarse step as read back after its Courant
+  // check (valid until the device copies may have changed)
+  unsigned long long last_acc[MAXLEV][2] = {};
+  bool acc_known = false;
   LevelH L[MAXLEV];
   int ctl0 = 0;  // index of level 0's LevelCtl
   int cnt = 0;   // index of the problem's counters
@@ -1653,6 +1657,7 @@ int mlswe_set_step_state(mlswe_ctx* c, int p, const double* in) {
   HIPCHK(c, hipMemcpyAsync(c->ctl + P.ctl0, h.data(), sizeof(LevelCtl) * h.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   P.have_dt = in[1] != 0.0;
+  P.acc_known = false;
   return MLSWE_OK;
 }
 
@@ -1681,6 +1686,7 @@ int mlswe_get_state(mlswe_ctx* c, int p, int level, double* q, int where) {
 int mlswe_step_level(mlswe_ctx* c, int level, const double* dt, double theta, double* smax_out) {
   if (!c) return MLSWE_EINVAL;
   if (c->probs.empty()) return fail(c, MLSWE_ESTATE, "no problem defined");
+  for (ProblemH& P : c->probs) P.acc_known = false;  // the substep adds to the device speeds
   const int np = (int)c->probs.size();
   for (int p = 0; p < np; ++p) {
     const ProblemH& P = c->probs[p];
@@ -1818,7 +1824,9 @@ int choose_time_ratios(mlswe_ctx* c) {
   const int np = (int)c->probs.size();
   std::vector<LevelCtl> h;
   int rc;
-  if ((rc = read_ctls(c, 0, np, h))) return rc;
+  bool cached = true;  // speeds already read back after the last step's Courant check
+  for (int p = 0; p < np; ++p) cached = cached && c->probs[p].acc_known;
+  if (!cached && (rc = read_ctls(c, 0, np, h))) return rc;
   const int base = c->probs[0].ctl0;
   const double inf = std::numeric_limits<double>::infinity();
   int RT[MAXLEV] = {0};
@@ -1830,10 +1838,11 @@ int choose_time_ratios(mlswe_ctx* c) {
       double a[MAXLEV], A[MAXLEV];
       double best = inf, fac = 1.0;
       for (int l = 0; l < P.nlev; ++l) {
-        const LevelCtl& C = h[(size_t)(P.ctl0 - base + l)];
+        const unsigned long long bx = cached ? P.last_acc[l][0] : h[(size_t)(P.ctl0 - base + l)].acc_smax[0];
+        const unsigned long long by = cached ? P.last_acc[l][1] : h[(size_t)(P.ctl0 - base + l)].acc_smax[1];
         if (l > 0) fac *= (double)P.ratio[l - 1];
-        const double sx = __builtin_bit_cast(double, (long long)C.acc_smax[0]);
-        const double sy = __builtin_bit_cast(double, (long long)C.acc_smax[1]);
+        const double sx = __builtin_bit_cast(double, (long long)bx);
+        const double sy = __builtin_bit_cast(double, (long long)by);
         const double ax = sx > 0.0 ? P.L[l].dx / sx : inf;
         const double ay = sy > 0.0 ? P.L[l].dy / sy : inf;
         const double m = ax < ay ? ax : ay;
@@ -1858,6 +1867,7 @@ int choose_time_ratios(mlswe_ctx* c) {
   }
   for (int p = 0; p < np; ++p) {
     ProblemH& P = c->probs[p];
+    P.acc_known = false;  // consumed: the coming step replaces the speeds
     for (int l = 0; l + 1 < P.nlev; ++l) {
       const int v = std::min(RT[l], P.ratio[l]);
       if (v != P.rt[l]) { P.rt[l] = v; c->pdt_dirty = true; }
@@ -2089,7 +2099,17 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
         dt0[p - p0] = dtp;
       }
     }
-    if (!any) return MLSWE_OK;
+    if (!any) {
+      for (int p = p0; p < p1; ++p) {
+        ProblemH& P = c->probs[p];
+        for (int l = 0; l < P.nlev; ++l) {
+          P.last_acc[l][0] = h[P.ctl0 + l].acc_smax[0];
+          P.last_acc[l][1] = h[P.ctl0 + l].acc_smax[1];
+        }
+        P.acc_known = true;
+      }
+      return MLSWE_OK;
+    }
     if (attempt + 1 > c->cfg.max_retries) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
     // put the group back
     size_t k = 0;
@@ -2521,6 +2541,7 @@ extern "C" int mlswe_autotune(mlswe_ctx* c, const char* cache_path, int reps) {
   for (const ProblemH& P : c->probs)
     if (!P.bathy || !P.state) return fail(c, MLSWE_ESTATE, "problems must be initialised before tuning");
   if (reps <= 0) reps = 3;
+  for (ProblemH& P : c->probs) P.acc_known = false;  // timed sweeps run on the device copies
   const std::string key = layout_key(c);
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "r");
