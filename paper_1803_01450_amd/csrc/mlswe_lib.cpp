@@ -836,11 +836,16 @@ int launch_fill(mlswe_ctx* c, int l, int p0, int p1, double theta) {
   const int fpar = P0.L[l].cur;
   const int cpar = l > 0 ? P0.L[l - 1].cur : 0;
   int first = -1, count = 0, maxring = 0;
+  bool walls = false;  // some patch's two-cell frame leaves the domain
   for (int p = p0; p < p1; ++p) {
     if (LL.fill_first[p] < 0) continue;
     if (first < 0) first = LL.fill_first[p];
     count = LL.fill_first[p] + LL.fill_count[p] - first;
-    for (const Box& b : c->probs[p].L[l].boxes) maxring = std::max(maxring, 4 * (b.nx + 4) + 4 * b.ny);
+    const LevelH& L = c->probs[p].L[l];
+    for (const Box& b : L.boxes) {
+      maxring = std::max(maxring, 4 * (b.nx + 4) + 4 * b.ny);
+      walls = walls || b.ilo < 2 || b.jlo < 2 || b.ilo + b.nx > L.nx - 2 || b.jlo + b.ny > L.ny - 2;
+    }
   }
   if (count == 0) return MLSWE_OK;
   const FillPatch* f = LL.fp[fpar * 2 + cpar] + first;
@@ -848,8 +853,11 @@ int launch_fill(mlswe_ctx* c, int l, int p0, int p1, double theta) {
     hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 0, theta);
     HIPCHK(c, hipGetLastError());
   }
-  hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 1, theta);
-  HIPCHK(c, hipGetLastError());
+  // the second pass only mirrors frame cells outside the domain
+  if (walls) {
+    hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 1, theta);
+    HIPCHK(c, hipGetLastError());
+  }
   return MLSWE_OK;
 }
 
