@@ -76,7 +76,9 @@ typedef struct mlswe_config {
                          level able to meet its own with full ratios; in a context
                          of several problems each level takes the largest number
                          any problem needs (so all launch modes agree); the first
-                         step of a problem uses the space ratios.  0 (default):
+                         step of a problem uses the space ratios, and so does a
+                         step in which a level holds patches but has no speeds of
+                         the last one (a level a regrid has just populated).  0 (default):
                          time ratio = space ratio */
   int pad_;
 } mlswe_config;

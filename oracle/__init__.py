@@ -14,6 +14,7 @@ it); the readings used are stated in the comments of ``ora_core.hpp``.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -53,50 +54,90 @@ _DP = ctypes.POINTER(ctypes.c_double)
 _IP = ctypes.POINTER(ctypes.c_int)
 
 
+def _configure(L):
+    L.ora_create.restype = _P
+    L.ora_create.argtypes = [_D, _D, _D, _D, _D, _D, _I, _IP, _I, _I, _D, _D]
+    L.ora_destroy.argtypes = [_P]
+    for name in ["ora_set_bathymetry"]:
+        getattr(L, name).argtypes = [_P, _DP]
+    L.ora_get_bathymetry.argtypes = [_P, _I, _DP]
+    L.ora_get_step_state.argtypes = [_P, _DP]
+    L.ora_set_reflux.argtypes = [_P, _I]
+    L.ora_set_dynamic_rt.argtypes = [_P, _I]
+    L.ora_get_rt.argtypes = [_P, _IP]
+    L.ora_set_step_state.argtypes = [_P, _DP]
+    L.ora_set_state.argtypes = [_P, _I, _DP]
+    L.ora_get_state.argtypes = [_P, _I, _DP]
+    L.ora_level_shape.argtypes = [_P, _I, _IP, _IP, _DP, _DP]
+    L.ora_set_patches.argtypes = [_P, _I, _I, _IP]
+    L.ora_get_npatches.argtypes = [_P, _I]
+    L.ora_get_patches.argtypes = [_P, _I, _IP]
+    L.ora_step_level.argtypes = [_P, _I, _D, _D, _DP]
+    L.ora_coarsen.argtypes = [_P, _I]
+    L.ora_flag.argtypes = [_P, _I, _D, _I, ctypes.POINTER(ctypes.c_ubyte)]
+    L.ora_cluster.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_ubyte), _IP, _I]
+    L.ora_regrid.argtypes = [_P, _DP, _I]
+    L.ora_advance.argtypes = [_P, _I, _I, _DP, _I, _DP]
+    L.ora_next_dt.restype = _D
+    L.ora_next_dt.argtypes = [_P]
+    L.ora_counters.argtypes = [_P, _DP]
+    L.ora_refine_point.argtypes = [_D, _I, _I, _I, _DP, _I, _I, _D, _DP]
+    L.ora_riemann.argtypes = [_D, _D, _D, _D, _DP, _DP, _DP, _DP, _IP, _DP, _DP]
+    L.ora_fixed_steps.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _I, _DP, _DP, _DP]
+    L.ora_time_fixed.restype = _D
+    L.ora_time_fixed.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _I, _D, _DP]
+    L.ora_count_ops.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _D,
+                                ctypes.POINTER(ctypes.c_longlong)]
+    L.ora_step_window.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _IP, _D, _DP, _DP]
+    L.ora_gauge_loss.restype = _D
+    L.ora_gauge_loss.argtypes = [_I, _D, _D, _D, _D, _D, _DP, _DP, _D, _I, _DP, _I, _I, _I, _I,
+                                 _DP, _DP, _DP, _DP]
+    L.ora_set_retries.argtypes = [_P, _I]
+    L.ora_ghost_fill.argtypes = [_P, _I, _D]
+    L.ora_get_level_raw.argtypes = [_P, _I, _I, _DP]
+    L.ora_mc_limiter.restype = _D
+    L.ora_mc_limiter.argtypes = [_D]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(_LIB)
-        L.ora_create.restype = _P
-        L.ora_create.argtypes = [_D, _D, _D, _D, _D, _D, _I, _IP, _I, _I, _D, _D]
-        L.ora_destroy.argtypes = [_P]
-        for name in ["ora_set_bathymetry"]:
-            getattr(L, name).argtypes = [_P, _DP]
-        L.ora_get_bathymetry.argtypes = [_P, _I, _DP]
-        L.ora_get_step_state.argtypes = [_P, _DP]
-        L.ora_set_reflux.argtypes = [_P, _I]
-        L.ora_set_dynamic_rt.argtypes = [_P, _I]
-        L.ora_get_rt.argtypes = [_P, _IP]
-        L.ora_set_step_state.argtypes = [_P, _DP]
-        L.ora_set_state.argtypes = [_P, _I, _DP]
-        L.ora_get_state.argtypes = [_P, _I, _DP]
-        L.ora_level_shape.argtypes = [_P, _I, _IP, _IP, _DP, _DP]
-        L.ora_set_patches.argtypes = [_P, _I, _I, _IP]
-        L.ora_get_npatches.argtypes = [_P, _I]
-        L.ora_get_patches.argtypes = [_P, _I, _IP]
-        L.ora_step_level.argtypes = [_P, _I, _D, _D, _DP]
-        L.ora_coarsen.argtypes = [_P, _I]
-        L.ora_flag.argtypes = [_P, _I, _D, _I, ctypes.POINTER(ctypes.c_ubyte)]
-        L.ora_cluster.argtypes = [_P, _I, ctypes.POINTER(ctypes.c_ubyte), _IP, _I]
-        L.ora_regrid.argtypes = [_P, _DP, _I]
-        L.ora_advance.argtypes = [_P, _I, _I, _DP, _I, _DP]
-        L.ora_next_dt.restype = _D
-        L.ora_next_dt.argtypes = [_P]
-        L.ora_counters.argtypes = [_P, _DP]
-        L.ora_refine_point.argtypes = [_D, _I, _I, _I, _DP, _I, _I, _D, _DP]
-        L.ora_riemann.argtypes = [_D, _D, _D, _D, _DP, _DP, _DP, _DP, _IP, _DP, _DP]
-        L.ora_fixed_steps.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _I, _DP, _DP, _DP]
-        L.ora_time_fixed.restype = _D
-        L.ora_time_fixed.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _I, _D, _DP]
-        L.ora_count_ops.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _D,
-                                    ctypes.POINTER(ctypes.c_longlong)]
-        L.ora_step_window.argtypes = [_I, _I, _D, _D, _D, _D, _D, _D, _DP, _DP, _IP, _D, _DP, _DP]
-        L.ora_gauge_loss.restype = _D
-        L.ora_gauge_loss.argtypes = [_I, _D, _D, _D, _D, _D, _DP, _DP, _D, _I, _DP, _I, _I, _I, _I,
-                                     _DP, _DP, _DP, _DP]
-        _lib = L
+        _lib = _configure(ctypes.CDLL(_LIB))
     return _lib
+
+
+@contextlib.contextmanager
+def variant(path):
+    """Runs the oracle's Python helpers against another build of the oracle
+    (the mutation tests plant a slip in a copy of the sources)."""
+    global _lib
+    saved = lib()
+    _lib = _configure(ctypes.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def sources():
+    """Paths of the oracle's C++ sources and header (for rebuilding a copy)."""
+    return [os.path.join(_HERE, s) for s in _SRCS] + [os.path.join(_HERE, "ora_core.hpp")]
+
+
+def compile_to(srcdir, out):
+    """Compiles the oracle sources found in srcdir into the library out, with
+    the flags of build()."""
+    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", out] + [os.path.join(srcdir, s) for s in _SRCS]
+    subprocess.check_call(cmd)
+    return out
+
+
+def mc_limiter(theta):
+    """The oracle's limiter function phi(theta)."""
+    return lib().ora_mc_limiter(float(theta))
 
 
 def _dp(a):
@@ -319,6 +360,23 @@ class Hierarchy:
         v = _f64(v)
         assert v.shape == (2 + 2 * self.nlev,)
         lib().ora_set_step_state(self.h, _dp(v))
+
+    def set_retries(self, n):
+        """Rejected coarse steps are retaken at most n times (default 8)."""
+        lib().ora_set_retries(self.h, int(n))
+
+    def ghost_fill(self, l, theta):
+        """Fills the frame cells of level l's patches at time fraction theta of
+        the coarser level's last step (as a substep of level l does first)."""
+        lib().ora_ghost_fill(self.h, l, float(theta))
+
+    def level_raw(self, l, which=0):
+        """Level l's buffer with its two-cell frame, [6][ny + 4][nx + 4];
+        which = 1: the state before the level's last step."""
+        nx, ny = self.shapes[l][:2]
+        q = np.zeros((6, ny + 4, nx + 4))
+        lib().ora_get_level_raw(self.h, l, int(which), _dp(q))
+        return q
 
     def counters(self):
         c = np.zeros(15)

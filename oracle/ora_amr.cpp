@@ -559,6 +559,12 @@ static void reflux_apply(Hier& H, int l, const std::vector<RefluxCell>& cells, d
 static void choose_rt(Hier& H, double dt) {
   for (int l = 0; l + 1 < H.nlev; ++l) H.rt[l] = H.ratio[l];
   if (!H.dyn_rt || !H.have_smax) return;
+  // A level with patches but no speeds of the last coarse step (one a regrid
+  // has just populated) has no Courant bound of its own: then every level keeps
+  // its space ratio, as on the first step, so that the new level's substep is
+  // no longer than with fixed ratios.
+  for (int l = 1; l < H.nlev; ++l)
+    if (!H.L[l].boxes.empty() && !(H.L[l].smax[0] > 0.0) && !(H.L[l].smax[1] > 0.0)) return;
   const double inf = std::numeric_limits<double>::infinity();
   double A[8];
   for (int l = H.nlev - 1; l >= 0; --l) {
@@ -794,6 +800,22 @@ double ora_next_dt(void* h) { return next_dt(*static_cast<Hier*>(h)); }
 void ora_set_reflux(void* h, int on) { static_cast<Hier*>(h)->reflux = on != 0; }
 
 void ora_set_dynamic_rt(void* h, int on) { static_cast<Hier*>(h)->dyn_rt = on != 0; }
+
+// Rejected coarse steps are retaken at most n times (n < 0: never).
+void ora_set_retries(void* h, int n) { static_cast<Hier*>(h)->retries = n < 0 ? 0 : n; }
+
+// Test hooks: the ghost fill of level l at time fraction th on its own, and a
+// level's raw buffers with their frames (which = 0: current, 1: the other one,
+// i.e. the state before the level's last step), [6][ny + 4][nx + 4].
+void ora_ghost_fill(void* h, int l, double th) { ghost_fill(*static_cast<Hier*>(h), l, th); }
+
+void ora_get_level_raw(void* h, int l, int which, double* out) {
+  const Level& L = static_cast<Hier*>(h)->L[l];
+  const std::vector<double>& q = L.q[which ? 1 - L.cur : L.cur];
+  std::copy(q.begin(), q.end(), out);
+}
+
+double ora_mc_limiter(double th) { return mc_limiter<double>(th); }
 
 // Time ratios of the last coarse step: out[nlev - 1].
 void ora_get_rt(void* h, int* out) {

@@ -18,7 +18,9 @@ from . import binding
 
 
 def _vp(t):
-    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    """Device pointer of a contiguous float64 GPU tensor (MlsweError otherwise)."""
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise binding.MlsweError(-1, "expected a contiguous float64 device tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -39,6 +41,13 @@ class MisfitProblem:
         self.ckpt = int(ckpt)
         nx, ny = solver.shapes[p][0][:2]
         self.nx, self.ny = nx, ny
+        self._pool = None  # states of one recomputed segment, allocated once
+
+    def _buffers(self):
+        if self._pool is None:
+            self._pool = [torch.empty((6, self.ny, self.nx), dtype=torch.float64, device="cuda")
+                          for _ in range(self.ckpt)]
+        return self._pool
 
     def _check(self, rc):
         self.S._check(rc)
@@ -49,8 +58,8 @@ class MisfitProblem:
             self._check(self.L.mlswe_run_fixed(self.S.h, self.p, s1 - s0,
                                                d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
-    def _state(self):
-        q = torch.empty((6, self.ny, self.nx), dtype=torch.float64, device="cuda")
+    def _state(self, out=None):
+        q = out if out is not None else torch.empty((6, self.ny, self.nx), dtype=torch.float64, device="cuda")
         self._check(self.L.mlswe_get_state(self.S.h, self.p, 0, _vp(q), binding.DEVICE))
         return q
 
@@ -67,6 +76,8 @@ class MisfitProblem:
 
     def forward(self, eta1_0, B):
         """Loss (device scalar tensor) and the checkpoints of the run."""
+        _vp(eta1_0)
+        _vp(B)
         self.S.set_bathymetry(self.p, B)
         q0 = torch.empty((6, self.ny, self.nx), dtype=torch.float64, device="cuda")
         self._check(self.L.mlswe_param_map(self.S.h, self.p, _vp(eta1_0), self.eta2, _vp(q0)))
@@ -94,10 +105,11 @@ class MisfitProblem:
         for seg in reversed(range(nseg)):
             s0, s1 = seg * self.ckpt, min(n, (seg + 1) * self.ckpt)
             self._set_state(ckpts[seg])
+            pool = self._buffers()
             states = [ckpts[seg]]
             for s in range(s0, s1):
                 self._run(s, s + 1)
-                states.append(self._state())
+                states.append(self._state(pool[s - s0]))
             for s in reversed(range(s0, s1)):
                 if (s + 1) % self.every == 0:
                     self._gauge((s + 1) // self.every - 1, states[s + 1 - s0], lam=lam, Bbar=Bbar)

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -131,16 +132,29 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def _ptr(a):
-    """(pointer, where) of a numpy array or a torch tensor (device pointers of
-    CUDA/HIP tensors are passed as device memory)."""
+def _ptr(a, shape, device=None):
+    """(pointer, where) of a numpy array or a torch tensor holding exactly
+    `shape` float64 values contiguously (device pointers of GPU tensors are
+    passed as device memory; they must live on the context's GPU `device`).
+    Anything else raises MlsweError(EINVAL) before the library reads it."""
+    shape = tuple(int(v) for v in shape)
     if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise MlsweError(-1, "expected a contiguous float64 array, got %s" % a.dtype)
+        if a.shape != shape:
+            raise MlsweError(-1, "array of shape %s, expected %s" % (a.shape, shape))
         return a.ctypes.data_as(ctypes.c_void_p), HOST
     if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if str(a.dtype) != "torch.float64" or not a.is_contiguous():
+            raise MlsweError(-1, "expected a contiguous float64 tensor, got %s" % a.dtype)
+        if tuple(a.shape) != shape:
+            raise MlsweError(-1, "tensor of shape %s, expected %s" % (tuple(a.shape), shape))
         if a.is_cuda:
+            if device is not None and a.device.index != device:
+                raise MlsweError(-1, "tensor on cuda:%s, the context runs on cuda:%d" % (a.device.index, device))
             return ctypes.c_void_p(a.data_ptr()), DEVICE
         return ctypes.c_void_p(a.data_ptr()), HOST
-    raise TypeError("expected a numpy array or a torch tensor")
+    raise MlsweError(-1, "expected a numpy array or a torch tensor")
 
 
 class Solver:
@@ -157,6 +171,11 @@ class Solver:
             raise MlsweError(rc, "mlswe_create failed (no usable GPU?)")
         self.h = h
         self.shapes = []   # per problem: list of (nx, ny, dx, dy)
+        self.dev = None
+        if "torch" in sys.modules:
+            import torch
+            if torch.cuda.is_available():
+                self.dev = torch.cuda.current_device()
 
     def close(self):
         if getattr(self, "h", None):
@@ -186,10 +205,19 @@ class Solver:
         self.shapes.append(shp)
         return p.value
 
+    def _device(self):
+        """Index of the GPU the context was created on (torch's numbering)."""
+        if self.dev is None and "torch" in sys.modules:
+            import torch
+            if torch.cuda.is_available():
+                self.dev = torch.cuda.current_device()
+        return self.dev
+
     def set_bathymetry(self, p, Bf):
         if isinstance(Bf, np.ndarray):
             Bf = _f64(Bf)
-        ptr, where = _ptr(Bf)
+        nx, ny = self.shapes[p][-1][:2]
+        ptr, where = _ptr(Bf, (ny, nx), self._device())
         self._check(self.L.mlswe_set_bathymetry(self.h, p, ptr, where))
 
     def set_patches(self, p, level, boxes):
@@ -214,9 +242,8 @@ class Solver:
     def set_state(self, p, level, q):
         if isinstance(q, np.ndarray):
             q = _f64(q)
-            nx, ny = self.shapes[p][level][:2]
-            assert q.shape == (6, ny, nx), q.shape
-        ptr, where = _ptr(q)
+        nx, ny = self.shapes[p][level][:2]
+        ptr, where = _ptr(q, (6, ny, nx), self._device())
         self._check(self.L.mlswe_set_state(self.h, p, level, ptr, where))
 
     def state(self, p, level):
@@ -352,11 +379,9 @@ class Solver:
 
     # ------------------------------------------------------------ M layers
     def _dev(self, t, shape):
-        if not (hasattr(t, "is_cuda") and t.is_cuda) or not t.is_contiguous() or str(t.dtype) != "torch.float64":
-            raise TypeError("expected a contiguous float64 device tensor")
-        if tuple(t.shape) != tuple(shape):
-            raise ValueError("shape %s, expected %s" % (tuple(t.shape), tuple(shape)))
-        return ctypes.c_void_p(t.data_ptr())
+        if not (hasattr(t, "is_cuda") and t.is_cuda):
+            raise MlsweError(-1, "expected a float64 device tensor")
+        return _ptr(t, shape, self._device())[0]
 
     def refine_layers(self, qc, Bc, Bf, qf, r, box=None, want_repairs=False):
         """Fine cells of box (fi0, fj0, fnx, fny) (default: the whole fine grid)

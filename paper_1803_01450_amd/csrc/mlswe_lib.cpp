@@ -1826,7 +1826,8 @@ namespace {
 // sx, dy / sy) (infinite without speeds), A_l = min(a_l, r_l A_{l+1}) from the
 // finest level up and dt0 the coming coarse step (the dt rule's value), level
 // l takes ceil(dt_{l-1} / A_l) substeps, clipped to [1, r]; a problem without
-// speeds takes the space ratios.  Each level then takes the largest number any
+// speeds, or with a populated level that has none (new since the last step),
+// takes the space ratios.  Each level then takes the largest number any
 // problem takes (clipped to each problem's ratio).
 int choose_time_ratios(mlswe_ctx* c) {
   const int np = (int)c->probs.size();
@@ -1842,7 +1843,18 @@ int choose_time_ratios(mlswe_ctx* c) {
     const ProblemH& P = c->probs[p];
     int k[MAXLEV];
     for (int l = 0; l + 1 < P.nlev; ++l) k[l] = P.ratio[l];
-    if (P.have_dt) {
+    // a level with patches but no speeds of the last coarse step (just
+    // populated by a regrid) has no Courant bound of its own: the problem then
+    // keeps its space ratios, as on its first step
+    bool fresh = false;
+    for (int l = 1; l < P.nlev && P.have_dt; ++l) {
+      const unsigned long long bx = cached ? P.last_acc[l][0] : h[(size_t)(P.ctl0 - base + l)].acc_smax[0];
+      const unsigned long long by = cached ? P.last_acc[l][1] : h[(size_t)(P.ctl0 - base + l)].acc_smax[1];
+      const double sx = __builtin_bit_cast(double, (long long)bx);
+      const double sy = __builtin_bit_cast(double, (long long)by);
+      if (!P.L[l].boxes.empty() && !(sx > 0.0) && !(sy > 0.0)) fresh = true;
+    }
+    if (P.have_dt && !fresh) {
       double a[MAXLEV], A[MAXLEV];
       double best = inf, fac = 1.0;
       for (int l = 0; l < P.nlev; ++l) {

@@ -166,3 +166,42 @@ def test_batch_of_problems_with_both_options_all_modes_agree():
         for a, b in zip(out[0][1], out[m][1]):
             assert np.array_equal(a[0], b[0], equal_nan=True) and np.array_equal(a[1], b[1], equal_nan=True)
             assert np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_newly_populated_level_takes_the_space_ratio(mode):
+    """A fine level that gets its first patches after two coarse steps (deep
+    water: one substep per coarse step would give a fine Courant number near
+    3.6) keeps the space ratio on its first step, with no retake allowed: no
+    rejection, no error, ratios, dts and states equal to the oracle's."""
+    from paper_1803_01450_amd.binding import Solver
+    say("case: dynamic time ratio, level populated mid-run, mode %d" % mode)
+    c = inputs.fixed_small()
+    box = (16, 64, 32, 64)
+    S = Solver(dynamic_rt=True, max_retries=-1)
+    p = S.define(64, 64, c["dx"], c["dx"], c["r"], (4,))
+    S.set_bathymetry(p, np.kron(c["B"], np.ones((4, 4)))); S.set_state(p, 0, c["q"])
+    S.set_patches(p, 1, [])
+    S.advance(2, mode=mode)
+    S.refine(p, 1, [box])
+    rts, dts = [], []
+    for _ in range(3):
+        dts.append(S.advance(1, mode=mode, want_dts=True)[0][0])
+        rts.append(int(S.time_ratios(p)[0]))
+    H = oracle.Hierarchy(64, 64, c["dx"], c["dx"], ratios=(4,), r=c["r"])
+    H.set_dynamic_rt(True); H.set_retries(0)
+    H.set_bathymetry(np.kron(c["B"], np.ones((4, 4)))); H.set_state(0, c["q"])
+    H.set_patches(1, [])
+    assert H.advance(2)[0] == 0
+    H.set_patches(1, [box])
+    ro, do = [], []
+    for _ in range(3):
+        rc, d = H.advance(1)
+        assert rc == 0
+        ro.append(int(H.time_ratios()[0])); do.append(d[0])
+    say("ratios", rts, ro)
+    assert rts == ro and rts[0] == 4
+    assert np.array_equal(np.array(dts), np.array(do))
+    assert S.counters(p)["rejected"] == 0
+    for l in range(2):
+        assert np.array_equal(S.state(p, l), H.state(l), equal_nan=True), l

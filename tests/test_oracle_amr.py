@@ -414,3 +414,27 @@ def test_dynamic_time_ratio_with_flux_correction_conserves_mass():
     assert rc == 0 and int(H.time_ratios()[0]) == 3
     drift = np.abs(_composite_mass(H, 2, (4,), c["dx"]) - m0) / m0
     assert np.all(drift <= 1e-14), drift
+
+
+def test_dynamic_time_ratio_for_a_newly_populated_level():
+    """A fine level that receives its first patches mid-run has no speeds of
+    the last coarse step: it takes the space ratio (as on a first step), so its
+    substeps stay within the Courant limit; with no retakes allowed the run
+    neither rejects a step nor fails.  Deep water under the patch: one substep
+    per coarse step would give a fine Courant number near 3.6."""
+    c = inputs.fixed_small()
+    H = oracle.Hierarchy(64, 64, c["dx"], c["dx"], ratios=(4,), r=c["r"])
+    H.set_dynamic_rt(True)
+    H.set_retries(0)
+    H.set_bathymetry(np.kron(c["B"], np.ones((4, 4)))); H.set_state(0, c["q"])
+    H.set_patches(1, [])
+    rc, _ = H.advance(2)
+    assert rc == 0
+    H.set_patches(1, [(16, 64, 32, 64)])
+    rts = []
+    for _ in range(3):
+        rc, _ = H.advance(1)
+        assert rc == 0
+        rts.append(int(H.time_ratios()[0]))
+    assert rts[0] == 4
+    assert H.counters()["rejected"] == 0
