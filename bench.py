@@ -10,7 +10,8 @@ Prints one JSON line (rank 0, N = 1):
   value        cell updates per second (interior cells x steps / seconds)
   roofline     the dominant kernel's algorithmic bytes per launch over its
                average HIP-event duration, against 8 TB/s
-  cpu_baseline the FP64 oracle on the host, single thread, on a bounded sample
+  cpu_baseline the FP64 oracle on the host on a bounded sample: all threads of
+               the process's share (value) and one thread
 """
 from __future__ import annotations
 
@@ -41,7 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=4096, help="grid cells per side")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps of the full grid")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps of the full grid, one thread")
+    ap.add_argument("--cpu-mt-steps", type=int, default=8, help="oracle steps of the full grid, all threads")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--y-rows", type=int, default=0)
@@ -352,6 +354,45 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
 
 
+def host_cpu():
+    """(host threads this process may use, capped at the 16 of one GPU's share;
+    the CPU model from /proc/cpuinfo; nproc)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(16, n), model, n
+
+
+def cpu_baseline(c, steps1, steps_mt):
+    """The oracle timed on the host on full-size steps of the same grid, in the
+    paper's two modes (Sec. 3, Table 1: one thread and several): one thread,
+    and all threads of this process's share (rows cut into strips stepped as
+    boxes, bit-identical results).  The reported value is the all-threads one."""
+    import numpy as np
+    import oracle
+    threads, model, nproc = host_cpu()
+    n = c["n"]
+    dt = 0.9 * c["dx"] / np.sqrt(9.81 * 4000.0)
+    print("bench: oracle CPU baseline, 1 thread, %d steps" % steps1, file=sys.stderr, flush=True)
+    r1, s1 = oracle.time_fixed(c["B"], c["q"], c["dx"], c["dx"], steps1, dt, r=c["r"])
+    print("bench: oracle CPU baseline, %d threads, %d steps" % (threads, steps_mt), file=sys.stderr, flush=True)
+    rm, sm = oracle.time_fixed_mt(c["B"], c["q"], c["dx"], c["dx"], steps_mt, dt, threads, r=c["r"])
+    return {"value": rm, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d steps of the full %dx%d grid on %d threads (%.1f s)" % (steps_mt, n, n, threads, sm),
+            "single_thread": {"value": r1, "cores": 1,
+                              "sample": "%d steps of the full %dx%d grid (%.1f s)" % (steps1, n, n, s1)},
+            "cpu_model": model, "nproc": nproc}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -478,13 +519,7 @@ def main():
         "fast": fast,
     }
     if not args.no_cpu:
-        import oracle
-        print("bench: oracle CPU baseline (%d steps of the full grid, 1 thread)" % args.cpu_steps,
-              file=sys.stderr, flush=True)
-        dt = 0.9 * c["dx"] / np.sqrt(9.81 * 4000.0)
-        crate, sec = oracle.time_fixed(c["B"], c["q"], c["dx"], c["dx"], args.cpu_steps, dt, r=c["r"])
-        out["cpu_baseline"] = {"value": crate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d steps of the full %dx%d grid (%.1f s)" % (args.cpu_steps, n, n, sec)}
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_steps, args.cpu_mt_steps)
     S.close()
     if not args.no_extras:
         st = stream.cuda_stream

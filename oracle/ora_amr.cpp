@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cstdio>
 #include <limits>
+#include <thread>
 
 namespace ora {
 
@@ -951,6 +952,51 @@ double ora_time_fixed(int nx, int ny, double dx, double dy, double g, double r, 
   auto t1 = std::chrono::steady_clock::now();
   double sec = std::chrono::duration<double>(t1 - t0).count();
   if (seconds) *seconds = sec;
+  return double(nx) * ny * nsteps / sec;
+}
+
+// The same stepping with nthreads host threads, the paper's multi-threaded
+// mode (Sec. 3 times its runs with one and with four threads): each step cuts
+// the level into nthreads strips of whole rows and steps every strip as a box
+// of its own on its own thread (frame rows come from the neighbouring strips of
+// the full state, as for any patch), so the results are those of the one-box
+// step bit for bit.  q_out (nullable, [6][ny][nx]) receives the final state.
+double ora_time_fixed_mt(int nx, int ny, double dx, double dy, double g, double r, double hdry, double kmin,
+                         const double* Bi, const double* q0, int nsteps, double dt, int nthreads, double* seconds,
+                         double* q_out) {
+  Params P = make_params(g, r, hdry, kmin);
+  Grid G; G.nx = nx; G.ny = ny;
+  const size_t pl = G.plane();
+  std::vector<double> a(6 * pl, 0.0), b(6 * pl, 0.0), B(pl, 0.0);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      B[G.idx(i, j)] = Bi[size_t(j) * nx + i];
+      for (int c = 0; c < 6; ++c) a[c * pl + G.idx(i, j)] = q0[(size_t(c) * ny + j) * nx + i];
+    }
+  wall_fill_B(G, B.data());
+  const int nt = std::max(1, std::min(nthreads, ny));
+  std::vector<Counters> C(nt);
+  auto t0 = std::chrono::steady_clock::now();
+  for (int n = 0; n < nsteps; ++n) {
+    wall_fill_all(G, a.data());
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t) {
+      const int j0 = int((long long)ny * t / nt), j1 = int((long long)ny * (t + 1) / nt);
+      pool.emplace_back([&, t, j0, j1] {
+        double s[2];
+        step_box(P, G, a.data(), B.data(), Box{0, j0, nx, j1 - j0}, dx, dy, dt, b.data(), s, C[t]);
+      });
+    }
+    for (std::thread& th : pool) th.join();
+    std::swap(a, b);
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  double sec = std::chrono::duration<double>(t1 - t0).count();
+  if (seconds) *seconds = sec;
+  if (q_out)
+    for (int c = 0; c < 6; ++c)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) q_out[(size_t(c) * ny + j) * nx + i] = a[c * pl + G.idx(i, j)];
   return double(nx) * ny * nsteps / sec;
 }
 
