@@ -189,6 +189,20 @@ int mlswe_coarsen(mlswe_ctx* ctx, int p, int fine_level);
  * tau, dilated by nbuf cells within the level's coverage.  Synchronises. */
 int mlswe_flag(mlswe_ctx* ctx, int p, int level, double tau, int nbuf, uint8_t* flags_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the flags of
+ * mlswe_flag, written to flags_dev (device memory of the context's GPU, ny_l x
+ * nx_l bytes, caller-owned) in the order of the context's stream, without
+ * synchronising and without allocating.  The undilated flags are staged in a
+ * device array of MLSWE_NOALLOC_SCRATCH_BYTES that the library holds once per
+ * GPU until the process ends (its address resolved by mlswe_create); every
+ * call on one GPU shares it, so calls that overlap on one GPU (two streams or
+ * two threads) race.  Errors: MLSWE_EINVAL (bad problem or level, nbuf < 0,
+ * null flags_dev, a level of more than MLSWE_NOALLOC_SCRATCH_BYTES cells),
+ * MLSWE_EDEVICE. */
+#define MLSWE_NOALLOC_SCRATCH_BYTES (16ll << 20)
+int mlswe_flag_noalloc(mlswe_ctx* ctx, int p, int level, double tau, int nbuf, uint8_t* flags_dev);
+
 /* Sets the patches of fine_level (> 0) and fills them: same as set_patches. */
 int mlswe_refine(mlswe_ctx* ctx, int p, int fine_level, int n, const int32_t* boxes);
 

@@ -82,6 +82,7 @@ def lib():
             "mlswe_step_level": (I, [P, I, DP, D, DP]),
             "mlswe_coarsen": (I, [P, I, I]),
             "mlswe_flag": (I, [P, I, I, D, I, ctypes.POINTER(ctypes.c_uint8)]),
+            "mlswe_flag_noalloc": (I, [P, I, I, D, I, V]),
             "mlswe_refine": (I, [P, I, I, I, I32P]),
             "mlswe_regrid": (I, [P, I, DP, I]),
             "mlswe_advance": (I, [P, I, I, DP, I, I, DP]),
@@ -273,6 +274,19 @@ class Solver:
         f = np.zeros((ny, nx), dtype=np.uint8)
         self._check(self.L.mlswe_flag(self.h, p, level, tau, nbuf, f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
         return f
+
+    def flag_noalloc(self, p, level, tau, out, nbuf=2):
+        """Flags of a level into `out`, a contiguous uint8 CUDA tensor of shape
+        (ny, nx) on the context's GPU, with no device allocation by the library
+        (asynchronous on the context's stream)."""
+        nx, ny = self.shapes[p][level][:2]
+        if not (hasattr(out, "data_ptr") and getattr(out, "is_cuda", False)):
+            raise MlsweError(-1, "expected a CUDA tensor")
+        if str(out.dtype) != "torch.uint8" or not out.is_contiguous() or tuple(out.shape) != (ny, nx):
+            raise MlsweError(-1, "expected a contiguous uint8 tensor of shape %s" % ((ny, nx),))
+        if self.dev is not None and out.device.index != self.dev:
+            raise MlsweError(-1, "tensor on cuda:%s, the context runs on cuda:%d" % (out.device.index, self.dev))
+        self._check(self.L.mlswe_flag_noalloc(self.h, p, level, tau, nbuf, ctypes.c_void_p(out.data_ptr())))
 
     def regrid(self, p, tau, nbuf=2):
         t = _f64(list(tau) + [0.0] * (MAXLEV - len(tau)))

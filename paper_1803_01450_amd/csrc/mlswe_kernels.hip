@@ -154,12 +154,10 @@ __device__ __forceinline__ void mirror_ij(int nx, int ny, int& i, int& j) {
   if (j < 0) j = -1 - j; else if (j >= ny) j = 2 * ny - 1 - j;
 }
 
-// Flags of level blockIdx.z of a list (one launch for many problems).
-__global__ __launch_bounds__(256) void k_flag_raw(const FlagLevel* __restrict__ Fs) {
-  const FlagLevel F = Fs[blockIdx.z];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= F.nx || j >= F.ny) return;
+// Undilated flag of cell (i, j): the top layer wet in the cell and its four
+// neighbours (mirrored at the domain edge) and the larger centred difference
+// of eta1 above tau.
+__device__ __forceinline__ unsigned char flag_raw_cell(const FlagLevel& F, int i, int j) {
   auto ok = [&](int a, int b) {
     mirror_ij(F.nx, F.ny, a, b);
     const long long id = cidx(F.pitch, a, b);
@@ -177,14 +175,12 @@ __global__ __launch_bounds__(256) void k_flag_raw(const FlagLevel* __restrict__ 
     double gm = gx > gy ? gx : gy;
     f = gm > F.tau ? 1 : 0;
   }
-  F.raw[(long long)j * F.nx + i] = f;
+  return f;
 }
 
-__global__ __launch_bounds__(256) void k_flag_dilate(const FlagLevel* __restrict__ Fs) {
-  const FlagLevel F = Fs[blockIdx.z];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= F.nx || j >= F.ny) return;
+// Flag of covered cell (i, j) dilated by nbuf cells (clipped to the level)
+// over the undilated flags F.raw.
+__device__ __forceinline__ unsigned char flag_dilate_cell(const FlagLevel& F, int i, int j) {
   unsigned char f = 0;
   if (F.mask[cidx(F.pitch, i, j)]) {
     const int j0 = j - F.nbuf < 0 ? 0 : j - F.nbuf, j1 = j + F.nbuf > F.ny - 1 ? F.ny - 1 : j + F.nbuf;
@@ -193,7 +189,41 @@ __global__ __launch_bounds__(256) void k_flag_dilate(const FlagLevel* __restrict
       for (int a = i0; a <= i1; ++a)
         if (F.raw[(long long)b * F.nx + a]) { f = 1; break; }
   }
-  F.out[(long long)j * F.nx + i] = f;
+  return f;
+}
+
+// Flags of level blockIdx.z of a list (one launch for many problems).
+__global__ __launch_bounds__(256) void k_flag_raw(const FlagLevel* __restrict__ Fs) {
+  const FlagLevel F = Fs[blockIdx.z];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= F.nx || j >= F.ny) return;
+  F.raw[(long long)j * F.nx + i] = flag_raw_cell(F, i, j);
+}
+
+__global__ __launch_bounds__(256) void k_flag_dilate(const FlagLevel* __restrict__ Fs) {
+  const FlagLevel F = Fs[blockIdx.z];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= F.nx || j >= F.ny) return;
+  F.out[(long long)j * F.nx + i] = flag_dilate_cell(F, i, j);
+}
+
+// The same two passes over one level with the descriptor passed by value and
+// one thread per cell of a flat grid (cell k = j nx + i), for callers whose
+// launches may use no device memory of the library's own.
+__global__ __launch_bounds__(256) void k_flag_raw_v(FlagLevel F) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)F.nx * F.ny) return;
+  const int i = (int)(k % F.nx), j = (int)(k / F.nx);
+  F.raw[k] = flag_raw_cell(F, i, j);
+}
+
+__global__ __launch_bounds__(256) void k_flag_dilate_v(FlagLevel F) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)F.nx * F.ny) return;
+  const int i = (int)(k % F.nx), j = (int)(k / F.nx);
+  F.out[k] = flag_dilate_cell(F, i, j);
 }
 
 // Tile summary for clustering (block row y: problem y of the list): one

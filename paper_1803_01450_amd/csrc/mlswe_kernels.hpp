@@ -252,6 +252,8 @@ constexpr int REFLUX_REG = 16 + 128;  // doubles of registers per record (ratios
 __global__ void k_reflux_apply(const RefluxCell* __restrict__ rc, int n, int parity, int rt);
 __global__ void k_flag_raw(const FlagLevel* __restrict__ Fs);
 __global__ void k_flag_dilate(const FlagLevel* __restrict__ Fs);
+__global__ void k_flag_raw_v(FlagLevel F);
+__global__ void k_flag_dilate_v(FlagLevel F);
 __global__ void k_flag_tiles(const FlagTiles* __restrict__ Ts);
 __global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, const TilePart* parts,
                                 double cflmax);

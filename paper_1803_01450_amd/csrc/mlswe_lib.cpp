@@ -12,6 +12,7 @@
 #include <cstring>
 #include <functional>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1388,7 +1389,65 @@ int copy_state(mlswe_ctx* c, LevelH& L, int buf, const double* src, int where, b
 }  // namespace
 
 // ============================================================ C ABI
+// ------------------------------------------------------------ allocation-free flagging
+// mlswe_flag_noalloc stages a level's undilated flags in this file-scope device
+// array instead of library allocations.  Each GPU holds its own copy at its own
+// address until the process ends; in host code the name stands for no device
+// address, so the copy's address is resolved per device (scratch_setup, from
+// mlswe_create with the context's device current) and only that address is
+// handed to kernels.
+namespace {
+constexpr long long NOALLOC_SCRATCH_BYTES = 16ll << 20;
+static_assert(NOALLOC_SCRATCH_BYTES == (long long)MLSWE_NOALLOC_SCRATCH_BYTES, "header and library agree");
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex scratch_mu;
+unsigned char* scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+int scratch_setup(mlswe_ctx* c) {
+  if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES) return MLSWE_OK;  // the variant then refuses
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_dev[c->device]) return MLSWE_OK;
+  void* a = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !a) return fail(c, MLSWE_EDEVICE, "scratch address: %s", hipGetErrorString(e));
+  scratch_dev[c->device] = (unsigned char*)a;
+  return MLSWE_OK;
+}
+
+unsigned char* scratch_of(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return scratch_dev[device];
+}
+}  // namespace
+
 extern "C" {
+
+int mlswe_flag_noalloc(mlswe_ctx* c, int p, int level, double tau, int nbuf, uint8_t* flags_dev) {
+  if (!c) return MLSWE_EINVAL;
+  if (!valid_prob(c, p) || level < 0 || level >= c->probs[p].nlev || !flags_dev || nbuf < 0)
+    return fail(c, MLSWE_EINVAL, "bad args");
+  const ProblemH& P = c->probs[p];
+  const LevelH& L = P.L[level];
+  const long long cells = (long long)L.nx * L.ny;
+  if (cells > NOALLOC_SCRATCH_BYTES)
+    return fail(c, MLSWE_EINVAL, "level %d holds %lld cells, above the %lld bytes of the allocation-free scratch",
+                level, cells, NOALLOC_SCRATCH_BYTES);
+  unsigned char* raw = scratch_of(c->device);
+  if (!raw) return fail(c, MLSWE_EDEVICE, "no allocation-free scratch on device %d", c->device);
+  FlagLevel F;
+  F.q = L.q[L.cur]; F.B = L.B; F.mask = L.mask; F.raw = raw; F.out = flags_dev;
+  F.pitch = L.pitch; F.plane = L.plane; F.nx = L.nx; F.ny = L.ny; F.nbuf = nbuf;
+  F.dx = L.dx; F.dy = L.dy; F.tau = tau; F.hdry = P.P.hdry;
+  // every raw byte of the level is written before the dilation reads it, so
+  // what an earlier call left in the scratch is never seen
+  const unsigned nb = (unsigned)((cells + 255) / 256);
+  hipLaunchKernelGGL(k_flag_raw_v, dim3(nb), dim3(256), 0, c->stream, F);
+  hipLaunchKernelGGL(k_flag_dilate_v, dim3(nb), dim3(256), 0, c->stream, F);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
 
 int mlswe_version(void) { return MLSWE_VERSION; }
 
@@ -1423,6 +1482,11 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
   c->tune.grid_x = 1;
   c->tune.grid_y = 1;
   if (dalloc(c, (void**)&c->tickets, 2 * sizeof(unsigned)) != MLSWE_OK) { delete c; return MLSWE_ENOMEM; }
+  if (scratch_setup(c) != MLSWE_OK) {
+    dfree(c->tickets);
+    delete c;
+    return MLSWE_EDEVICE;
+  }
   *out = c;
   return MLSWE_OK;
 }
