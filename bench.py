@@ -8,8 +8,9 @@ time step of that grid: wall ghost cells, x-sweep, y-sweep, CFL bookkeeping.
 
 Prints one JSON line (rank 0, N = 1):
   value        cell updates per second (interior cells x steps / seconds)
-  roofline     the dominant kernel's algorithmic bytes per launch over its
-               average HIP-event duration, against 8 TB/s
+  roofline     the step's algorithmic bytes (104 B per cell update) over the
+               summed average HIP-event durations of the kernels of one
+               step, against 8 TB/s
   cpu_baseline the FP64 oracle on the host on a bounded sample: all threads of
                the process's share (value) and one thread
 """
@@ -51,12 +52,14 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-vs-plain, AMR and adjoint measurements")
     ap.add_argument("--batch-problems", type=int, default=512)
-    ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--amr-steps", type=int, default=16)
+    ap.add_argument("--batch-steps", type=int, default=300)
+    ap.add_argument("--batch-plain-steps", type=int, default=10)
+    ap.add_argument("--amr-steps", type=int, default=200)
+    ap.add_argument("--amr-plain-steps", type=int, default=20)
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--only", choices=("batch", "amr", "adjoint", "shelf", "layers"), default=None,
                     help="run only this extra measurement and print its JSON (for profiling)")
-    ap.add_argument("--modes", default="plain,batched,graph",
+    ap.add_argument("--modes", default="plain,per_patch,batched,graph,reflux,dynrt",
                     help="launch modes of the batch / AMR measurements")
     return ap.parse_args()
 
@@ -86,84 +89,112 @@ def phase_breakdown(S, steps, every, tau, mode):
     return {k: round(ms / steps, 4) for k, (ms, n) in ph.items()}
 
 
-def ratios(out, modes):
-    if "plain" in modes:
-        for m in ("batched", "graph"):
-            if m in modes:
-                out[m + "_vs_plain"] = out[m]["rate"] / out["plain"]["rate"]
-
-
-def bench_batch(nprob, steps, stream, modes=("plain", "batched", "graph")):
+def bench_batch(nprob, steps, stream, modes=("plain", "per_patch", "batched", "graph"), plain_steps=10):
     """The batch of uneven problems (48..512 cells a side, two levels, ratio 2,
-    regrid every 10 steps): plain per-problem launches against one launch per
-    level substep over all problems (eager and graph-replayed)."""
+    regrid every 10 steps), after two untimed coarse steps (initial dt, first
+    regrid, graph capture): one launch per level substep over all problems
+    (eager and graph-replayed) timed over `steps` coarse steps (300: the whole
+    run); against them, over the first `plain_steps` coarse steps, plain
+    launches (per patch, one problem at a time, each with its own Courant
+    check) and per-patch launches of the whole group (one Courant check per
+    coarse step), with the batched launches timed over the same steps."""
     import numpy as np
     from paper_1803_01450_amd import inputs
-    from paper_1803_01450_amd.binding import Solver, PLAIN, BATCHED, GRAPH
+    from paper_1803_01450_amd.binding import Solver, PLAIN, BATCHED, GRAPH, PER_PATCH
     sizes = inputs.batch_sizes(nprob)
     probs = [inputs.batch_problem(k, int(n)) for k, n in enumerate(sizes)]
     tau = np.tile([2e-5, 0.0], (nprob, 1))
     out = {}
-    for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH)):
-        if name not in modes:
-            continue
-        print("bench: batch %d problems, %s" % (nprob, name), file=sys.stderr, flush=True)
+
+    def run(name, mode, nsteps, breakdown=False):
+        print("bench: batch %d problems, %s, %d coarse steps" % (nprob, name, nsteps), file=sys.stderr, flush=True)
         S = Solver(stream=stream)
         for c in probs:
             p = S.define(c["n"], c["n"], c["dx"], c["dx"], c["r"], (2,))
             S.set_bathymetry(p, np.kron(c["B"], np.ones((2, 2))))
             S.set_state(p, 0, c["q"])
-        if name != "plain":
+        if mode in (BATCHED, GRAPH):
             S.autotune(None, reps=1)
         S.advance(2, 10, tau, mode=mode)   # initial dt, first regrid, graph capture
-        sec, upd = timed_advance(S, steps, 10, tau, mode)
-        out[name] = {"seconds": sec, "cell_updates": upd, "rate": upd / sec}
-        if name == "batched":
+        sec, upd = timed_advance(S, nsteps, 10, tau, mode)
+        res = {"seconds": sec, "coarse_steps": nsteps, "cell_updates": upd, "rate": upd / sec}
+        if breakdown:
             out["tuning"] = S.tuning()
-            out["phases_ms_per_coarse_step"] = phase_breakdown(S, steps, 10, tau, mode)
+            out["phases_ms_per_coarse_step"] = phase_breakdown(S, 20, 10, tau, mode)
         S.close()
-    ratios(out, modes)
+        return res
+
+    for name, mode in (("batched", BATCHED), ("graph", GRAPH)):
+        if name in modes:
+            out[name] = run(name, mode, steps, breakdown=name == "batched")
+    short = [m for m in ("plain", "per_patch") if m in modes]
+    for name in short:
+        out[name] = run(name, PLAIN if name == "plain" else PER_PATCH, plain_steps)
+    if short:
+        out["batched_first_steps"] = run("batched", BATCHED, plain_steps)
+        for name in short:
+            out["batched_vs_" + name] = out["batched_first_steps"]["rate"] / out[name]["rate"]
+    if "graph" in out and "batched" in out:
+        out["graph_vs_batched"] = out["graph"]["rate"] / out["batched"]["rate"]
     out["problems"] = nprob
     out["level0_cells"] = int(sum(int(n) ** 2 for n in sizes))
-    out["coarse_steps"] = steps
     return out
 
 
-def bench_amr(steps, stream, modes=("plain", "batched", "graph", "reflux", "dynrt")):
+# flag thresholds of the three-level shoreline run (levels 0 and 1): from the
+# first regrid's ~0.3M finest cells the refined region follows the spreading
+# pulse to ~3M finest cells by coarse step 200, ~2.4e9 cell updates in all
+AMR_TAU = [2e-7, 4e-7]
+
+
+def bench_amr(steps, stream, modes=("plain", "batched", "graph", "reflux", "dynrt"), plain_steps=20):
     """Three levels (ratios 2 and 4) over 400 km with shorelines, 16 level-0
-    patches of 64^2, regrid every 4 coarse steps.  "reflux": batched launches
-    with the mass flux correction at coarse-fine edges; "dynrt": batched with
-    time ratios chosen per coarse step."""
+    patches of 64^2, regrid every 4 coarse steps, `steps` coarse steps from the
+    initial state (200: the whole run), each mode timed over the whole run.
+    "plain" (per-patch launches, one problem at a time) is timed over the first
+    `plain_steps` coarse steps, with the batched launches timed over the same
+    steps beside it for the ratio.  "reflux": batched launches with the mass
+    flux correction at coarse-fine edges; "dynrt": batched with time ratios
+    chosen per coarse step."""
     import numpy as np
     from paper_1803_01450_amd import inputs
     from paper_1803_01450_amd.binding import Solver, PLAIN, BATCHED, GRAPH
     c = inputs.amr_shoreline()
-    tau = [[2e-6, 4e-6]]
+    tau = [AMR_TAU]
     out = {}
-    for name, mode in (("plain", PLAIN), ("batched", BATCHED), ("graph", GRAPH), ("reflux", BATCHED),
-                       ("dynrt", BATCHED)):
-        if name not in modes:
-            continue
-        print("bench: AMR 3 levels, %s" % name, file=sys.stderr, flush=True)
+
+    def run(name, mode, nsteps, breakdown=False):
+        print("bench: AMR 3 levels, %s, %d coarse steps" % (name, nsteps), file=sys.stderr, flush=True)
         S = Solver(stream=stream, reflux=name == "reflux", dynamic_rt=name == "dynrt")
         p = S.define(c["n0"], c["n0"], c["dx0"], c["dx0"], c["r"], c["ratios"])
         S.set_bathymetry(p, c["Bf"])
         S.set_patches(p, 0, c["level0_boxes"])
         S.set_state(p, 0, c["q0"])
-        S.advance(2, 4, tau, mode=mode)
-        sec, upd = timed_advance(S, steps, 4, tau, mode)
-        if name == "batched":
-            out["phases_ms_per_coarse_step"] = phase_breakdown(S, steps, 4, tau, mode)
-        out[name] = {"seconds": sec, "cell_updates": upd, "rate": upd / sec,
-                     "finest_patches": int(len(S.patches(p, 2))),
-                     "time_ratios": [int(v) for v in S.time_ratios(p)]}
+        sec, upd = timed_advance(S, nsteps, 4, tau, mode)
+        fine = [int(b[2]) * int(b[3]) for b in S.patches(p, 2)]
+        res = {"seconds": sec, "coarse_steps": nsteps, "cell_updates": upd, "rate": upd / sec,
+               "finest_patches": len(fine), "finest_cells": int(sum(fine)),
+               "time_ratios": [int(v) for v in S.time_ratios(p)]}
+        if breakdown:
+            out["phases_ms_per_coarse_step"] = phase_breakdown(S, 50, 4, tau, mode)
         S.close()
-    ratios(out, modes)
+        return res
+
+    for name, mode in (("batched", BATCHED), ("graph", GRAPH), ("reflux", BATCHED), ("dynrt", BATCHED)):
+        if name in modes:
+            out[name] = run(name, mode, steps, breakdown=name == "batched")
+    if "plain" in modes:
+        out["plain"] = run("plain", PLAIN, plain_steps)
+        out["batched_first_steps"] = run("batched", BATCHED, plain_steps)
+        out["batched_vs_plain"] = out["batched_first_steps"]["rate"] / out["plain"]["rate"]
     if "reflux" in out and "batched" in out:
         out["reflux_time_ratio"] = out["reflux"]["seconds"] / out["batched"]["seconds"]
     if "dynrt" in out and "batched" in out:
         out["dynrt_time_ratio"] = out["dynrt"]["seconds"] / out["batched"]["seconds"]
-    out["coarse_steps"] = steps
+    if "graph" in out and "batched" in out:
+        out["graph_vs_batched"] = out["graph"]["rate"] / out["batched"]["rate"]
+    out["workload"] = "amr_shoreline_3level_256"
+    out["tau"] = AMR_TAU
     return out
 
 
@@ -416,9 +447,9 @@ def main():
         modes = tuple(args.modes.split(","))
         st = stream.cuda_stream
         if args.only == "batch":
-            res = bench_batch(args.batch_problems, args.batch_steps, st, modes)
+            res = bench_batch(args.batch_problems, args.batch_steps, st, modes, args.batch_plain_steps)
         elif args.only == "amr":
-            res = bench_amr(args.amr_steps, st, modes)
+            res = bench_amr(args.amr_steps, st, modes, args.amr_plain_steps)
         elif args.only == "shelf":
             res = bench_shelf(st)
         elif args.only == "layers":
@@ -485,26 +516,38 @@ def main():
     # algorithmic bytes per launch: x-sweep reads 7 and writes 6 doubles for the
     # n x (n + 4) cells it updates (interior rows and the two frame rows on each
     # side); y-sweep reads 7 and writes 6 for the n x n interior cells
-    kinds = [("x_sweep", BYTES_PER_CELL * n * (n + 4)), ("y_sweep", BYTES_PER_CELL * n * n)]
+    # The roofline unit is the cell update: one full step of a cell reads its
+    # six fields and B once and writes six once (104 B).  A step's kernels are
+    # the x- and y-sweep launches (the split scheme moves its intermediate
+    # through HBM between them), so the step's algorithmic bytes are charged to
+    # the two together: achieved = 104 B x cells / (x + y average durations).
+    # Each sweep's own traffic (seven fields read, six written per swept cell)
+    # is listed beside it as a per-kernel bandwidth.
+    names = ("x_sweep", "y_sweep")
+    sweep_bytes = {"x_sweep": BYTES_PER_CELL * n * (n + 4), "y_sweep": BYTES_PER_CELL * n * n}
     per = []
-    for k, (name, byts) in enumerate(kinds):
+    for k, name in enumerate(names):
         avg = ms[k] / max(1, launches[k]) / 1e3
-        per.append(dict(kernel=name, avg_ms=avg * 1e3, launches=launches[k], bytes=byts,
-                        gbs=byts / avg / 1e9 if avg > 0 else 0.0))
-    dom = max(per, key=lambda d: d["avg_ms"])
-    achieved = dom["gbs"]
-    traffic = profiled_traffic(dom["kernel"]) if n == 4096 else None
+        per.append(dict(kernel=LAUNCHED[name], avg_ms=avg * 1e3, launches=launches[k],
+                        sweep_bytes=sweep_bytes[name], sweep_gbs=sweep_bytes[name] / avg / 1e9 if avg > 0 else 0.0))
+    step_ms = sum(d["avg_ms"] for d in per)
+    step_bytes = BYTES_PER_CELL * n * n
+    achieved = step_bytes / (step_ms * 1e-3) / 1e9
+    traffic = None
+    if n == 4096:
+        tr = [profiled_traffic(name) for name in names]
+        traffic = None if any(t is None for t in tr) else sum(tr)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic,
-            "kernel": dom["kernel"], "avg_ms": round(dom["avg_ms"], 4),
-            "bytes_per_launch": dom["bytes"], "all_kernels": per}
-    # the same kernel against the FP64 vector peak, with the census flop count
+            "kernel": "+".join(LAUNCHED[nm] for nm in names), "avg_ms": round(step_ms, 4),
+            "bytes_per_launch": step_bytes, "per_kernel": per}
+    # the same kernels against the FP64 vector peak, with the census flop count
     if n == 4096:
-        cells_dom = dom["bytes"] / BYTES_PER_CELL
-        tf = FLOPS_PER_CELL[dom["kernel"]] * cells_dom / (dom["avg_ms"] * 1e-3) / 1e12
+        fl = FLOPS_PER_CELL["x_sweep"] * n * (n + 4) + FLOPS_PER_CELL["y_sweep"] * n * n
+        tf = fl / (step_ms * 1e-3) / 1e12
         roof["alu"] = {"bound": "alu", "achieved": round(tf, 3), "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
                        "frac": round(tf * 1e12 / FP64_PEAK, 4),
-                       "flops_per_cell": FLOPS_PER_CELL[dom["kernel"]]}
+                       "flops_per_cell": FLOPS_PER_CELL["x_sweep"] + FLOPS_PER_CELL["y_sweep"]}
 
     out = {
         "metric": METRIC, "value": rate, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -523,8 +566,8 @@ def main():
     S.close()
     if not args.no_extras:
         st = stream.cuda_stream
-        out["batch"] = bench_batch(args.batch_problems, args.batch_steps, st)
-        out["amr"] = bench_amr(args.amr_steps, st)
+        out["batch"] = bench_batch(args.batch_problems, args.batch_steps, st, plain_steps=args.batch_plain_steps)
+        out["amr"] = bench_amr(args.amr_steps, st, plain_steps=args.amr_plain_steps)
         out["adjoint"] = bench_adjoint(args.adjoint_steps, st)
         out["shelf_demo"] = bench_shelf(st)
         out["layers"] = bench_layers(st)

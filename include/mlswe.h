@@ -41,7 +41,7 @@ enum {
 };
 
 enum { MLSWE_HOST = 0, MLSWE_DEVICE = 1 };
-enum { MLSWE_PLAIN = 0, MLSWE_BATCHED = 1, MLSWE_GRAPH = 2 };
+enum { MLSWE_PLAIN = 0, MLSWE_BATCHED = 1, MLSWE_GRAPH = 2, MLSWE_PER_PATCH = 3 };
 
 typedef struct mlswe_ctx mlswe_ctx;
 
@@ -221,7 +221,10 @@ int mlswe_regrid(mlswe_ctx* ctx, int p, const double* tau, int nbuf);
  * patches of all problems;
  * MLSWE_GRAPH does the same and replays each coarse step from a captured
  * hipGraph (captured on first use, again after a regrid; the first step of a
- * run, which derives dt from the state, runs uncaptured).
+ * run, which derives dt from the state, runs uncaptured);
+ * MLSWE_PER_PATCH steps all problems together like MLSWE_BATCHED (one Courant
+ * check and retake decision per coarse step for the whole group) but launches
+ * the sweeps per patch, as MLSWE_PLAIN does.
  * dts_out (nullable, host [n_problems][n_coarse_steps]) receives the coarse
  * steps.  Errors: MLSWE_EINVAL, MLSWE_ESTATE, MLSWE_ECFL (Courant number above
  * cfl_max after the allowed retakes), MLSWE_ENAN (a non-finite Courant

@@ -21,7 +21,7 @@ LIBPATH = os.path.join(HERE, "libmlswe.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ECFL, ENAN, ESTATE = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
-PLAIN, BATCHED, GRAPH = 0, 1, 2
+PLAIN, BATCHED, GRAPH, PER_PATCH = 0, 1, 2, 3
 MAXLEV = 8
 
 ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECFL: "ECFL", ENAN: "ENAN", ESTATE: "ESTATE"}

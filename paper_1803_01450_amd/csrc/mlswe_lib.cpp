@@ -445,8 +445,8 @@ int build_launch(mlswe_ctx* c, int l) {
       for (const Box& b : P.L[l].boxes) {
         const int ns = axis == 0 ? (b.nx + XTILE_COLS - 1) / XTILE_COLS : (b.nx + 63) / 64;
         const int h = axis == 0 ? b.ny + 4 : b.ny;
-        for (int s = 0; s < ns; ++s)
-          for (int j = 0; j < h; j += rows) d.push_back(std::min(rows, h - j));
+        for (int j = 0; j < h; j += rows)
+          for (int s = 0; s < ns; ++s) d.push_back(std::min(rows, h - j));
       }
     }
   };
@@ -542,18 +542,17 @@ int build_launch(mlswe_ctx* c, int l) {
       }
       LL.patch_prob.push_back((int)pi);
       const int x0 = (int)xt.size();
-      for (int i0 = b.ilo; i0 < b.ilo + b.nx; i0 += XTILE_COLS) {
-        const int nc = std::min(XTILE_COLS, b.ilo + b.nx - i0);
-        for (int j0 = b.jlo - 2; j0 < b.jlo + b.ny + 2; j0 += xrows)
-          xt.push_back(XTile{id, i0, nc, j0, std::min(xrows, b.jlo + b.ny + 2 - j0)});
-      }
+      // tiles row-major within the patch (the launch hands contiguous bands of
+      // them to the XCDs, so a band is a strip of whole tile rows)
+      for (int j0 = b.jlo - 2; j0 < b.jlo + b.ny + 2; j0 += xrows)
+        for (int i0 = b.ilo; i0 < b.ilo + b.nx; i0 += XTILE_COLS)
+          xt.push_back(XTile{id, i0, std::min(XTILE_COLS, b.ilo + b.nx - i0), j0,
+                             std::min(xrows, b.jlo + b.ny + 2 - j0)});
       const int y0 = (int)yt.size();
-      for (int i0 = b.ilo; i0 < b.ilo + b.nx; i0 += 64) {
-        const int nc = std::min(64, b.ilo + b.nx - i0);
-        for (int j0 = b.jlo; j0 < b.jlo + b.ny; j0 += yrows) {
-          const int nr = std::min(yrows, b.jlo + b.ny - j0);
-          yt.push_back(YTile{id, i0, nc, j0, nr, (j0 + nr == b.jlo + b.ny) ? 1 : 0});
-        }
+      for (int j0 = b.jlo; j0 < b.jlo + b.ny; j0 += yrows) {
+        const int nr = std::min(yrows, b.jlo + b.ny - j0);
+        for (int i0 = b.ilo; i0 < b.ilo + b.nx; i0 += 64)
+          yt.push_back(YTile{id, i0, std::min(64, b.ilo + b.nx - i0), j0, nr, (j0 + nr == b.jlo + b.ny) ? 1 : 0});
       }
       LL.xr.push_back({x0, (int)xt.size() - x0});
       LL.yr.push_back({y0, (int)yt.size() - y0});
@@ -784,9 +783,11 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc;
   const int sx = c->tune.sched_x, sy = c->tune.sched_y;
+  // one wave per tile: a multiple of eight blocks (the kernels hand each XCD a
+  // band of the tiles); persistent schedules: a multiple of the compute units
   auto grid_of = [&](int ntiles, int sched, int mult) {
     const int need = (ntiles + 3) / 4;
-    if (sched == 0) return need;
+    if (sched == 0) return (need + 7) / 8 * 8;
     const int g = std::max(1, mult) * c->ncu;
     return std::min(need, g);
   };
@@ -2121,7 +2122,8 @@ int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt
 // unused before they are read again, so the backup leaves them out.
 int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
   int rc;
-  const bool together = mode != MLSWE_PLAIN;
+  // one launch per level substep over the group's patches, or one per patch
+  const bool together = mode == MLSWE_BATCHED || mode == MLSWE_GRAPH;
   const bool retry = c->cfg.max_retries > 0;
   int nctl = 0;
   for (const ProblemH& P : c->probs) nctl += P.nlev;
@@ -2224,7 +2226,7 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
   const int np = (int)c->probs.size();
   if (np == 0) return fail(c, MLSWE_ESTATE, "no problem defined");
   if (nsteps < 0 || regrid_every < 0 || (regrid_every > 0 && !tau) || nbuf < 0 ||
-      (mode != MLSWE_PLAIN && mode != MLSWE_BATCHED && mode != MLSWE_GRAPH))
+      (mode != MLSWE_PLAIN && mode != MLSWE_BATCHED && mode != MLSWE_GRAPH && mode != MLSWE_PER_PATCH))
     return fail(c, MLSWE_EINVAL, "bad advance arguments");
   for (int p = 0; p < np; ++p)
     if (!c->probs[p].bathy || !c->probs[p].state) return fail(c, MLSWE_ESTATE, "problem %d not initialised", p);
@@ -2236,8 +2238,9 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
         if (c->probs[p].ratio[l] != c->probs[0].ratio[l]) return fail(c, MLSWE_EINVAL, "batched ratios differ");
     }
   // every coarse step: the regrid of all problems (one pass, the problems are
-  // independent), then the step of the problems together (batched, graph) or
-  // one problem at a time with one launch per patch (plain)
+  // independent), then the step of the problems together (batched, graph: one
+  // launch per level substep; per-patch: one launch per patch) or one problem
+  // at a time with one launch per patch (plain)
   const int ngroups = together ? 1 : np;
   for (int n = 0; n < nsteps; ++n) {
     int rc;

@@ -117,20 +117,25 @@ def roofline_grid(n=4096, L=409.6e3, seed=SEED0 + 3):
     return dict(n=n, L=L, dx=L / n, B=B, q=q, r=0.97, nsteps=500)
 
 
-def amr_shoreline(n0=256, L=400e3, ratios=(2, 4), seed=SEED0 + 2):
+def amr_shoreline(n0=256, L=400e3, ratios=(2, 4), seed=SEED0 + 2, pulses=1):
     """Three levels (ratios 2 and 4) over 400 km: bathymetry from 64 Gaussians
     mapped to [-4000, +200] m at the finest samples, interface at -100 m, a 2 m
-    pulse on eta1 centred where B < -2000 m.  Level 0 is 16 patches of 64x64."""
+    pulse on eta1 (sigma 15 km) centred where B < -2000 m.  Level 0 is 16
+    patches of 64x64.  pulses > 1 adds further such pulses, drawn after the
+    first (the first pulse and everything before it are unchanged), so that the
+    refined region is large from the first regrid on."""
     rng = np.random.default_rng(seed)
     nf = n0 * int(np.prod(ratios))
     Bf = smooth_field(rng, nf, L, 64, -4000.0, 200.0)
     B0 = block_mean(Bf, int(np.prod(ratios)))
-    while True:
-        c = rng.uniform(0.1 * L, 0.9 * L, 2)
-        i = int(c[0] / (L / n0)); j = int(c[1] / (L / n0))
-        if B0[j, i] < -2000.0:
-            break
-    eta1 = gaussian(n0, L, c, 15e3, 2.0)
+    eta1 = np.zeros((n0, n0))
+    for _ in range(pulses):
+        while True:
+            c = rng.uniform(0.1 * L, 0.9 * L, 2)
+            i = int(c[0] / (L / n0)); j = int(c[1] / (L / n0))
+            if B0[j, i] < -2000.0:
+                break
+        eta1 = eta1 + gaussian(n0, L, c, 15e3, 2.0)
     eta2 = np.full((n0, n0), -100.0)
     q = state_from_surfaces(eta1, eta2, B0)
     ps = 64

@@ -74,6 +74,44 @@ def test_adjoint_matches_oracle_dual_64():
     S.close()
 
 
+def test_adjoint_matches_oracle_dual_256_full_run():
+    """256^2, the full 400 steps with checkpoints every 20: the gradient's
+    directional derivatives along two seeded random directions in eta1 and
+    two in B against the oracle's forward-mode (dual number) derivative of the
+    same discrete map, within 1e-9 relative.  The five oracle runs go to host
+    threads (the oracle releases the interpreter while it runs)."""
+    from concurrent.futures import ThreadPoolExecutor
+    say("case: adjoint 256x256, 400 steps, vs oracle dual numbers in 4 directions")
+    n, nsteps = 256, 400
+    c, dts, tg, S, prob = make(n, nsteps)
+    L, ge, gB = gradients(c, prob)
+    rng = np.random.default_rng(256)
+    dirs = [(rng.standard_normal((n, n)), None), (None, rng.standard_normal((n, n))),
+            (rng.standard_normal((n, n)), None), (None, rng.standard_normal((n, n)))]
+
+    def loss_only():
+        return oracle.gauge_loss(c["eta1"], c["B"], c["dx"], c["eta2"], dts, c["every"], c["gauge"], tg, r=c["r"])
+
+    def dual(v):
+        return oracle.gauge_loss(c["eta1"], c["B"], c["dx"], c["eta2"], dts, c["every"], c["gauge"], tg,
+                                 v_eta=v[0], v_B=v[1], r=c["r"])[1]
+
+    with ThreadPoolExecutor(max_workers=5) as ex:
+        fl = ex.submit(loss_only)
+        fd = [ex.submit(dual, v) for v in dirs]
+        Lo = fl.result()
+        ds = [f.result() for f in fd]
+    say("loss gpu %.17g oracle %.17g" % (L, Lo))
+    assert abs(L - Lo) <= 1e-10 * abs(Lo)
+    scale = max(np.abs(ge).max(), np.abs(gB).max())
+    for (ve, vb), d in zip(dirs, ds):
+        g = (ge * ve).sum() if ve is not None else (gB * vb).sum()
+        say("directional derivative (%s) gpu %.15e oracle %.15e rel %.2e" % (
+            "eta1" if ve is not None else "B", g, d, abs(g - d) / abs(d)))
+        assert abs(g - d) <= 1e-9 * abs(d) + 1e-12 * scale
+    S.close()
+
+
 def test_adjoint_full_size_central_differences():
     """1024^2, 400 steps, checkpoints every 20: the gradient at 64 seeded cells
     within 3 sigma of the pulse centre against central differences of the GPU

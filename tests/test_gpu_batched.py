@@ -130,3 +130,19 @@ def test_auto_tile_heights_bitwise():
     B.advance(6, 3, TAU, mode=1)
     assert same(states(A), states(B))
     A.close(); B.close()
+
+
+@pytest.mark.parametrize("mode", [0, 3])
+def test_per_patch_and_plain_launches_match_batched(mode):
+    """Per-patch launches, one problem at a time (plain, 0) or all problems
+    together with one Courant check per coarse step (per-patch, 3), give the
+    batched results bit for bit across two regrids."""
+    say("case: launch mode", mode, "vs batched, 8 coarse steps")
+    A = build()
+    A.advance(8, 4, TAU, mode=1)
+    B = build()
+    B.advance(8, 4, TAU, mode=mode)
+    assert same(states(A), states(B))
+    for p in range(len(SIZES)):
+        assert A.counters(p)["updates"] == B.counters(p)["updates"]
+    A.close(); B.close()

@@ -105,3 +105,39 @@ def test_full_amr_shoreline():
     assert len(S.patches(p, 2)) > 50
     assert S.counters(p)["updates"] == H.counters()["updates"]
     S.close()
+
+
+def test_amr_shoreline_at_stated_size():
+    """The shoreline run at its stated size of about 1.5M finest cells: eight
+    pulses (the same bathymetry and first pulse, seven more drawn after it), so
+    that the first regrid at tau (2e-7, 4e-7), the benchmark's thresholds,
+    already refines ~1.67M finest cells in ~870 patches; then four coarse
+    steps (8 substeps of the finest level each), batched launches in the
+    benchmark's configuration, every level against the oracle."""
+    from paper_1803_01450_amd.binding import Solver, BATCHED
+    c = inputs.amr_shoreline(pulses=8)
+    nsteps, every, tau = 4, 4, [2e-7, 4e-7]
+    say("case: AMR shoreline at stated size, 256^2 + 8 pulses, %d coarse steps, batched" % nsteps)
+    S = Solver()
+    p = S.define(c["n0"], c["n0"], c["dx0"], c["dx0"], c["r"], c["ratios"])
+    S.set_bathymetry(p, c["Bf"])
+    S.set_patches(p, 0, c["level0_boxes"])
+    S.set_state(p, 0, c["q0"])
+    dts = S.advance(nsteps, every, [tau], mode=BATCHED, want_dts=True)
+    fine = sum(int(b[2]) * int(b[3]) for b in S.patches(p, 2))
+    say("finest cells", fine, "patches", len(S.patches(p, 2)))
+    assert fine >= 1_200_000
+    H = oracle.Hierarchy(c["n0"], c["n0"], c["dx0"], c["dx0"], ratios=c["ratios"], r=c["r"])
+    H.set_bathymetry(c["Bf"])
+    H.set_patches(0, c["level0_boxes"])
+    H.set_state(0, c["q0"])
+    rc, rdts = H.advance(nsteps, every, tau)
+    assert rc == 0
+    assert np.abs(dts[0] - rdts).max() <= 1e-12 * rdts.max()
+    for l in range(3):
+        assert np.array_equal(S.patches(p, l), H.patches(l)), l
+        err = rel_err(S.state(p, l), H.state(l))
+        say("level", l, "patches", len(S.patches(p, l)), "rel err", err.max())
+        assert err.max() <= 1e-9
+    assert S.counters(p)["updates"] == H.counters()["updates"]
+    S.close()
