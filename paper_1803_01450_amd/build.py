@@ -14,8 +14,14 @@ SRCS = [(os.path.join(CSRC, "mlswe_kernels.hip"), []),
         (os.path.join(CSRC, "mlswe_sweeps_fast.hip"), ["-ffp-contract=fast"]),
         (os.path.join(CSRC, "mlswe_adjoint.hip"), []),
         (os.path.join(CSRC, "mlswe_layers.hip"), []),
-        (os.path.join(CSRC, "mlswe_lib.cpp"), [])]
+        (os.path.join(CSRC, "mlswe_lib.cpp"), []),
+        (os.path.join(CSRC, "mlswe_launch.cpp"), []),
+        (os.path.join(CSRC, "mlswe_regrid.cpp"), []),
+        (os.path.join(CSRC, "mlswe_advance.cpp"), []),
+        (os.path.join(CSRC, "mlswe_adjoint_host.cpp"), []),
+        (os.path.join(CSRC, "mlswe_tuning.cpp"), [])]
 HDRS = [os.path.join(HERE, "csrc", "mlswe_kernels.hpp"), os.path.join(HERE, "csrc", "mlswe_device.hpp"),
+        os.path.join(HERE, "csrc", "mlswe_host.hpp"),
         os.path.join(HERE, "csrc", "mlswe_layers.hpp"),
         os.path.join(ROOT, "include", "mlswe.h")]
 ARCH = os.environ.get("MLSWE_ARCH", "gfx950")
