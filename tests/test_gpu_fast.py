@@ -193,3 +193,25 @@ def test_fast_batched_shoreline_problems_match_exact():
             err = rel_err(sf[k][l], se[k][l])
             say("problem", k, "level", l, "rel err", err.max())
             assert err.max() <= 1e-9
+
+
+def test_fast_roofline_grid_ten_steps_full():
+    """The fast build on the 4096^2 grid, ten steps at a fixed dt, against the
+    oracle over the whole grid: within 1e-9 relative per field."""
+    import os
+    say("case: fast build, 4096^2 ten steps, whole grid")
+    c = inputs.roofline_grid()
+    n = c["n"]
+    S = fast_solver()
+    p = S.define(n, n, c["dx"], c["dx"], c["r"])
+    S.set_bathymetry(p, c["B"])
+    S.set_state(p, 0, c["q"])
+    dt = 0.9 * c["dx"] / np.sqrt(G * 4000.0)
+    S.run_fixed(p, np.full(10, dt))
+    g = S.state(p, 0)
+    S.close()
+    threads = min(16, len(os.sched_getaffinity(0)))
+    _, sec, ref = oracle.time_fixed_mt(c["B"], c["q"], c["dx"], c["dx"], 10, dt, threads, r=c["r"], want_state=True)
+    err = rel_err(g, ref)
+    say("oracle %.1f s; rel err per field" % sec, err)
+    assert err.max() <= 1e-9

@@ -339,3 +339,29 @@ def test_roofline_grid_sampled_windows():
         _, wsm = oracle.step_window(c["B"], c["q"], c["dx"], c["dx"], b, dt, r=c["r"])
         assert wsm[0] <= sm[0, 0] and wsm[1] <= sm[0, 1]
     S.close()
+
+
+def test_roofline_grid_ten_steps_full():
+    """The 4096^2 grid, ten steps at a fixed dt through the benchmark's kernels
+    (one x- and one y-sweep launch per step over the patch's tiles, handed to
+    the XCDs in bands), against the oracle's ten steps over the whole grid (on
+    the host's threads: row strips stepped as boxes, the one-box arithmetic):
+    bit for bit."""
+    import os
+    say("case: 4096^2 ten steps, whole grid")
+    c = inputs.roofline_grid()
+    n = c["n"]
+    S = solver()
+    p = S.define(n, n, c["dx"], c["dx"], c["r"])
+    S.set_bathymetry(p, c["B"])
+    S.set_state(p, 0, c["q"])
+    dt = 0.9 * c["dx"] / np.sqrt(G * 4000.0)
+    S.run_fixed(p, np.full(10, dt))
+    g = S.state(p, 0)
+    S.close()
+    threads = min(16, len(os.sched_getaffinity(0)))
+    _, sec, ref = oracle.time_fixed_mt(c["B"], c["q"], c["dx"], c["dx"], 10, dt, threads, r=c["r"], want_state=True)
+    say("oracle: %d threads, %.1f s" % (threads, sec))
+    err = rel_err(g, ref)
+    say("rel err", err.max())
+    assert np.array_equal(g, ref)
