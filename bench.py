@@ -333,8 +333,6 @@ def bench_layers(stream, M=4, r=2, n=2048, reps=20):
                         "frac": crs_b / (crs_ms * 1e-3) / HBM_PEAK}}
 
 
-# the kernels the timed steps launch (one wave per tile, no branch signature)
-LAUNCHED = {"x_sweep": "k_sweep_x1", "y_sweep": "k_sweep_y1"}
 # the sources the sweep kernels are compiled from
 SWEEP_SOURCES = ("mlswe_kernels.hip", "mlswe_sweeps_fast.hip", "mlswe_sweeps.inc", "mlswe_wave.hpp",
                  "mlswe_device.hpp", "mlswe_kernels.hpp")
@@ -348,8 +346,9 @@ def kernel_source_sha():
 
 
 def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None if the kernel sources changed since it was taken."""
+    """HBM bytes per launch of the kernel named `kernel` from the committed
+    rocprofv3 counter summary, or None if the kernel sources changed since it
+    was taken (or the summary does not cover that kernel)."""
     path = os.path.join(ROOT, "profiles", "sweeps_roofline_grid_4096_hbm_traffic.md")
     if not os.path.exists(path):
         return None
@@ -357,7 +356,7 @@ def profiled_traffic(kernel):
     for line in open(path):
         if line.startswith("kernel_source_sha256:"):
             sha = line.split(":", 1)[1].strip()
-        if line.startswith("traffic_bytes_per_launch %s:" % LAUNCHED[kernel]):
+        if line.startswith("traffic_bytes_per_launch %s:" % kernel):
             val = float(line.split(":", 1)[1])
     if sha != kernel_source_sha() or val is None:
         return None
@@ -469,6 +468,11 @@ def main():
     S.set_bathymetry(p, Bd)
     S.set_state(p, 0, qd)
     del Bd, qd
+    if not (args.x_rows or args.y_rows):
+        # the library's autotuner picks tile heights and schedules for this layout
+        print("bench: autotune", file=sys.stderr, flush=True)
+        S.autotune(None, reps=3)
+    tuning = S.tuning()
     print("bench: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
     S.advance(args.warmup)
     S.synchronize()
@@ -524,22 +528,25 @@ def main():
     # Each sweep's own traffic (seven fields read, six written per swept cell)
     # is listed beside it as a per-kernel bandwidth.
     names = ("x_sweep", "y_sweep")
+    # kernels launched: one wave per tile (schedule 0) or persistent waves
+    launched = {"x_sweep": "k_sweep_x1" if tuning.get("sched_x", 0) == 0 else "k_sweep_x",
+                "y_sweep": "k_sweep_y1" if tuning.get("sched_y", 0) == 0 else "k_sweep_y"}
     sweep_bytes = {"x_sweep": BYTES_PER_CELL * n * (n + 4), "y_sweep": BYTES_PER_CELL * n * n}
     per = []
     for k, name in enumerate(names):
         avg = ms[k] / max(1, launches[k]) / 1e3
-        per.append(dict(kernel=LAUNCHED[name], avg_ms=avg * 1e3, launches=launches[k],
+        per.append(dict(kernel=launched[name], avg_ms=avg * 1e3, launches=launches[k],
                         sweep_bytes=sweep_bytes[name], sweep_gbs=sweep_bytes[name] / avg / 1e9 if avg > 0 else 0.0))
     step_ms = sum(d["avg_ms"] for d in per)
     step_bytes = BYTES_PER_CELL * n * n
     achieved = step_bytes / (step_ms * 1e-3) / 1e9
     traffic = None
     if n == 4096:
-        tr = [profiled_traffic(name) for name in names]
+        tr = [profiled_traffic(launched[name]) for name in names]
         traffic = None if any(t is None for t in tr) else sum(tr)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic,
-            "kernel": "+".join(LAUNCHED[nm] for nm in names), "avg_ms": round(step_ms, 4),
+            "kernel": "+".join(launched[nm] for nm in names), "avg_ms": round(step_ms, 4),
             "bytes_per_launch": step_bytes, "per_kernel": per}
     # the same kernels against the FP64 vector peak, with the census flop count
     if n == 4096:
@@ -558,6 +565,7 @@ def main():
         "step_hbm_frac": round(rate * BYTES_PER_CELL / HBM_PEAK, 4),
         "event_ms_per_step": ev_ms / args.steps,
         "roofline": roof,
+        "tuning": tuning,
         "status": status,
         "fast": fast,
     }

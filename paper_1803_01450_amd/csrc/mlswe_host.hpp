@@ -108,6 +108,9 @@ struct LevelLaunch {
   int model_rows[4] = {0, 0, 0, 0};
   TilePart* parts = nullptr;                 // per tile: x tiles, then y tiles
   int cap_parts = 0;
+  SliceRed* red = nullptr;                   // slice results of the partial reduction
+  unsigned* arrive = nullptr;                // its arrival counters (zero between launches)
+  int cap_red = 0, cap_arrive = 0;
   int max_info_tiles = 0;                    // most tiles of one problem on the level
   FillPatch* fp[4] = {nullptr, nullptr, nullptr, nullptr};   // [fine parity * 2 + coarse parity]
   CoarsenPatch* cp[4] = {nullptr, nullptr, nullptr, nullptr};

@@ -254,27 +254,36 @@ __global__ __launch_bounds__(256) void k_flag_tiles(const FlagTiles* __restrict_
 // adds the fix-up and clamp counts to the problem's counters.  Speeds are kept
 // as the bit patterns of non-negative doubles.  Block size: a multiple of 64,
 // at most 1024.
+// Block (x, y) of a grid of (problems, slices) reduces slice y of problem x's
+// partials (its x tiles, then its y tiles, cut into gridDim.y equal slices).
+// With one slice the block finishes the problem itself; with several, each
+// block leaves its slice's result in red and the last block to arrive (by an
+// atomic counter it then sets back to zero) combines the slices in slice order,
+// so the result does not depend on which block comes last.
 __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos,
-                                                        const TilePart* parts, double cflmax) {
+                                                        const TilePart* parts, double cflmax, SliceRed* red,
+                                                        unsigned* arrive) {
   __shared__ double red_d[4][16];
   __shared__ unsigned long long red_u[4][16];
   const LevelInfo I = infos[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ns = (int)gridDim.y, sl = (int)blockIdx.y;
   double sx = 0.0, sy = 0.0, c1 = 0.0, c2 = 0.0;
   unsigned long long h = 0, nc = 0, rp = 0, nf = 0;
-  // four independent loads in flight per pass (the passes are latency bound)
   const int ntot = I.nx + I.ny, step = blockDim.x;
-  for (int k0 = threadIdx.x; k0 < ntot; k0 += 4 * step) {
+  const int kb = (int)((long long)ntot * sl / ns), ke = (int)((long long)ntot * (sl + 1) / ns);
+  // four independent loads in flight per pass (the passes are latency bound)
+  for (int k0 = kb + (int)threadIdx.x; k0 < ke; k0 += 4 * step) {
     TilePart T[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + u * step;
-      if (k < ntot) T[u] = parts[k < I.nx ? I.x0 + k : I.y0 + (k - I.nx)];
+      if (k < ke) T[u] = parts[k < I.nx ? I.x0 + k : I.y0 + (k - I.nx)];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + u * step;
-      if (k >= ntot) continue;
+      if (k >= ke) continue;
       if (k < I.nx) sx = T[u].smax > sx ? T[u].smax : sx;
       else sy = T[u].smax > sy ? T[u].smax : sy;
       c1 += T[u].clip1;
@@ -304,6 +313,23 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
     sy = red_d[1][w] > sy ? red_d[1][w] : sy;
     c1 += red_d[2][w]; c2 += red_d[3][w];
     h += red_u[0][w]; nc += red_u[1][w]; rp += red_u[2][w]; nf += red_u[3][w];
+  }
+  if (ns > 1) {
+    SliceRed* R = red + (size_t)blockIdx.x * ns;
+    R[sl] = SliceRed{sx, sy, c1, c2, h, nc, rp, nf};
+    __threadfence();  // the slice's result is visible before the arrival counts
+    if (atomicAdd(arrive + blockIdx.x, 1u) != (unsigned)(ns - 1)) return;
+    __threadfence();  // every slice's result is visible to this block
+    const volatile SliceRed* V = R;
+    sx = V[0].sx; sy = V[0].sy; c1 = V[0].c1; c2 = V[0].c2;
+    h = V[0].h; nc = V[0].nc; rp = V[0].rp; nf = V[0].nf;
+    for (int k = 1; k < ns; ++k) {
+      sx = V[k].sx > sx ? V[k].sx : sx;
+      sy = V[k].sy > sy ? V[k].sy : sy;
+      c1 += V[k].c1; c2 += V[k].c2;
+      h += V[k].h; nc += V[k].nc; rp += V[k].rp; nf += V[k].nf;
+    }
+    arrive[blockIdx.x] = 0u;  // ready for the next launch
   }
   LevelCtl& C = ctls[I.ctl];
   const double ax = sx / I.dx, ay = sy / I.dy;

@@ -255,8 +255,15 @@ __global__ void k_flag_dilate(const FlagLevel* __restrict__ Fs);
 __global__ void k_flag_raw_v(FlagLevel F);
 __global__ void k_flag_dilate_v(FlagLevel F);
 __global__ void k_flag_tiles(const FlagTiles* __restrict__ Ts);
+// Reduction of one slice of a (problem, level)'s tile partials when several
+// blocks share the reduction.
+struct SliceRed {
+  double sx, sy, c1, c2;
+  unsigned long long h, nc, rp, nf;
+};
+constexpr int AFTER_MAX_SLICES = 32;
 __global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, const TilePart* parts,
-                                double cflmax);
+                                double cflmax, SliceRed* red, unsigned* arrive);
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
 __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial);
 __global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);

@@ -385,6 +385,15 @@ int build_launch(mlswe_ctx* c, int l) {
   LL.cap_cp = capc[0];
   if ((rc = ensure(c, &LL.li, &LL.cap_li, 4 * LL.nli))) return rc;
   if ((rc = ensure(c, &LL.parts, &LL.cap_parts, LL.nxt + LL.nyt))) return rc;
+  // slices of the partial reduction: one block per problem, or up to 32 per
+  // problem when a problem has many tiles; the counters start (and are left)
+  // at zero
+  if ((rc = ensure(c, &LL.red, &LL.cap_red, AFTER_MAX_SLICES * std::max(1, LL.nli)))) return rc;
+  {
+    const int had = LL.cap_arrive;
+    if ((rc = ensure(c, &LL.arrive, &LL.cap_arrive, std::max(1, LL.nli)))) return rc;
+    if (LL.cap_arrive != had) HIPCHK(c, hipMemsetAsync(LL.arrive, 0, sizeof(unsigned) * LL.cap_arrive, c->stream));
+  }
   if (LL.nptch) {
     HIPCHK(c, hipMemcpyAsync(LL.pd[0], pd[0].data(), sizeof(PatchDev) * npd, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(LL.pd[1], pd[1].data(), sizeof(PatchDev) * npd, hipMemcpyHostToDevice, c->stream));
@@ -571,9 +580,12 @@ int launch_after(mlswe_ctx* c, int l, int p0, int p1, int runs) {
     n = LL.li_first[p] + 1 - first;
   }
   if (n == 0) return MLSWE_OK;
-  // one wave per problem suffices for a few tiles; a problem with many gets 16
-  hipLaunchKernelGGL(k_after_substep, dim3(n), dim3(LL.max_info_tiles > 256 ? 1024 : 64), 0, c->stream, c->ctl, c->cnt,
-                     LL.li + (size_t)runs * LL.nli + first, LL.parts, c->cfg.cfl_max);
+  // one wave per problem suffices for a few tiles; a problem with many gets 16,
+  // and one with thousands gets a block per 1024 of them (at most 32)
+  const int big = LL.max_info_tiles > 256;
+  const int slices = std::min(AFTER_MAX_SLICES, std::max(1, LL.max_info_tiles / 1024));
+  hipLaunchKernelGGL(k_after_substep, dim3(n, slices), dim3(big ? 1024 : 64), 0, c->stream, c->ctl, c->cnt,
+                     LL.li + (size_t)runs * LL.nli + first, LL.parts, c->cfg.cfl_max, LL.red, LL.arrive);
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }

@@ -186,6 +186,7 @@ int mlswe_destroy(mlswe_ctx* c) {
     }
   for (LevelLaunch& LL : c->launch) {
     dfree(LL.pd[0]); dfree(LL.pd[1]); dfree(LL.xt); dfree(LL.yt); dfree(LL.li); dfree(LL.parts);
+    dfree(LL.red); dfree(LL.arrive);
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
     dfree(LL.rfx); dfree(LL.rfx_reg);
   }
