@@ -57,7 +57,15 @@ typedef struct mlswe_config {
   int max_retries;    /* a coarse step whose largest substep Courant number exceeds
                          cfl_max is undone and retaken with dt scaled by
                          cfl_desired / that number, at most this often; -1 = never
-                         (the step then fails with MLSWE_ECFL), 0 = the default 8 */
+                         (the step then fails with MLSWE_ECFL), 0 = the default 8.
+                         mlswe_advance in MLSWE_BATCHED, MLSWE_GRAPH and
+                         MLSWE_PER_PATCH checks once per window of up to 32
+                         coarse steps (and before each regrid) with no host
+                         wait in between: the first failing substep halts the
+                         window on the device, and the run resumes from that
+                         step's retake, with results identical to a check
+                         after every step (which plain mode, dts_out, kernel
+                         timing, reflux and dynamic_rt keep) */
   int reflux;         /* 1: mass flux correction at coarse-fine edges (the paper has
                          none), within mlswe_advance (mlswe_step_level and
                          mlswe_coarsen called on their own leave it out): after a
@@ -268,6 +276,14 @@ int mlswe_get_counters(mlswe_ctx* ctx, int p, mlswe_counters* out);
 
 /* Waits for all work queued on the context's stream. */
 int mlswe_synchronize(mlswe_ctx* ctx);
+
+/* Host-side synchronisation counts since the context was created: the waits
+ * of the library's calls for the context's stream (advance, regrid, readbacks,
+ * launch-data uploads), and the coarse-step graphs captured and replayed.  A
+ * batched advance with retakes waits once per window of up to 32 coarse steps
+ * and once per regrid; the Courant check of paper Sec. 2 needs no other wait.
+ * Does not synchronise.  Errors: MLSWE_EINVAL (null argument). */
+int mlswe_sync_counts(mlswe_ctx* ctx, int64_t* host_waits, int64_t* graph_captures, int64_t* graph_launches);
 
 /* Kernel timing: when enabled, HIP events bracket every sweep launch on the
  * context's stream; mlswe_kernel_times returns, per kernel class (0: x-sweep,

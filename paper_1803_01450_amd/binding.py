@@ -88,6 +88,8 @@ def lib():
             "mlswe_advance": (I, [P, I, I, DP, I, I, DP]),
             "mlswe_get_counters": (I, [P, I, ctypes.POINTER(CountersC)]),
             "mlswe_synchronize": (I, [P]),
+            "mlswe_sync_counts": (I, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]),
             "mlswe_set_kernel_timing": (I, [P, I]),
             "mlswe_kernel_times": (I, [P, DP, ctypes.POINTER(ctypes.c_int64)]),
             "mlswe_phase_times": (I, [P, DP, ctypes.POINTER(ctypes.c_int64), I]),
@@ -354,6 +356,12 @@ class Solver:
 
     def synchronize(self):
         self._check(self.L.mlswe_synchronize(self.h))
+
+    def sync_counts(self):
+        """(host waits on the stream, graphs captured, graphs replayed) so far."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.L.mlswe_sync_counts(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return int(a.value), int(b.value), int(c.value)
 
     def set_kernel_timing(self, on=True):
         self._check(self.L.mlswe_set_kernel_timing(self.h, 1 if on else 0))

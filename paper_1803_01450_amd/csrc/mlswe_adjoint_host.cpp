@@ -150,11 +150,11 @@ extern "C" int mlswe_branch_signature(mlswe_ctx* c, int enable, int p, uint64_t*
     if (!valid_prob(c, p)) return fail(c, MLSWE_EINVAL, "bad problem %d", p);
     Counters h;
     HIPCHK(c, hipMemcpyAsync(&h, c->cnt + c->probs[p].cnt, sizeof h, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
     *sig_out = h.sig;
     h.sig = 0;
     HIPCHK(c, hipMemcpyAsync(c->cnt + c->probs[p].cnt, &h, sizeof h, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
   }
   return MLSWE_OK;
 }
@@ -182,7 +182,7 @@ extern "C" int mlswe_param_map_adjoint(mlswe_ctx* c, int p, const double* eta1_0
   const LevelH& L = c->probs[p].L[0];
   AdjBuf& A = c->probs[p].adj;
   if (A.status) {  // the adjoint steps so far: any non-wet edge fails the chain
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
     int st = 0;
     HIPCHK(c, hipMemcpy(&st, A.status, sizeof(int), hipMemcpyDeviceToHost));
     if (st) {

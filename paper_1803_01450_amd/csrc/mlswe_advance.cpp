@@ -191,45 +191,216 @@ int graph_step(mlswe_ctx* c, int p0, int p1) {
 // Backup (to_bk) or restore of a group's coarse-step start: the patch interiors
 // of its finer levels and the control blocks and counters of every problem,
 // in one launch.
-int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt) {
-  std::vector<CopyBox> boxes;
-  long long longest = 0;
-  auto add = [&](const double* from, double* to, long long pitch, long long plane, int nx, int ny, int nf) {
-    boxes.push_back(CopyBox{from, to, pitch, plane, nx, ny, nf, 0});
-    longest = std::max(longest, (long long)nx * ny * nf);
-  };
-  auto run = [&](double* live, double* saved, long long n) {
-    if (n > 0) add(to_bk ? live : saved, to_bk ? saved : live, 0, 0, (int)n, 1, 1);
-  };
-  static_assert(sizeof(LevelCtl) % sizeof(double) == 0 && sizeof(Counters) % sizeof(double) == 0, "copied as doubles");
-  run((double*)c->ctl, (double*)c->ctl_bk, (long long)nctl * (long long)(sizeof(LevelCtl) / sizeof(double)));
-  run((double*)c->cnt, (double*)c->cnt_bk, (long long)ncnt * (long long)(sizeof(Counters) / sizeof(double)));
-  for (int p = p0; p < p1; ++p) {
-    ProblemH& P = c->probs[p];
-    for (int l = 1; l < P.nlev; ++l) {
-      LevelH& L = P.L[l];
-      for (const Box& b : L.boxes) {
-        // pieces of whole rows, about 4096 doubles each over the six fields
-        const int rows = std::max(1, 4096 / (6 * b.nx));
-        for (int j = b.jlo; j < b.jlo + b.ny; j += rows) {
-          const long long off = idx(L, b.ilo, j);
-          double* q = L.q[L.cur] + off;
-          double* k = L.bk + off;
-          add(to_bk ? q : k, to_bk ? k : q, L.pitch, L.plane, b.nx, std::min(rows, b.jlo + b.ny - j), 6);
+int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt, bool mark) {
+  // the list depends on the launch data (generation), the direction and the
+  // buffer parity of every level: built and uploaded once per combination
+  std::vector<char> cur;
+  for (int p = p0; p < p1; ++p)
+    for (int l = 1; l < c->probs[p].nlev; ++l) cur.push_back((char)c->probs[p].L[l].cur);
+  for (auto it = c->box_lists.begin(); it != c->box_lists.end();) {
+    if (it->gen != c->generation) {
+      dfree(it->d);
+      it = c->box_lists.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  mlswe_ctx::BoxList* hit = nullptr;
+  for (auto& b : c->box_lists)
+    if (b.to_bk == to_bk && b.p0 == p0 && b.p1 == p1 && b.cur == cur) hit = &b;
+  if (!hit) {
+    std::vector<CopyBox> boxes;
+    long long longest = 0;
+    auto add = [&](const double* from, double* to, long long pitch, long long plane, int nx, int ny, int nf) {
+      boxes.push_back(CopyBox{from, to, pitch, plane, nx, ny, nf, 0});
+      longest = std::max(longest, (long long)nx * ny * nf);
+    };
+    auto run = [&](double* live, double* saved, long long n) {
+      if (n > 0) add(to_bk ? live : saved, to_bk ? saved : live, 0, 0, (int)n, 1, 1);
+    };
+    static_assert(sizeof(LevelCtl) % sizeof(double) == 0 && sizeof(Counters) % sizeof(double) == 0,
+                  "copied as doubles");
+    run((double*)c->ctl, (double*)c->ctl_bk, (long long)nctl * (long long)(sizeof(LevelCtl) / sizeof(double)));
+    run((double*)c->cnt, (double*)c->cnt_bk, (long long)ncnt * (long long)(sizeof(Counters) / sizeof(double)));
+    for (int p = p0; p < p1; ++p) {
+      ProblemH& P = c->probs[p];
+      for (int l = 1; l < P.nlev; ++l) {
+        LevelH& L = P.L[l];
+        for (const Box& b : L.boxes) {
+          // pieces of whole rows, about 4096 doubles each over the six fields
+          const int rows = std::max(1, 4096 / (6 * b.nx));
+          for (int j = b.jlo; j < b.jlo + b.ny; j += rows) {
+            const long long off = idx(L, b.ilo, j);
+            double* q = L.q[L.cur] + off;
+            double* k = L.bk + off;
+            add(to_bk ? q : k, to_bk ? k : q, L.pitch, L.plane, b.nx, std::min(rows, b.jlo + b.ny - j), 6);
+          }
         }
       }
     }
+    if (c->box_lists.size() >= 32) {  // a bound on the cache: drop the oldest
+      HIPCHK(c, host_wait(c));
+      dfree(c->box_lists.front().d);
+      c->box_lists.erase(c->box_lists.begin());
+    }
+    mlswe_ctx::BoxList bl;
+    bl.to_bk = to_bk; bl.cur = cur; bl.gen = c->generation; bl.p0 = p0; bl.p1 = p1; bl.d = nullptr;
+    bl.n = (int)boxes.size(); bl.longest = longest;
+    int rc;
+    if ((rc = dalloc(c, (void**)&bl.d, sizeof(CopyBox) * boxes.size()))) return rc;
+    HIPCHK(c, hipMemcpyAsync(bl.d, boxes.data(), sizeof(CopyBox) * boxes.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, host_wait(c));  // the host vector goes out of scope
+    c->box_lists.push_back(bl);
+    hit = &c->box_lists.back();
   }
-  int rc;
-  if ((rc = ensure(c, &c->boxes_d, &c->boxes_cap, (int)boxes.size()))) return rc;
-  HIPCHK(c, hipMemcpyAsync(c->boxes_d, boxes.data(), sizeof(CopyBox) * boxes.size(), hipMemcpyHostToDevice, c->stream));
-  // a block per piece of up to 4096 doubles (sixteen per thread)
-  const unsigned gx = (unsigned)std::min<long long>(64, (longest + 4095) / 4096);
-  for (size_t k0 = 0; k0 < boxes.size(); k0 += 65535)  // grid y is at most 65535
-    hipLaunchKernelGGL(k_copy_boxes, dim3(gx, (unsigned)std::min<size_t>(65535, boxes.size() - k0)), dim3(256), 0,
-                       c->stream, c->boxes_d + k0);
+  const unsigned gx = (unsigned)std::min<long long>(64, (hit->longest + 4095) / 4096);
+  const int nboxes = hit->n;
+  CopyBox* boxes_d = hit->d;
+  // backups skip once a deferred window has halted (and the first launch counts
+  // the backup); restores always run
+  for (int k0 = 0; k0 < nboxes; k0 += 65535)  // grid y is at most 65535
+    hipLaunchKernelGGL(k_copy_boxes, dim3(gx, (unsigned)std::min(65535, nboxes - k0)), dim3(256), 0, c->stream,
+                       boxes_d + k0, to_bk ? c->halt : nullptr, (mark && k0 == 0) ? 1 : 0);
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
+}
+
+// Host bookkeeping of a coarse step's start: buffer parity and update count of
+// every level of every problem of a group, problem-major.
+struct StepMark {
+  std::vector<int> cur;
+  std::vector<long long> upd;
+};
+
+// Records the group's step start and makes sure its backup arrays exist.
+int mark_step(mlswe_ctx* c, int p0, int p1, int nctl, int ncnt, StepMark& m) {
+  int rc;
+  if ((rc = ensure(c, &c->ctl_bk, &c->bk_cap, nctl))) return rc;
+  if ((rc = ensure(c, &c->cnt_bk, &c->cbk_cap, ncnt))) return rc;
+  m.cur.clear();
+  m.upd.clear();
+  for (int p = p0; p < p1; ++p) {
+    ProblemH& P = c->probs[p];
+    for (int l = 0; l < P.nlev; ++l) {
+      LevelH& L = P.L[l];
+      m.cur.push_back(L.cur);
+      m.upd.push_back(P.updates[l]);
+      if (l == 0 || L.boxes.empty()) continue;
+      const size_t sb = sizeof(double) * 6 * (size_t)L.plane;
+      if (!L.bk && (rc = dalloc(c, (void**)&L.bk, sb))) return rc;
+    }
+  }
+  return MLSWE_OK;
+}
+
+// The group's coarse step itself: replayed from a graph, or launched.
+int run_step(mlswe_ctx* c, int p0, int p1, int mode) {
+  const bool together = mode == MLSWE_BATCHED || mode == MLSWE_GRAPH;
+  bool all_dt = true;
+  for (int p = p0; p < p1; ++p) all_dt = all_dt && c->probs[p].have_dt;
+  if (mode == MLSWE_GRAPH && all_dt && !c->timing) return graph_step(c, p0, p1);
+  return coarse_step(c, p0, p1, together);
+}
+
+// The control blocks of every problem in pinned memory, and (want_halt) the
+// halt words after them, in one synchronised copy each.
+int read_controls(mlswe_ctx* c, int nctl, bool want_halt, const LevelCtl** h, const unsigned** hw) {
+  const size_t need = (size_t)nctl * sizeof(LevelCtl) + 64;
+  if (need > c->ctl_pin_cap) {
+    if (c->ctl_pin) (void)hipHostFree(c->ctl_pin);
+    c->ctl_pin = nullptr;
+    c->ctl_pin_cap = 0;
+    HIPCHK(c, hipHostMalloc((void**)&c->ctl_pin, 2 * need, hipHostMallocDefault));
+    c->ctl_pin_cap = 2 * need;
+  }
+  unsigned* words = (unsigned*)((char*)c->ctl_pin + (size_t)nctl * sizeof(LevelCtl));
+  HIPCHK(c, hipMemcpyAsync(c->ctl_pin, c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToHost, c->stream));
+  if (want_halt)
+    HIPCHK(c, hipMemcpyAsync(words, c->halt, HALT_WORDS * sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, host_wait(c));
+  *h = c->ctl_pin;
+  if (hw) *hw = words;
+  return MLSWE_OK;
+}
+
+// From the control blocks after a step: each problem's largest substep Courant
+// number; a problem above cfl_max gets dt scaled by cfl_desired / that number
+// for its retake, the others keep theirs.  MLSWE_ENAN on a non-finite state.
+int judge(mlswe_ctx* c, int p0, int p1, const LevelCtl* h, std::vector<double>& dt0, bool* any) {
+  *any = false;
+  dt0.assign((size_t)(p1 - p0), 0.0);
+  for (int p = p0; p < p1; ++p) {
+    const ProblemH& P = c->probs[p];
+    double cm = 0.0;
+    bool nan = false;
+    for (int l = 0; l < P.nlev; ++l) {
+      const double v = h[P.ctl0 + l].cmax;
+      if (v != v || (h[P.ctl0 + l].status & STATUS_NAN)) nan = true;
+      else if (v > cm) cm = v;
+    }
+    const double dtp = h[P.ctl0].dt;
+    if (nan) return fail(c, MLSWE_ENAN, "non-finite state or Courant number in problem %d", p);
+    if (cm > c->cfg.cfl_max) {
+      *any = true;
+      dt0[p - p0] = dtp * (c->cfg.cfl_desired / cm);
+    } else {
+      dt0[p - p0] = dtp;
+    }
+  }
+  return MLSWE_OK;
+}
+
+void accept_step(mlswe_ctx* c, int p0, int p1, const LevelCtl* h) {
+  for (int p = p0; p < p1; ++p) {
+    ProblemH& P = c->probs[p];
+    for (int l = 0; l < P.nlev; ++l) {
+      P.last_acc[l][0] = h[P.ctl0 + l].acc_smax[0];
+      P.last_acc[l][1] = h[P.ctl0 + l].acc_smax[1];
+    }
+    P.acc_known = true;
+  }
+}
+
+// Retakes a rejected coarse step of the group: host bookkeeping back to the
+// step's start m, patch interiors, controls and counters from the backup, dt0
+// for every problem, the subcycled recursion again; checked after each
+// attempt until it passes or max_retries retakes are spent.
+int retake(mlswe_ctx* c, int p0, int p1, bool together, const StepMark& m, std::vector<double> dt0, int nctl,
+           int ncnt) {
+  int rc;
+  const int np = p1 - p0;
+  for (int attempt = 1;; ++attempt) {
+    if (attempt > c->cfg.max_retries) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
+    size_t k = 0;
+    for (int p = p0; p < p1; ++p) {
+      ProblemH& P = c->probs[p];
+      P.rejected++;
+      for (int l = 0; l < P.nlev; ++l, ++k) {
+        P.L[l].cur = m.cur[k];
+        P.updates[l] = m.upd[k];
+      }
+    }
+    if ((rc = copy_step_start(c, p0, p1, false, nctl, ncnt, false))) return rc;
+    if ((rc = ensure(c, &c->dt0_d, &c->dt0_cap, np))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->dt0_d, dt0.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_set_dt0, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, c->dt0_d, np);
+    HIPCHK(c, hipGetLastError());
+    if ((rc = adv(c, 0, p0, p1, 0.0, together))) return rc;
+    const LevelCtl* h = nullptr;
+    if ((rc = read_controls(c, nctl, false, &h, nullptr))) return rc;
+    bool any = false;
+    if ((rc = judge(c, p0, p1, h, dt0, &any))) return rc;
+    if (!any) {
+      accept_step(c, p0, p1, h);
+      return MLSWE_OK;
+    }
+  }
+}
+
+void counts(const mlswe_ctx* c, int* nctl, int* ncnt) {
+  *nctl = 0;
+  for (const ProblemH& P : c->probs) *nctl += P.nlev;
+  *ncnt = (int)c->probs.size();
 }
 
 // A coarse step of problems [p0, p1) with rejection: when the largest substep
@@ -238,102 +409,90 @@ int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt
 // level 0 keeps its input buffer through a step) and the step is retaken, the
 // failing problems with dt scaled by cfl_desired / that number, the others
 // unchanged.  Frames and uncovered cells of the finer levels are refilled or
-// unused before they are read again, so the backup leaves them out.
+// unused before they are read again, so the backup leaves them out.  The check
+// waits for the step (one host round trip per coarse step).
 int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
   int rc;
-  // one launch per level substep over the group's patches, or one per patch
   const bool together = mode == MLSWE_BATCHED || mode == MLSWE_GRAPH;
-  const bool retry = c->cfg.max_retries > 0;
-  int nctl = 0;
-  for (const ProblemH& P : c->probs) nctl += P.nlev;
-  const int ncnt = (int)c->probs.size();
-  std::vector<int> cur0;
-  std::vector<long long> upd0;
-  if (retry) {
-    if ((rc = ensure(c, &c->ctl_bk, &c->bk_cap, nctl))) return rc;
-    if ((rc = ensure(c, &c->cnt_bk, &c->cbk_cap, ncnt))) return rc;
-    for (int p = p0; p < p1; ++p) {
-      ProblemH& P = c->probs[p];
-      for (int l = 0; l < P.nlev; ++l) {
-        LevelH& L = P.L[l];
-        cur0.push_back(L.cur);
-        upd0.push_back(P.updates[l]);
-        if (l == 0 || L.boxes.empty()) continue;
-        const size_t sb = sizeof(double) * 6 * (size_t)L.plane;
-        if (!L.bk && (rc = dalloc(c, (void**)&L.bk, sb))) return rc;
-      }
-    }
-    if ((rc = copy_step_start(c, p0, p1, true, nctl, ncnt))) return rc;
+  if (c->cfg.max_retries <= 0) return run_step(c, p0, p1, mode);
+  int nctl, ncnt;
+  counts(c, &nctl, &ncnt);
+  StepMark m;
+  if ((rc = mark_step(c, p0, p1, nctl, ncnt, m))) return rc;
+  if ((rc = copy_step_start(c, p0, p1, true, nctl, ncnt, false))) return rc;
+  if ((rc = run_step(c, p0, p1, mode))) return rc;
+  const LevelCtl* h = nullptr;
+  if ((rc = read_controls(c, nctl, false, &h, nullptr))) return rc;
+  std::vector<double> dt0;
+  bool any = false;
+  if ((rc = judge(c, p0, p1, h, dt0, &any))) return rc;
+  if (!any) {
+    accept_step(c, p0, p1, h);
+    return MLSWE_OK;
   }
-  bool all_dt = true;
-  for (int p = p0; p < p1; ++p) all_dt = all_dt && c->probs[p].have_dt;
-  if (mode == MLSWE_GRAPH && all_dt && !c->timing)
-    rc = graph_step(c, p0, p1);
-  else
-    rc = coarse_step(c, p0, p1, together);
-  if (rc || !retry) return rc;
-  const int np = p1 - p0;
-  std::vector<double> dt0(np);
-  for (int attempt = 0;; ++attempt) {
-    if ((size_t)nctl * sizeof(LevelCtl) > c->ctl_pin_cap) {
-      if (c->ctl_pin) (void)hipHostFree(c->ctl_pin);
-      c->ctl_pin = nullptr;
-      c->ctl_pin_cap = 0;
-      HIPCHK(c, hipHostMalloc((void**)&c->ctl_pin, 2 * (size_t)nctl * sizeof(LevelCtl), hipHostMallocDefault));
-      c->ctl_pin_cap = 2 * (size_t)nctl * sizeof(LevelCtl);
-    }
-    const LevelCtl* h = c->ctl_pin;  // pinned: the readback is one short DMA
-    HIPCHK(c, hipMemcpyAsync(c->ctl_pin, c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    bool any = false;
-    for (int p = p0; p < p1; ++p) {
-      const ProblemH& P = c->probs[p];
-      double cm = 0.0;
-      bool nan = false;
-      for (int l = 0; l < P.nlev; ++l) {
-        const double v = h[P.ctl0 + l].cmax;
-        if (v != v || (h[P.ctl0 + l].status & STATUS_NAN)) nan = true;
-        else if (v > cm) cm = v;
-      }
-      const double dtp = h[P.ctl0].dt;
-      if (nan || cm > c->cfg.cfl_max) {
-        if (nan) return fail(c, MLSWE_ENAN, "non-finite state or Courant number in problem %d", p);
-        any = true;
-        dt0[p - p0] = dtp * (c->cfg.cfl_desired / cm);
-      } else {
-        dt0[p - p0] = dtp;
-      }
-    }
-    if (!any) {
-      for (int p = p0; p < p1; ++p) {
-        ProblemH& P = c->probs[p];
-        for (int l = 0; l < P.nlev; ++l) {
-          P.last_acc[l][0] = h[P.ctl0 + l].acc_smax[0];
-          P.last_acc[l][1] = h[P.ctl0 + l].acc_smax[1];
-        }
-        P.acc_known = true;
-      }
-      return MLSWE_OK;
-    }
-    if (attempt + 1 > c->cfg.max_retries) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
-    // put the group back
-    size_t k = 0;
-    for (int p = p0; p < p1; ++p) {
-      ProblemH& P = c->probs[p];
-      P.rejected++;
-      for (int l = 0; l < P.nlev; ++l, ++k) {
-        LevelH& L = P.L[l];
-        L.cur = cur0[k];
-        P.updates[l] = upd0[k];
-      }
-    }
-    if ((rc = copy_step_start(c, p0, p1, false, nctl, ncnt))) return rc;
-    if ((rc = ensure(c, &c->dt0_d, &c->dt0_cap, np))) return rc;
-    HIPCHK(c, hipMemcpyAsync(c->dt0_d, dt0.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(k_set_dt0, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, c->dt0_d, np);
+  return retake(c, p0, p1, together, m, dt0, nctl, ncnt);
+}
+
+// Deferred checks: the steps of a window run back to back with no host wait.
+// Each takes its backup and counts it; the substep reduction that first finds
+// a Courant number above the limit halts the window, after which the backups,
+// outputs, coarsening, dt rule and reductions of the following kernels do
+// nothing.  One readback at the window's end either accepts every step or
+// finds the first failing one (the backup holds its start), puts the group
+// back there and retakes it as step_with_retry does; the steps after it are
+// then run again.  Results are those of step_with_retry bit for bit.
+int deferred_step(mlswe_ctx* c, int mode, std::vector<StepMark>& win) {
+  int rc;
+  const int np = (int)c->probs.size();
+  int nctl, ncnt;
+  counts(c, &nctl, &ncnt);
+  if (win.empty()) {
+    hipLaunchKernelGGL(k_set_halt, dim3(1), dim3(64), 0, c->stream, c->halt, 1u);
     HIPCHK(c, hipGetLastError());
-    if ((rc = adv(c, 0, p0, p1, 0.0, together))) return rc;
+    c->armed = true;
   }
+  win.emplace_back();
+  if ((rc = mark_step(c, 0, np, nctl, ncnt, win.back()))) return rc;
+  if ((rc = copy_step_start(c, 0, np, true, nctl, ncnt, true))) return rc;
+  return run_step(c, 0, np, mode);
+}
+
+int disarm(mlswe_ctx* c) {
+  if (!c->armed) return MLSWE_OK;
+  c->armed = false;
+  hipLaunchKernelGGL(k_set_halt, dim3(1), dim3(64), 0, c->stream, c->halt, 0u);
+  HIPCHK(c, hipGetLastError());
+  return MLSWE_OK;
+}
+
+// kept: how many of the window's steps stand once it is checked (all, or up to
+// and including the retaken first failure).
+int verify_window(mlswe_ctx* c, int mode, std::vector<StepMark>& win, int* kept) {
+  int rc;
+  const int np = (int)c->probs.size();
+  const bool together = mode == MLSWE_BATCHED || mode == MLSWE_GRAPH;
+  int nctl, ncnt;
+  counts(c, &nctl, &ncnt);
+  const LevelCtl* h = nullptr;
+  const unsigned* hw = nullptr;
+  if ((rc = read_controls(c, nctl, true, &h, &hw))) return rc;
+  const bool halted = hw[HALT_SET] != 0;
+  const int f = (int)hw[HALT_MARKS] - 1;
+  if ((rc = disarm(c))) return rc;
+  std::vector<double> dt0;
+  bool any = false;
+  if ((rc = judge(c, 0, np, h, dt0, &any))) return rc;
+  if (!halted) {
+    if (any) return fail(c, MLSWE_ESTATE, "deferred check: a failing step did not halt its window");
+    accept_step(c, 0, np, h);
+    *kept = (int)win.size();
+    return MLSWE_OK;
+  }
+  if (!any || f < 0 || f >= (int)win.size())
+    return fail(c, MLSWE_ESTATE, "deferred check: halted window without a failing step");
+  if ((rc = retake(c, 0, np, together, win[f], dt0, nctl, ncnt))) return rc;
+  *kept = f + 1;
+  return MLSWE_OK;
 }
 
 }  // namespace mlswe_host
@@ -361,7 +520,20 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
   // launch per level substep; per-patch: one launch per patch) or one problem
   // at a time with one launch per patch (plain)
   const int ngroups = together ? 1 : np;
-  for (int n = 0; n < nsteps; ++n) {
+  // batched, graph and per-patch steps with retakes check the Courant number
+  // once per window of up to 32 coarse steps (and before every regrid) instead
+  // of after every step; per-step readbacks (dts_out, timing, the dynamic time
+  // ratio's speeds) and the flux correction keep the per-step check
+  const bool defer = together && c->cfg.max_retries > 0 && !dts_out && !c->timing && !c->cfg.reflux &&
+                     !c->cfg.dynamic_rt;
+  constexpr int WINDOW = 32;
+  std::vector<StepMark> win;
+  struct Guard {
+    mlswe_ctx* c;
+    ~Guard() { (void)disarm(c); }
+  } guard{c};
+  int n = 0;
+  while (n < nsteps) {
     int rc;
     if (regrid_every > 0 && n % regrid_every == 0) {
       const auto t0 = std::chrono::steady_clock::now();
@@ -373,6 +545,17 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
     }
     if (c->cfg.dynamic_rt && (rc = choose_time_ratios(c))) return rc;
     if ((rc = build_pdt(c))) return rc;
+    if (defer) {
+      if ((rc = deferred_step(c, mode, win))) return rc;
+      ++n;
+      if ((int)win.size() >= WINDOW || n == nsteps || (regrid_every > 0 && n % regrid_every == 0)) {
+        int kept = 0;
+        if ((rc = verify_window(c, mode, win, &kept))) return rc;
+        n -= (int)win.size() - kept;
+        win.clear();
+      }
+      continue;
+    }
     for (int gi = 0; gi < ngroups; ++gi) {
       const int p0 = together ? 0 : gi, p1 = together ? np : gi + 1;
       if ((rc = step_with_retry(c, p0, p1, mode))) return rc;
@@ -385,6 +568,7 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
       if ((rc = read_ctls(c, 0, np, h))) return rc;
       for (int p = 0; p < np; ++p) dts_out[(size_t)p * nsteps + n] = h[c->probs[p].ctl0].dt;
     }
+    ++n;
   }
   int status = 0;
   int rc = read_status(c, 0, np, &status);
@@ -397,7 +581,7 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
 int mlswe_get_counters(mlswe_ctx* c, int p, mlswe_counters* out) {
   if (!c) return MLSWE_EINVAL;
   if (!valid_prob(c, p) || !out) return fail(c, MLSWE_EINVAL, "bad args");
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   Counters h;
   HIPCHK(c, hipMemcpy(&h, c->cnt + c->probs[p].cnt, sizeof h, hipMemcpyDeviceToHost));
   mlswe_counters o;
@@ -420,7 +604,7 @@ int mlswe_get_counters(mlswe_ctx* c, int p, mlswe_counters* out) {
 
 int mlswe_synchronize(mlswe_ctx* c) {
   if (!c) return MLSWE_EINVAL;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   return MLSWE_OK;
 }
 
@@ -447,6 +631,14 @@ int mlswe_kernel_times(mlswe_ctx* c, double* ms_out, int64_t* launches_out) {
   if (rc) return rc;
   ms_out[0] = c->kms[0]; ms_out[1] = c->kms[1];
   launches_out[0] = c->klaunch[0]; launches_out[1] = c->klaunch[1];
+  return MLSWE_OK;
+}
+
+int mlswe_sync_counts(mlswe_ctx* c, int64_t* host_waits, int64_t* graph_captures, int64_t* graph_launches) {
+  if (!c || !host_waits || !graph_captures || !graph_launches) return MLSWE_EINVAL;
+  *host_waits = c->host_waits;
+  *graph_captures = c->graph_captures;
+  *graph_launches = c->graph_launches;
   return MLSWE_OK;
 }
 

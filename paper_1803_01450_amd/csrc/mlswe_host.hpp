@@ -109,8 +109,7 @@ struct LevelLaunch {
   TilePart* parts = nullptr;                 // per tile: x tiles, then y tiles
   int cap_parts = 0;
   SliceRed* red = nullptr;                   // slice results of the partial reduction
-  unsigned* arrive = nullptr;                // its arrival counters (zero between launches)
-  int cap_red = 0, cap_arrive = 0;
+  int cap_red = 0;
   int max_info_tiles = 0;                    // most tiles of one problem on the level
   FillPatch* fp[4] = {nullptr, nullptr, nullptr, nullptr};   // [fine parity * 2 + coarse parity]
   CoarsenPatch* cp[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -167,6 +166,8 @@ struct mlswe_ctx {
   mlswe_tuning tune;
   int ncu = 256;
   unsigned* tickets = nullptr;  // [2] atomic work tickets of the persistent sweeps
+  unsigned* halt = nullptr;     // [HALT_WORDS] halt words of deferred Courant checks
+  bool armed = false;           // a deferred window is open (halt words armed)
   // graph replay of whole coarse steps
   hipStream_t cap_stream = nullptr;
   long long generation = 0;      // bumped whenever launch data may have changed
@@ -180,13 +181,24 @@ struct mlswe_ctx {
   };
   std::vector<GraphRec> graphs;
   long long graph_launches = 0, graph_captures = 0;
+  long long host_waits = 0;  // waits of the host on the context's stream
   LevelCtl* ctl_bk = nullptr;
   Counters* cnt_bk = nullptr;
   int bk_cap = 0, cbk_cap = 0;
   double* dt0_d = nullptr;
   int dt0_cap = 0;
-  CopyBox* boxes_d = nullptr;  // copy list of a coarse step's backup / restore
-  int boxes_cap = 0;
+  // copy lists uploaded for the current launch data, by (direction, buffer
+  // parities of the group's levels): a backup is one launch with no upload
+  struct BoxList {
+    bool to_bk;
+    std::vector<char> cur;  // buffer parity of every level above 0 of the group
+    long long gen;
+    int p0, p1;
+    CopyBox* d;
+    int n;
+    long long longest;
+  };
+  std::vector<BoxList> box_lists;
   LevelCtl* ctl_pin = nullptr;  // pinned readback of the control blocks
   size_t ctl_pin_cap = 0;
   unsigned char* pin = nullptr;  // pinned staging of the regrid flags
@@ -216,6 +228,11 @@ namespace mlswe_host {
   } while (0)
 
 inline long long idx(const LevelH& L, int i, int j) { return (long long)(j + 2) * L.pitch + (i + XOFF); }
+// The host waits for the context's stream (every such wait is counted).
+inline hipError_t host_wait(mlswe_ctx* c) {
+  c->host_waits++;
+  return hipStreamSynchronize(c->stream);
+}
 inline unsigned blocks(long long n) { return (unsigned)((n + 255) / 256); }
 inline bool valid_prob(mlswe_ctx* c, int p) { return p >= 0 && p < (int)c->probs.size(); }
 
@@ -258,7 +275,7 @@ int choose_time_ratios(mlswe_ctx* c);
 int build_all(mlswe_ctx* c);
 int coarse_step(mlswe_ctx* c, int p0, int p1, bool batched);
 int graph_step(mlswe_ctx* c, int p0, int p1);
-int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt);
+int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt, bool mark);
 int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode);
 
 // grow-only device array

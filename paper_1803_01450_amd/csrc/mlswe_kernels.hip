@@ -127,6 +127,7 @@ __global__ __launch_bounds__(256) void k_refine_new(const FillPatch* __restrict_
 // (row-major sum times 1/r^2) for all six fields, then the dry-state fix-up.
 __global__ __launch_bounds__(256) void k_coarsen(const CoarsenPatch* __restrict__ cps) {
   const CoarsenPatch& C = cps[blockIdx.y];
+  if (C.halt[HALT_SET]) return;
   const int r = C.r;
   const int cnx = C.bnx / r, cny = C.bny / r;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -254,15 +255,43 @@ __global__ __launch_bounds__(256) void k_flag_tiles(const FlagTiles* __restrict_
 // adds the fix-up and clamp counts to the problem's counters.  Speeds are kept
 // as the bit patterns of non-negative doubles.  Block size: a multiple of 64,
 // at most 1024.
+// The end of a (problem, level)'s substep reduction: the Courant check,
+// status bits, speeds and counters from the reduced partials.
+__device__ __forceinline__ void after_tail(LevelCtl* ctls, Counters* cnts, const LevelInfo& I, double sx, double sy,
+                                           double c1, double c2, unsigned long long h, unsigned long long nc,
+                                           unsigned long long rp, unsigned long long nf, double cflmax,
+                                           unsigned* halt) {
+  // a halted window keeps the failing substep's control block and counters
+  if (halt[HALT_SET]) return;
+  LevelCtl& C = ctls[I.ctl];
+  const double ax = sx / I.dx, ay = sy / I.dy;
+  const double courant = C.dt * (ax > ay ? ax : ay);
+  if (halt[HALT_ARMED] && (!(courant <= cflmax) || nf)) halt[HALT_SET] = 1u;
+  if (courant > C.cmax || courant != courant) C.cmax = courant;
+  if (!(courant <= cflmax)) C.status |= STATUS_CFL;
+  if (nf) C.status |= STATUS_NAN;
+  const unsigned long long bx = (unsigned long long)__double_as_longlong(sx);
+  const unsigned long long by = (unsigned long long)__double_as_longlong(sy);
+  C.last_smax[0] = bx;
+  C.last_smax[1] = by;
+  if (bx > C.acc_smax[0]) C.acc_smax[0] = bx;
+  if (by > C.acc_smax[1]) C.acc_smax[1] = by;
+  Counters& K = cnts[I.cnt];
+  K.hyp += h;
+  K.nclip += nc;
+  K.repair += rp;
+  if (c1 != 0.0) K.clip1 += c1;
+  if (c2 != 0.0) K.clip2 += c2;
+}
+
 // Block (x, y) of a grid of (problems, slices) reduces slice y of problem x's
 // partials (its x tiles, then its y tiles, cut into gridDim.y equal slices).
 // With one slice the block finishes the problem itself; with several, each
-// block leaves its slice's result in red and the last block to arrive (by an
-// atomic counter it then sets back to zero) combines the slices in slice order,
-// so the result does not depend on which block comes last.
+// block leaves its slice's result in red and k_after_combine, launched next,
+// combines the slices in slice order.
 __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos,
                                                         const TilePart* parts, double cflmax, SliceRed* red,
-                                                        unsigned* arrive) {
+                                                        unsigned* halt) {
   __shared__ double red_d[4][16];
   __shared__ unsigned long long red_u[4][16];
   const LevelInfo I = infos[blockIdx.x];
@@ -315,40 +344,28 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
     h += red_u[0][w]; nc += red_u[1][w]; rp += red_u[2][w]; nf += red_u[3][w];
   }
   if (ns > 1) {
-    SliceRed* R = red + (size_t)blockIdx.x * ns;
-    R[sl] = SliceRed{sx, sy, c1, c2, h, nc, rp, nf};
-    __threadfence();  // the slice's result is visible before the arrival counts
-    if (atomicAdd(arrive + blockIdx.x, 1u) != (unsigned)(ns - 1)) return;
-    __threadfence();  // every slice's result is visible to this block
-    const volatile SliceRed* V = R;
-    sx = V[0].sx; sy = V[0].sy; c1 = V[0].c1; c2 = V[0].c2;
-    h = V[0].h; nc = V[0].nc; rp = V[0].rp; nf = V[0].nf;
-    for (int k = 1; k < ns; ++k) {
-      sx = V[k].sx > sx ? V[k].sx : sx;
-      sy = V[k].sy > sy ? V[k].sy : sy;
-      c1 += V[k].c1; c2 += V[k].c2;
-      h += V[k].h; nc += V[k].nc; rp += V[k].rp; nf += V[k].nf;
-    }
-    arrive[blockIdx.x] = 0u;  // ready for the next launch
+    red[(size_t)blockIdx.x * ns + sl] = SliceRed{sx, sy, c1, c2, h, nc, rp, nf};
+    return;
   }
-  LevelCtl& C = ctls[I.ctl];
-  const double ax = sx / I.dx, ay = sy / I.dy;
-  const double courant = C.dt * (ax > ay ? ax : ay);
-  if (courant > C.cmax || courant != courant) C.cmax = courant;
-  if (!(courant <= cflmax)) C.status |= STATUS_CFL;
-  if (nf) C.status |= STATUS_NAN;
-  const unsigned long long bx = (unsigned long long)__double_as_longlong(sx);
-  const unsigned long long by = (unsigned long long)__double_as_longlong(sy);
-  C.last_smax[0] = bx;
-  C.last_smax[1] = by;
-  if (bx > C.acc_smax[0]) C.acc_smax[0] = bx;
-  if (by > C.acc_smax[1]) C.acc_smax[1] = by;
-  Counters& K = cnts[I.cnt];
-  K.hyp += h;
-  K.nclip += nc;
-  K.repair += rp;
-  if (c1 != 0.0) K.clip1 += c1;
-  if (c2 != 0.0) K.clip2 += c2;
+  after_tail(ctls, cnts, I, sx, sy, c1, c2, h, nc, rp, nf, cflmax, halt);
+}
+
+// One thread per problem: its ns slice results combined in slice order, then
+// the end of the reduction.
+__global__ void k_after_combine(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, int n, int ns,
+                                const SliceRed* __restrict__ red, double cflmax, unsigned* halt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const SliceRed* R = red + (size_t)i * ns;
+  double sx = R[0].sx, sy = R[0].sy, c1 = R[0].c1, c2 = R[0].c2;
+  unsigned long long h = R[0].h, nc = R[0].nc, rp = R[0].rp, nf = R[0].nf;
+  for (int k = 1; k < ns; ++k) {
+    sx = R[k].sx > sx ? R[k].sx : sx;
+    sy = R[k].sy > sy ? R[k].sy : sy;
+    c1 += R[k].c1; c2 += R[k].c2;
+    h += R[k].h; nc += R[k].nc; rp += R[k].rp; nf += R[k].nf;
+  }
+  after_tail(ctls, cnts, infos[i], sx, sy, c1, c2, h, nc, rp, nf, cflmax, halt);
 }
 
 // Largest initial signal speed max(|u|,|v|) + sqrt(g (h1 + h2)) over covered cells.
@@ -386,9 +403,10 @@ __global__ __launch_bounds__(256) void k_initial_speed(const SpeedLevel* __restr
 
 // Next coarse dt of each problem from the speeds of its last coarse step (or, on
 // the first step, the initial signal speed), then the levels' substep dt.
-__global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial) {
+__global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial,
+                          const unsigned* halt) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprob) return;
+  if (p >= nprob || halt[HALT_SET]) return;
   const ProbDt& D = pd[p];
   const double inf = __longlong_as_double(0x7ff0000000000000ll);
   double best = inf;
@@ -630,7 +648,13 @@ __global__ __launch_bounds__(256) void k_mask_boxes(const MaskBox* __restrict__ 
 // Many box copies in one launch: block row y copies box y; its elements are
 // numbered column-fastest over the (field, row) lines and strided over the
 // block row's threads.
-__global__ __launch_bounds__(256) void k_copy_boxes(const CopyBox* __restrict__ boxes) {
+// halt (nullable): a backup of a coarse step's start, skipped once a deferred
+// window has halted; mark: this launch counts the backup in HALT_MARKS.
+__global__ __launch_bounds__(256) void k_copy_boxes(const CopyBox* __restrict__ boxes, unsigned* halt, int mark) {
+  if (halt) {
+    if (halt[HALT_SET]) return;
+    if (mark && halt[HALT_ARMED] && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) halt[HALT_MARKS] += 1u;
+  }
   const CopyBox C = boxes[blockIdx.y];
   const unsigned nx = (unsigned)C.nx, ny = (unsigned)C.ny;
   const unsigned n = nx * ny * (unsigned)C.nf;
@@ -639,6 +663,15 @@ __global__ __launch_bounds__(256) void k_copy_boxes(const CopyBox* __restrict__ 
     const unsigned f = line / ny, b = line - f * ny;
     const long long off = (long long)f * C.plane + (long long)b * C.pitch + a;
     C.dst[off] = C.src[off];
+  }
+}
+
+// Halt words cleared, armed (1) for a deferred window or disarmed (0).
+__global__ void k_set_halt(unsigned* halt, unsigned armed) {
+  if (threadIdx.x == 0) {
+    halt[HALT_SET] = 0u;
+    halt[HALT_MARKS] = 0u;
+    halt[HALT_ARMED] = armed;
   }
 }
 

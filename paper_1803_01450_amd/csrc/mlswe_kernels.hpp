@@ -9,6 +9,16 @@ constexpr int XTILE_COLS = 60;  // interior columns per x-sweep wave (64 lanes -
 constexpr int STATUS_CFL = 1;
 constexpr int STATUS_NAN = 2;
 
+// Halt words of a context (device memory), for coarse steps whose Courant
+// check is deferred: while HALT_ARMED is set, the first substep reduction that
+// finds a Courant number above the limit (or a non-finite state) sets
+// HALT_SET, and from then on the kernels that would change what a retake
+// needs (y-sweep outputs, coarsening, the dt rule, the step-start backups and
+// the substep reductions' results) do nothing, so the backup still holds the
+// failing step's start.  HALT_MARKS counts the backups taken while armed and
+// not halted: the failing step's index in the window plus one.
+constexpr int HALT_SET = 0, HALT_MARKS = 1, HALT_ARMED = 2, HALT_WORDS = 4;
+
 struct Counters {
   unsigned long long hyp, nclip, repair;
   double clip1, clip2;
@@ -41,6 +51,7 @@ struct PatchDev {
   PhysParams P;
   int sig_on;        // accumulate the branch signature into cnt->sig
   const unsigned char* mask;  // coverage of the level (bits below)
+  const unsigned* halt;       // the context's halt words (HALT_*)
 };
 
 // Coverage byte of a level cell: interior of some patch, and whether the cell
@@ -82,6 +93,7 @@ struct CoarsenPatch {
   long long fpitch, fplane, cpitch, cplane;
   int ilo, jlo, bnx, bny, r;
   PhysParams P;
+  const unsigned* halt;
 };
 
 struct FlagLevel {
@@ -263,9 +275,12 @@ struct SliceRed {
 };
 constexpr int AFTER_MAX_SLICES = 32;
 __global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, const TilePart* parts,
-                                double cflmax, SliceRed* red, unsigned* arrive);
+                                double cflmax, SliceRed* red, unsigned* halt);
+__global__ void k_after_combine(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, int n, int ns,
+                                const SliceRed* __restrict__ red, double cflmax, unsigned* halt);
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
-__global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial);
+__global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial,
+                          const unsigned* halt);
 __global__ void k_nan_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, int nx, int ny);
 __global__ void k_zero_uncovered(double* q, const unsigned char* __restrict__ mask, long long pitch, long long plane,
                                  int nx, int ny);
@@ -279,7 +294,8 @@ struct CopyBox {
   long long pitch, plane;
   int nx, ny, nf, pad;
 };
-__global__ void k_copy_boxes(const CopyBox* __restrict__ boxes);
+__global__ void k_copy_boxes(const CopyBox* __restrict__ boxes, unsigned* halt, int mark);
+__global__ void k_set_halt(unsigned* halt, unsigned armed);
 // Byte runs: copied (src set) or filled with a value (src null).
 struct ByteSeg {
   const unsigned char* src;

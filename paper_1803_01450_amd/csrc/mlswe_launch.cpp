@@ -251,6 +251,7 @@ int build_launch(mlswe_ctx* c, int l) {
         d.dx = L.dx; d.dy = L.dy; d.P = P.P;
         d.sig_on = c->sig_on;
         d.mask = L.mask;
+        d.halt = c->halt;
         pd[par].push_back(d);
       }
       LL.patch_prob.push_back((int)pi);
@@ -289,6 +290,7 @@ int build_launch(mlswe_ctx* c, int l) {
         cc.fpitch = L.pitch; cc.fplane = L.plane; cc.cpitch = Cl->pitch; cc.cplane = Cl->plane;
         cc.ilo = b.ilo; cc.jlo = b.jlo; cc.bnx = b.nx; cc.bny = b.ny; cc.r = P.ratio[l - 1];
         cc.P = P.P;
+        cc.halt = c->halt;
       } else {
         f.coarse_none = 1;
         f.r = 1;
@@ -385,15 +387,9 @@ int build_launch(mlswe_ctx* c, int l) {
   LL.cap_cp = capc[0];
   if ((rc = ensure(c, &LL.li, &LL.cap_li, 4 * LL.nli))) return rc;
   if ((rc = ensure(c, &LL.parts, &LL.cap_parts, LL.nxt + LL.nyt))) return rc;
-  // slices of the partial reduction: one block per problem, or up to 32 per
-  // problem when a problem has many tiles; the counters start (and are left)
-  // at zero
+  // slice results of the partial reduction (one block per problem, or up to 32
+  // per problem when a problem has many tiles)
   if ((rc = ensure(c, &LL.red, &LL.cap_red, AFTER_MAX_SLICES * std::max(1, LL.nli)))) return rc;
-  {
-    const int had = LL.cap_arrive;
-    if ((rc = ensure(c, &LL.arrive, &LL.cap_arrive, std::max(1, LL.nli)))) return rc;
-    if (LL.cap_arrive != had) HIPCHK(c, hipMemsetAsync(LL.arrive, 0, sizeof(unsigned) * LL.cap_arrive, c->stream));
-  }
   if (LL.nptch) {
     HIPCHK(c, hipMemcpyAsync(LL.pd[0], pd[0].data(), sizeof(PatchDev) * npd, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(LL.pd[1], pd[1].data(), sizeof(PatchDev) * npd, hipMemcpyHostToDevice, c->stream));
@@ -417,7 +413,7 @@ int build_launch(mlswe_ctx* c, int l) {
       HIPCHK(c, hipMemcpyAsync(LL.rfx, rfx.data(), sizeof(RefluxCell) * LL.nrfx, hipMemcpyHostToDevice, c->stream));
   }
   // host vectors must outlive the asynchronous copies
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   LL.dirty = false;
   return MLSWE_OK;
 }
@@ -449,7 +445,7 @@ int build_pdt(mlswe_ctx* c) {
   int rc = ensure(c, &c->pdt, &c->pdt_cap, (int)v.size());
   if (rc) return rc;
   HIPCHK(c, hipMemcpyAsync(c->pdt, v.data(), sizeof(ProbDt) * v.size(), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   c->pdt_dirty = false;
   return MLSWE_OK;
 }
@@ -469,7 +465,7 @@ int ev_begin(mlswe_ctx* c, hipEvent_t* e) {
 
 int collect_events(mlswe_ctx* c) {
   if (c->ev_used.empty()) return MLSWE_OK;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   for (auto& u : c->ev_used) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, u.second.first, u.second.second));
@@ -581,11 +577,18 @@ int launch_after(mlswe_ctx* c, int l, int p0, int p1, int runs) {
   }
   if (n == 0) return MLSWE_OK;
   // one wave per problem suffices for a few tiles; a problem with many gets 16,
-  // and one with thousands gets a block per 1024 of them (at most 32)
+  // and one with tens of thousands gets a block per 8192 of them (at most 32),
+  // combined by a second launch
   const int big = LL.max_info_tiles > 256;
-  const int slices = std::min(AFTER_MAX_SLICES, std::max(1, LL.max_info_tiles / 1024));
-  hipLaunchKernelGGL(k_after_substep, dim3(n, slices), dim3(big ? 1024 : 64), 0, c->stream, c->ctl, c->cnt,
-                     LL.li + (size_t)runs * LL.nli + first, LL.parts, c->cfg.cfl_max, LL.red, LL.arrive);
+  const int slices = std::min(AFTER_MAX_SLICES, std::max(1, LL.max_info_tiles / 8192));
+  const LevelInfo* li = LL.li + (size_t)runs * LL.nli + first;
+  hipLaunchKernelGGL(k_after_substep, dim3(n, slices), dim3(big ? 1024 : 64), 0, c->stream, c->ctl, c->cnt, li,
+                     LL.parts, c->cfg.cfl_max, LL.red, c->halt);
+  if (slices > 1) {
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_after_combine, dim3((n + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->cnt, li, n, slices,
+                       LL.red, c->cfg.cfl_max, c->halt);
+  }
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;
 }
@@ -760,11 +763,11 @@ int next_dt(mlswe_ctx* c, int p0, int p1, bool initial) {
     HIPCHK(c, hipMemcpyAsync(c->spd, sl.data(), sizeof(SpeedLevel) * sl.size(), hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_initial_speed, dim3(64, (unsigned)sl.size()), dim3(256), 0, c->stream, c->spd);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
   }
   return timed(c, 6, [&]() -> int {
     hipLaunchKernelGGL(k_next_dt, dim3((p1 - p0 + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, p1 - p0,
-                       c->cfg.cfl_desired, initial ? 1 : 0);
+                       c->cfg.cfl_desired, initial ? 1 : 0, c->halt);
     HIPCHK(c, hipGetLastError());
     return MLSWE_OK;
   });
@@ -775,7 +778,7 @@ int read_ctls(mlswe_ctx* c, int p0, int p1, std::vector<LevelCtl>& h) {
   const int a = c->probs[p0].ctl0, b = c->probs[p1 - 1].ctl0 + c->probs[p1 - 1].nlev;
   h.resize((size_t)(b - a));
   HIPCHK(c, hipMemcpyAsync(h.data(), c->ctl + a, sizeof(LevelCtl) * h.size(), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   return MLSWE_OK;
 }
 

@@ -60,7 +60,7 @@ int copy_state(mlswe_ctx* c, LevelH& L, int buf, const double* src, int where, b
   }
   // device-to-device copies stay ordered on the stream; host memory is released
   // to the caller only once the copy is done
-  if (where != MLSWE_DEVICE) HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (where != MLSWE_DEVICE) HIPCHK(c, host_wait(c));
   return MLSWE_OK;
 }
 
@@ -160,8 +160,16 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
   c->tune.grid_x = 1;
   c->tune.grid_y = 1;
   if (dalloc(c, (void**)&c->tickets, 2 * sizeof(unsigned)) != MLSWE_OK) { delete c; return MLSWE_ENOMEM; }
+  if (dalloc(c, (void**)&c->halt, HALT_WORDS * sizeof(unsigned)) != MLSWE_OK ||
+      hipMemsetAsync(c->halt, 0, HALT_WORDS * sizeof(unsigned), c->stream) != hipSuccess) {
+    dfree(c->tickets);
+    dfree(c->halt);
+    delete c;
+    return MLSWE_ENOMEM;
+  }
   if (scratch_setup(c) != MLSWE_OK) {
     dfree(c->tickets);
+    dfree(c->halt);
     delete c;
     return MLSWE_EDEVICE;
   }
@@ -171,7 +179,7 @@ int mlswe_create(const mlswe_config* cfg, void* hip_stream, mlswe_ctx** out) {
 
 int mlswe_destroy(mlswe_ctx* c) {
   if (!c) return MLSWE_EINVAL;
-  (void)hipStreamSynchronize(c->stream);
+  (void)host_wait(c);
   for (ProblemH& P : c->probs) {
     dfree(P.adj.lam1); dfree(P.adj.lamS); dfree(P.adj.lamG); dfree(P.adj.cL); dfree(P.adj.cR);
     dfree(P.adj.Bbx); dfree(P.adj.Bby); dfree(P.adj.status);
@@ -186,13 +194,14 @@ int mlswe_destroy(mlswe_ctx* c) {
     }
   for (LevelLaunch& LL : c->launch) {
     dfree(LL.pd[0]); dfree(LL.pd[1]); dfree(LL.xt); dfree(LL.yt); dfree(LL.li); dfree(LL.parts);
-    dfree(LL.red); dfree(LL.arrive);
+    dfree(LL.red);
     for (int k = 0; k < 4; ++k) { dfree(LL.fp[k]); dfree(LL.cp[k]); }
     dfree(LL.rfx); dfree(LL.rfx_reg);
   }
   dfree(c->ctl); dfree(c->cnt); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
-  dfree(c->tickets); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d); dfree(c->boxes_d);
+  dfree(c->tickets); dfree(c->halt); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d);
   dfree(c->bsegs_d); dfree(c->mboxes_d); dfree(c->rfills_d); dfree(c->flv_d);
+  for (auto& bl : c->box_lists) dfree(bl.d);
   dfree(c->ftl_d); dfree(c->tbits_d); dfree(c->lrep_d);
   if (c->pin) (void)hipHostFree(c->pin);
   if (c->ctl_pin) (void)hipHostFree(c->ctl_pin);
@@ -269,7 +278,7 @@ int mlswe_problem_define(mlswe_ctx* c, int* p_out, double r, int nx0, int ny0, d
     HIPCHK(c, hipMemsetAsync(ncn, 0, sizeof(Counters) * ccap, c->stream));
     if (c->ctl) HIPCHK(c, hipMemcpyAsync(nc, c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToDevice, c->stream));
     if (c->cnt) HIPCHK(c, hipMemcpyAsync(ncn, c->cnt, sizeof(Counters) * pidx, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
     dfree(c->ctl); dfree(c->cnt);
     c->ctl = nc; c->cnt = ncn; c->ctl_cap = ncap; c->cnt_cap = ccap;
     for (int l = 0; l < MAXLEV; ++l) c->launch[l].dirty = true;  // descriptors hold ctl pointers
@@ -317,7 +326,7 @@ int mlswe_set_bathymetry(mlswe_ctx* c, int p, const double* Bf, int where) {
     }
     mirror_frame_host(L, a);
     HIPCHK(c, hipMemcpyAsync(L.B, a.data(), sizeof(double) * a.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
     prev.swap(a);
   }
   P.bathy = true;
@@ -372,7 +381,7 @@ int mlswe_get_step_state(mlswe_ctx* c, int p, double* out) {
   const ProblemH& P = c->probs[p];
   std::vector<LevelCtl> h((size_t)P.nlev);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->ctl + P.ctl0, sizeof(LevelCtl) * h.size(), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   out[0] = h[0].t;
   out[1] = P.have_dt ? 1.0 : 0.0;
   for (int l = 0; l < P.nlev; ++l) {
@@ -399,14 +408,14 @@ int mlswe_set_step_state(mlswe_ctx* c, int p, const double* in) {
       return fail(c, MLSWE_EINVAL, "speed %g of level %d is not finite and non-negative", in[2 + l], l / 2);
   std::vector<LevelCtl> h((size_t)P.nlev);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->ctl + P.ctl0, sizeof(LevelCtl) * h.size(), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   h[0].t = in[0];
   for (int l = 0; l < P.nlev; ++l) {
     h[l].acc_smax[0] = (unsigned long long)__builtin_bit_cast(long long, in[2 + 2 * l]);
     h[l].acc_smax[1] = (unsigned long long)__builtin_bit_cast(long long, in[3 + 2 * l]);
   }
   HIPCHK(c, hipMemcpyAsync(c->ctl + P.ctl0, h.data(), sizeof(LevelCtl) * h.size(), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   P.have_dt = in[1] != 0.0;
   P.acc_known = false;
   return MLSWE_OK;
@@ -454,7 +463,7 @@ int mlswe_step_level(mlswe_ctx* c, int level, const double* dt, double theta, do
   }
   if ((rc = substep(c, level, 0, np, theta, true))) return rc;
   if (smax_out) {
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
     int status = 0;
     for (int p = 0; p < np; ++p) {
       LevelCtl h;
@@ -474,7 +483,7 @@ int mlswe_coarsen(mlswe_ctx* c, int p, int fine_level) {
   if (!valid_prob(c, p) || fine_level < 1 || fine_level >= c->probs[p].nlev) return fail(c, MLSWE_EINVAL, "bad level");
   int rc = coarsen_level(c, fine_level, p, p + 1);
   if (rc) return rc;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   return MLSWE_OK;
 }
 
@@ -531,7 +540,7 @@ int mlswe_refine_layers(mlswe_ctx* c, int M, int r, const double* qc, const doub
   if (repairs_out) {
     unsigned long long n = 0;
     HIPCHK(c, hipMemcpyAsync(&n, c->lrep_d, sizeof n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
     *repairs_out = (int64_t)n;
   }
   return MLSWE_OK;

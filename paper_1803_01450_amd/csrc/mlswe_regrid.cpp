@@ -41,7 +41,7 @@ std::vector<Box> cluster_tiles(int fnx, int fny, const unsigned char* bits) {
 int upload_mask(mlswe_ctx* c, LevelH& L) {
   host_mask(L);
   HIPCHK(c, hipMemcpyAsync(L.mask, L.mask_h.data(), L.mask_h.size(), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   return MLSWE_OK;
 }
 
@@ -141,7 +141,7 @@ int set_patches_impl(mlswe_ctx* c, int p, int l, int n, const int32_t* bx) {
     HIPCHK(c, hipMemcpyAsync(fd, f.data(), sizeof(FillPatch) * f.size(), hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_refine_new, dim3((maxn + 255) / 256, (unsigned)f.size()), dim3(256), 0, c->stream, fd);
     hipError_t e = hipGetLastError();
-    hipError_t s = hipStreamSynchronize(c->stream);
+    hipError_t s = host_wait(c);
     dfree(fd);
     c->bytes -= (long long)(sizeof(FillPatch) * f.size());
     if (e != hipSuccess || s != hipSuccess)
@@ -169,7 +169,7 @@ int flag_impl(mlswe_ctx* c, int p, int l, double tau, int nbuf, std::vector<unsi
   HIPCHK(c, hipGetLastError());
   out.resize((size_t)L.nx * L.ny);
   HIPCHK(c, hipMemcpyAsync(out.data(), L.fout, out.size(), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   return MLSWE_OK;
 }
 
@@ -243,7 +243,7 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
     }
     HIPCHK(c, hipGetLastError());
     if (total > c->pin_cap) {
-      HIPCHK(c, hipStreamSynchronize(c->stream));
+      HIPCHK(c, host_wait(c));
       if (c->pin) (void)hipHostFree(c->pin);
       c->pin = nullptr;
       c->pin_cap = 0;
@@ -251,7 +251,7 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
       c->pin_cap = total;
     }
     HIPCHK(c, hipMemcpyAsync(c->pin, c->tbits_d, total, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
     // host: clusters, then the new layouts
     std::vector<std::vector<Box>> nbs(who.size());
     for (size_t k = 0; k < who.size(); ++k) {
@@ -311,7 +311,7 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
     HIPCHK(c, hipGetLastError());
     // the descriptor lists above are host vectors read by the copies: wait
     // before they go out of scope (one wait per level of the regrid)
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, host_wait(c));
   }
   return MLSWE_OK;
 }

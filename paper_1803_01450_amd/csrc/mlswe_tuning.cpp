@@ -107,7 +107,7 @@ extern "C" int mlswe_autotune(mlswe_ctx* c, const char* cache_path, int reps) {
   const int ncnt = (int)c->probs.size();
   std::vector<LevelCtl> ctl_save(nctl);
   std::vector<Counters> cnt_save(ncnt);
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   HIPCHK(c, hipMemcpy(ctl_save.data(), c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(cnt_save.data(), c->cnt, sizeof(Counters) * ncnt, hipMemcpyDeviceToHost));
   const int scheds[5][2] = {{0, 0}, {1, 1}, {1, 2}, {2, 1}, {2, 2}};
@@ -135,7 +135,7 @@ extern "C" int mlswe_autotune(mlswe_ctx* c, const char* cache_path, int reps) {
       }
   }
   c->timing = saved_timing;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, host_wait(c));
   HIPCHK(c, hipMemcpy(c->ctl, ctl_save.data(), sizeof(LevelCtl) * nctl, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->cnt, cnt_save.data(), sizeof(Counters) * ncnt, hipMemcpyHostToDevice));
   if (rc) return rc;

@@ -118,10 +118,14 @@ def test_adjoint_full_size_central_differences():
     forward (eps 1e-4 m on eta1; 0.5 m on B, since 1 cm on a 4 km column is below
     the rounding noise of the misfit).  The discrete map is only piecewise
     smooth (MC limiter branches): the branch signature shows how many +-eps runs
-    switch a branch somewhere in the 4e8 edge solves, and such switches bias the
-    differences, so the bar is statistical: over cells whose gradient stands
-    above the noise floor, median relative error <= 1e-3 and worst <= 5e-2.  The
-    exact derivative is pinned on the 64x64 copy against the oracle."""
+    switch a branch somewhere in the 4e8 edge solves (on the MI355X each of the
+    64 cells has such a run, so none can be held to a tight bar), and such
+    switches bias the differences, so this is a report with a
+    statistical bar: over cells whose gradient stands above the noise floor,
+    median relative error <= 1e-3 and worst <= 5e-2 (measured: 2.2e-5 and
+    2.4e-2, 14 of 40 within 1e-5).  The exact derivative is held to 1e-9
+    against the oracle's dual numbers on 256^2 over 400 steps in four
+    directions (test_adjoint_matches_oracle_dual_256_full_run)."""
     import torch
     say("case: adjoint 1024^2, 400 steps, FD at 64 cells")
     n, nsteps = 1024, 400

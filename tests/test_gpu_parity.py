@@ -310,6 +310,77 @@ def test_rejected_step_matches_oracle():
         S.close()
 
 
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_deferred_check_retakes_like_per_step_check(mode):
+    """Without per-step readbacks the library checks the Courant number once
+    per window of coarse steps (the first failing substep halts the window);
+    the run must retake the same steps as a run checked after every step
+    (dts requested) and as the oracle: same rejections, bit-identical states,
+    the same simulated time."""
+    say("case: deferred Courant check, batch problem 301, mode", mode)
+    c = inputs.batch_problem(301, 152)
+    n = 152
+    Bf = np.kron(c["B"], np.ones((2, 2)))
+    tau = [[2e-5, 0.0]]
+
+    def run(want):
+        S = solver()
+        p = S.define(n, n, c["dx"], c["dx"], c["r"], (2,))
+        S.set_bathymetry(p, Bf)
+        S.set_state(p, 0, c["q"])
+        S.advance(22, 10, tau, mode=mode, want_dts=want)
+        return S, p
+
+    A, pa = run(False)
+    B, pb = run(True)
+    H = oracle.Hierarchy(n, n, c["dx"], c["dx"], ratios=(2,), r=c["r"])
+    H.set_bathymetry(Bf); H.set_state(0, c["q"])
+    rc, _ = H.advance(22, 10, [2e-5])
+    assert rc == 0
+    ca, cb, co = A.counters(pa), B.counters(pb), H.counters()
+    say("rejected: deferred", ca["rejected"], "per step", cb["rejected"], "oracle", co["rejected"])
+    assert ca["rejected"] == cb["rejected"] == co["rejected"] >= 1
+    assert ca["t"] == cb["t"]
+    assert ca["updates"] == cb["updates"] == co["updates"]
+    for l in range(2):
+        x, y = A.state(pa, l), B.state(pb, l)
+        assert np.array_equal(np.isnan(x), np.isnan(y))
+        m = ~np.isnan(x)
+        assert np.array_equal(x[m], y[m]), l
+        assert rel_err(x, H.state(l)).max() <= 1e-9
+    A.close(); B.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_coarse_steps_without_host_waits(mode):
+    """Between regrids a batched (1) or graph (2) advance with retakes waits for
+    the stream once per window of 32 coarse steps plus once at its end (the
+    final status): 64 steps of four two-level problems take at most 3 waits,
+    no graph is captured after the first window, and every coarse step of the
+    graph mode is one replay."""
+    say("case: host waits per coarse step, mode", mode)
+    S = solver()
+    n = 96
+    for k in range(4):
+        c = inputs.batch_problem(400 + k, n)
+        p = S.define(n, n, c["dx"], c["dx"], c["r"], (2,))
+        S.set_bathymetry(p, np.kron(c["B"], np.ones((2, 2))))
+        S.set_state(p, 0, c["q"])
+    S.advance(4, 4, [[2e-5, 0.0]] * 4, mode=mode)  # regrid, launch data, graphs
+    rej0 = sum(S.counters(p)["rejected"] for p in range(4))
+    w0, c0, g0 = S.sync_counts()
+    S.advance(64, 0, None, mode=mode)
+    w1, c1, g1 = S.sync_counts()
+    rej = sum(S.counters(p)["rejected"] for p in range(4)) - rej0
+    say("waits", w1 - w0, "captures", c1 - c0, "replays", g1 - g0, "retakes", rej)
+    # a retake (none expected here) re-checks its window's rest step by step
+    assert w1 - w0 <= 3 + 40 * rej
+    if mode == 2 and rej == 0:
+        assert c1 - c0 == 0
+        assert g1 - g0 == 64
+    S.close()
+
+
 # ---------------------------------------------------------------- full size
 def test_roofline_grid_sampled_windows():
     """The 4096^2 grid in the benchmark's launch configuration: one step, checked
