@@ -6,13 +6,15 @@
 // the x- and y-sweeps.  A sweep updates cell k of a line by
 //   out_k = q_k - nu ((A+dQ_k - F_k) + (A-dQ_{k+1} + F_{k+1}))
 // where edge k lies between cells k-1 and k and F is the limited correction
-// flux.  Its adjoint is computed per edge: the thread of edge e recomputes the
-// waves of edges e-1, e, e+1, gathers the adjoint of its own waves from its
-// fluctuations, its correction flux and the correction fluxes of its
-// neighbours whose limiter looks at it, and pushes it back through the edge
-// solve onto its two cells.  A gather pass sums the two edge contributions of
-// every cell; a fold pass maps ghost cells back through the walls.
+// flux.  Its adjoint is computed per edge: the lane of edge e solves it once,
+// gathers the adjoint of its own waves from its fluctuations, its correction
+// flux and the correction fluxes of its neighbours whose limiter looks at it
+// (their waves and limiter terms come from the neighbouring lanes), and pushes
+// it back through the edge solve onto its two cells; each cell then sums the
+// contributions of its two edges with its own output adjoint, in the same
+// kernel.  A fold pass maps ghost cells back through the walls.
 #include "mlswe_kernels.hpp"
+#include "mlswe_wave.hpp"
 
 namespace mlswe {
 
@@ -20,6 +22,10 @@ namespace {
 
 __device__ __forceinline__ long long aidx(const AdjView& V, int line, int k) {
   return V.base + (long long)line * V.lstride + (long long)k * V.kstride;
+}
+
+__device__ __forceinline__ long long lidx(const AdjView& V, int line, int k) {
+  return V.lbase + (long long)line * V.llstride + (long long)k * V.lkstride;
 }
 
 // Cell seen along the line (normal / transverse momenta by orientation).
@@ -41,8 +47,8 @@ __device__ __forceinline__ void adj_lam(const AdjView& V, int line, int k, doubl
     for (int c = 0; c < 6; ++c) l[c] = 0.0;
     return;
   }
-  const long long id = aidx(V, line, k);
-  const long long pl = V.plane;
+  const long long id = lidx(V, line, k);
+  const long long pl = V.lplane;
   const int fm1 = V.orient ? 2 : 1, ft1 = V.orient ? 1 : 2;
   const int fm2 = V.orient ? 5 : 4, ft2 = V.orient ? 4 : 5;
   l[0] = V.lam[id]; l[1] = V.lam[fm1 * pl + id]; l[2] = V.lam[ft1 * pl + id];
@@ -318,50 +324,65 @@ __device__ __forceinline__ void add_zbar(WaveBar& B, const EdgeW& W, int p, cons
 
 }  // namespace
 
-// One thread per edge e in [-1, n + 1] of every line.
-__global__ __launch_bounds__(256) void k_adj_edges(AdjView V) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long ne = (long long)V.n + 3;
-  if (t >= ne * V.nlines) return;
-  // neighbouring threads take neighbouring memory: along the line when the
-  // line is contiguous (x), across lines otherwise (y)
-  const int line = V.orient ? (int)(t % V.nlines) : (int)(t / ne);
-  const int e = (V.orient ? (int)(t / V.nlines) : (int)(t % ne)) - 1;
-  const int n = V.n;
-  const double nu = V.nu;
-  const bool hasPrev = e >= 0;      // edge e-1 exists (its left cell is >= -2)
-  const bool hasNext = e <= n;      // edge e+1 exists (its right cell is <= n+1)
-  CellX Cm1 = adj_cell(V, line, e - 1), C0 = adj_cell(V, line, e);
-  CellX Cm2, Cp1;
-  EdgeW Wm, W, Wp;
-  bool ok = all_wet(Cm1) && all_wet(C0);
-  riemann(V.P, Cm1, C0, W);
-  if (hasPrev) { Cm2 = adj_cell(V, line, e - 2); ok = ok && all_wet(Cm2); riemann(V.P, Cm2, Cm1, Wm); }
-  if (hasNext) { Cp1 = adj_cell(V, line, e + 1); ok = ok && all_wet(Cp1); riemann(V.P, C0, Cp1, Wp); }
-  if (!ok) { atomicOr(V.status, 1); return; }
-  // adjoints of the outputs of cells e-2 .. e+1
-  double lm2[6], lm1[6], l0[6], lp1[6];
-  adj_lam(V, line, e - 2, lm2);
-  adj_lam(V, line, e - 1, lm1);
-  adj_lam(V, line, e, l0);
-  adj_lam(V, line, e + 1, lp1);
+// Edge adjoints, one solve and one limiter evaluation per edge.  A wave takes
+// 64 consecutive edges of one line, e = 61 s - 3 + L on lane L of segment s;
+// the waves of edges e - 1 and e + 1 come from lanes L - 1 and L + 1 by
+// whole-wave rotations.  Lanes 1..62 own their edges (own: in range and not
+// an end lane), lanes 0 and 63 lend their waves and limiter terms.  The term by which a neighbour's limiter
+// looks at edge e is the neighbour's own coefficient dnu (the adjoint of its
+// ratio's numerator) times the neighbour's wave, so each lane evaluates only
+// its own limiter and passes dnu on.  Per edge the contributions are: the
+// edge's fluctuations and correction flux, the correction fluxes of the
+// neighbours whose limiter reads it, and (through its own limiter ratio) the
+// upwind neighbour's wave; they are pushed back through the edge solve onto
+// its two cells (ol: left cell, orr: right cell, line-local field order).
+// Src gives the line's cells and output adjoints by position along the line.
+template <class Src>
+__device__ __forceinline__ void adj_edge_lane(const Src& src, const PhysParams& P, double nu, int n, int e,
+                                              bool exists, int* status, bool own, double ol[7], double orr[7]) {
+  const bool hasPrev = e >= 0, hasNext = e <= n;
+  EdgeW W;
+  int okc;
+  {
+    CellX Cm1, C0;
+    if (exists) {
+      Cm1 = src.cell(e - 1);
+      C0 = src.cell(e);
+    } else {
+      Cm1 = load_cell(P, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0);  // a still, flat edge, lent to no owned lane
+      C0 = Cm1;
+    }
+    okc = all_wet(Cm1) && all_wet(C0);
+    riemann(P, Cm1, C0, W);
+  }
+  const int okm = shup_i(okc), okp = shdn_i(okc);
+  const bool ok = okc && (!hasPrev || okm) && (!hasNext || okp);
+  double dotp[6], dotm[6];
+  {
+    const EdgeW Wp = shdn_edge(W);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) dotp[p] = hasNext ? wdot(W, Wp, p) : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    dotm[p] = shup(dotp[p]);
+    if (!hasPrev) dotm[p] = 0.0;
+  }
   WaveBar Bw;
 #pragma unroll
   for (int p = 0; p < 4; ++p) { Bw.Ab[p] = 0.0; Bw.Cb[p] = 0.0; }
 #pragma unroll
   for (int p = 0; p < 6; ++p) Bw.sb[p] = 0.0;
   Bw.v1b = 0.0; Bw.v2b = 0.0; Bw.z4b = 0.0; Bw.z5b = 0.0;
-  double dd[6], ddm[6], ddp[6], dotm[6], dotp[6];
+  // own fluctuations and correction flux (edges 0..n feed the updates; the
+  // end lanes too, their dnu serves the owned lanes beside them)
+  double dnu[6];
 #pragma unroll
-  for (int p = 0; p < 6; ++p) {
-    dd[p] = wdot(W, W, p);
-    ddm[p] = hasPrev ? wdot(Wm, Wm, p) : 0.0;
-    ddp[p] = hasNext ? wdot(Wp, Wp, p) : 0.0;
-    dotm[p] = hasPrev ? wdot(Wm, W, p) : 0.0;
-    dotp[p] = hasNext ? wdot(W, Wp, p) : 0.0;
-  }
-  // own fluctuations and correction flux (edges 0..n feed the updates)
-  if (e >= 0 && e <= n) {
+  for (int p = 0; p < 6; ++p) dnu[p] = 0.0;
+  if (exists && e >= 0 && e <= n) {
+    double l0[6], lm1[6];
+    src.lam(e, l0);
+    src.lam(e - 1, lm1);
     double Fb[6], amb[6], apb[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -375,9 +396,9 @@ __global__ __launch_bounds__(256) void k_adj_edges(AdjView V) {
       const int md = slot_mode(W, p);
       const double wm = md == 2 ? 0.0 : (sv < 0.0 ? 1.0 : (sv == 0.0 ? 0.5 : 0.0));
       const double wp = md == 1 ? 0.0 : (sv > 0.0 ? 1.0 : (sv == 0.0 ? 0.5 : 0.0));
-      double z[6], u[6];
+      double z[6];
       wvec(W, p, z);
-      LimP Lm = lim_of(W, p, dd[p], dotm[p], dotp[p], nu);
+      LimP Lm = lim_of(W, p, wdot(W, W, p), dotm[p], dotp[p], nu);
       double coefb = 0.0, X[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
@@ -389,102 +410,238 @@ __global__ __launch_bounds__(256) void k_adj_edges(AdjView V) {
         const double sgn = sv > 0.0 ? 1.0 : -1.0;
         Bw.sb[p] += coefb * Lm.phi * Lm.sg * (-nu * sgn);
         const double thb = coefb * Lm.K * Lm.dphi;
-        const double dnb = thb / Lm.dd;
         const double ddb = -thb * Lm.th / Lm.dd;
-        const EdgeW& Up = sv > 0.0 ? Wm : Wp;
-        wvec(Up, p, u);
+        dnu[p] = thb / Lm.dd;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) X[c] = dnb * u[c] + 2.0 * ddb * z[c];
+        for (int c = 0; c < 6; ++c) X[c] = 2.0 * ddb * z[c];
         add_zbar(Bw, W, p, X);
       }
     }
   }
-  // correction flux of edge e-1 whose limiter looks at edge e (left-going waves)
-  if (e - 1 >= 0 && e - 1 <= n) {
-    double Fb[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) Fb[c] = nu * (lm1[c] - lm2[c]);
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      if (!(Wm.s[p] < 0.0)) continue;
-      LimP Lm = lim_of(Wm, p, ddm[p], 0.0, dotm[p], nu);
-      if (!Lm.on) continue;
-      double z[6];
-      wvec(Wm, p, z);
-      double coefb = 0.0;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) coefb += Fb[c] * z[c];
-      const double dnb = coefb * Lm.K * Lm.dphi / Lm.dd;
-      double X[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) X[c] = dnb * z[c];
-      add_zbar(Bw, W, p, X);
-    }
-  }
-  // correction flux of edge e+1 whose limiter looks at edge e (right-going waves)
-  if (e + 1 >= 0 && e + 1 <= n) {
-    double Fb[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) Fb[c] = nu * (lp1[c] - l0[c]);
+  {
+    // edge e+1: its right-going waves' limiter reads edge e; edge e's
+    // left-going waves' limiter reads edge e+1
+    const EdgeW Wp = shdn_edge(W);
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
-      if (!(Wp.s[p] > 0.0)) continue;
-      LimP Lm = lim_of(Wp, p, ddp[p], dotp[p], 0.0, nu);
-      if (!Lm.on) continue;
-      double z[6];
-      wvec(Wp, p, z);
-      double coefb = 0.0;
+      const double dn = shdn(dnu[p]);
+      double X[6], u[6];
+      if (hasNext && Wp.s[p] > 0.0 && dn != 0.0) {
+        wvec(Wp, p, u);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) coefb += Fb[c] * z[c];
-      const double dnb = coefb * Lm.K * Lm.dphi / Lm.dd;
-      double X[6];
+        for (int c = 0; c < 6; ++c) X[c] = dn * u[c];
+        add_zbar(Bw, W, p, X);
+      }
+      if (!(W.s[p] > 0.0) && dnu[p] != 0.0) {
+        wvec(Wp, p, u);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) X[c] = dnb * z[c];
-      add_zbar(Bw, W, p, X);
+        for (int c = 0; c < 6; ++c) X[c] = dnu[p] * u[c];
+        add_zbar(Bw, W, p, X);
+      }
     }
   }
-  CellBar Lb, Rb;
-  zero_cb(Lb);
-  zero_cb(Rb);
-  riemann_reverse(V.P, Cm1, C0, Bw.Ab, Bw.Cb, Bw.sb, Bw.v1b, Bw.v2b, Bw.z4b, Bw.z5b, Lb, Rb);
-  double ol[7], orr[7];
-  cell_reverse(Cm1, Lb, ol);
-  cell_reverse(C0, Rb, orr);
-  // store in field order at the edge's position
-  const long long id = aidx(V, line, e);
-  const long long pl = V.plane;
-  const int fm1 = V.orient ? 2 : 1, ft1 = V.orient ? 1 : 2;
-  const int fm2 = V.orient ? 5 : 4, ft2 = V.orient ? 4 : 5;
-  V.cL[id] = ol[0]; V.cL[fm1 * pl + id] = ol[1]; V.cL[ft1 * pl + id] = ol[2];
-  V.cL[3 * pl + id] = ol[3]; V.cL[fm2 * pl + id] = ol[4]; V.cL[ft2 * pl + id] = ol[5];
-  V.cL[6 * pl + id] = ol[6];
-  V.cR[id] = orr[0]; V.cR[fm1 * pl + id] = orr[1]; V.cR[ft1 * pl + id] = orr[2];
-  V.cR[3 * pl + id] = orr[3]; V.cR[fm2 * pl + id] = orr[4]; V.cR[ft2 * pl + id] = orr[5];
-  V.cR[6 * pl + id] = orr[6];
+  {
+    // edge e-1: its left-going waves' limiter reads edge e; edge e's
+    // right-going waves' limiter reads edge e-1
+    const EdgeW Wm = shup_edge(W);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const double dn = shup(dnu[p]);
+      double X[6], u[6];
+      if (hasPrev && Wm.s[p] < 0.0 && dn != 0.0) {
+        wvec(Wm, p, u);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) X[c] = dn * u[c];
+        add_zbar(Bw, W, p, X);
+      }
+      if (W.s[p] > 0.0 && dnu[p] != 0.0) {
+        wvec(Wm, p, u);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) X[c] = dnu[p] * u[c];
+        add_zbar(Bw, W, p, X);
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 7; ++f) { ol[f] = 0.0; orr[f] = 0.0; }
+  if (own && !ok) atomicOr(status, 1);
+  if (own && ok) {
+    // the two cells again (not held through the limiter passes)
+    const CellX Cm1 = src.cell_again(e - 1), C0 = src.cell_again(e);
+    CellBar Lb, Rb;
+    zero_cb(Lb);
+    zero_cb(Rb);
+    riemann_reverse(P, Cm1, C0, Bw.Ab, Bw.Cb, Bw.sb, Bw.v1b, Bw.v2b, Bw.z4b, Bw.z5b, Lb, Rb);
+    cell_reverse(Cm1, Lb, ol);
+    cell_reverse(C0, Rb, orr);
+  }
 }
 
-// lam_in(k) = lam_out(k) (updated cells) + contribution as right cell of edge k
-// + contribution as left cell of edge k + 1, for k in [-2, n + 1]; bathymetry
-// adjoint likewise.
-__global__ __launch_bounds__(256) void k_adj_gather(AdjView V, double* lam_in, double* Bbar) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long nk = (long long)V.n + 4;
-  if (t >= nk * V.nlines) return;
-  const int line = V.orient ? (int)(t % V.nlines) : (int)(t / nk);
-  const int k = (V.orient ? (int)(t / V.nlines) : (int)(t % nk)) - 2;
-  const long long id = aidx(V, line, k);
-  const long long pl = V.plane;
-  const bool upd = k >= 0 && k < V.n;
-  const bool hasR = k >= -1;         // edge k exists
-  const bool hasL = k + 1 <= V.n + 1;  // edge k + 1 exists
-  const long long idn = aidx(V, line, k + 1);
+// A line's cells and output adjoints straight from the level arrays.
+struct LineSrc {
+  const AdjView* V;
+  int line;
+  __device__ CellX cell(int k) const { return adj_cell(*V, line, k); }
+  __device__ CellX cell_again(int k) const {
+    // an address the compiler cannot match with the first loads
+    long long d = 0;
+    __asm__ volatile("" : "+v"(d));
+    AdjView Vr = *V;
+    Vr.base += d;
+    return adj_cell(Vr, line, k);
+  }
+  __device__ void lam(int k, double l[6]) const { adj_lam(*V, line, k, l); }
+};
+
+// Cells and output adjoints of one column of a tile staged in LDS: rows k0 ..
+// k0 + 64 of TCOLS columns, 13 fields in line-local order (h1 m1 t1 h2 m2 t2
+// B, then the six output adjoints; zero outside the updated cells).
+constexpr int TCOLS = 4, TPAD = 5, TROWS = 65;
+struct TileSrc {
+  const double* t;  // [13][TROWS][TPAD]
+  int k0, col, n;
+  PhysParams P;
+  __device__ double at(int f, int k) const { return t[(f * TROWS + (k - k0)) * TPAD + col]; }
+  __device__ CellX cell(int k) const {
+    return load_cell(P, at(0, k), at(1, k), at(2, k), at(3, k), at(4, k), at(5, k), at(6, k));
+  }
+  __device__ CellX cell_again(int k) const { return cell(k); }
+  __device__ void lam(int k, double l[6]) const {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) l[c] = at(7 + c, k);
+  }
+};
+
+// Cell k of a line sums its own output adjoint (cells 0..n-1), what edge k
+// gives its right cell and what edge k + 1 gives its left cell: lane L holds
+// edge k = e and receives edge k + 1 from lane L + 1.  Lanes 1..61 write cells
+// k = 61 s - 2 + L - 1, so the segments' cells tile -2 .. n+1 once.
+__device__ __forceinline__ void cell_sums(const double ol[7], const double orr[7], const double l0[6], bool hasR,
+                                          bool hasL, double out[7]) {
 #pragma unroll
   for (int f = 0; f < 7; ++f) {
-    double v = (upd && f < 6) ? V.lam[f * pl + id] : 0.0;
-    if (hasR) v += V.cR[f * pl + id];
-    if (hasL) v += V.cL[f * pl + idn];
-    if (f < 6) lam_in[f * pl + id] = v;
-    else Bbar[id] = v;
+    const double fromL = shdn(ol[f]);  // edge k + 1, lane L + 1
+    double v = f < 6 ? l0[f] : 0.0;
+    if (hasR) v += orr[f];
+    if (hasL) v += fromL;
+    out[f] = v;
+  }
+}
+
+// Rows (the x-sweep's lines): one wave per 61 cells of a row, cells read by
+// each lane from memory (consecutive lanes, consecutive cells).  Writes the
+// adjoint of the wall-filled state (lam_in, level layout) and the row sweep's
+// bathymetry adjoint.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_edges_row(AdjView V,
+                                                                                                double* lam_in,
+                                                                                                double* Bbar) {
+  const int lane = (int)(threadIdx.x & 63);
+  const long long wv = (long long)blockIdx.x * 4 + (long long)(threadIdx.x >> 6);
+  const int n = V.n;
+  const int nseg = (n + 4 + 60) / 61;
+  if (wv >= (long long)nseg * V.nlines) return;  // whole waves
+  const int line = (int)(wv / nseg), seg = (int)(wv % nseg);
+  const int e = 61 * seg - 3 + lane;
+  const bool exists = e >= -1 && e <= n + 1;
+  const bool own = exists && lane >= 1 && lane <= 62;
+  const LineSrc src{&V, line};
+  double ol[7], orr[7];
+  adj_edge_lane(src, V.P, V.nu, n, e, exists, V.status, own, ol, orr);
+  double l0[6];
+  adj_lam(V, line, e, l0);  // zero outside the updated cells
+  double out[7];
+  cell_sums(ol, orr, l0, e >= -1, e + 1 <= n + 1, out);
+  if (lane < 1 || lane > 61 || e < -2 || e > n + 1) return;
+  const long long id = aidx(V, line, e);
+  const long long pl = V.plane;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) lam_in[f * pl + id] = out[f];
+  Bbar[id] = out[6];
+}
+
+// Field plane of line-local field f (h1 m1 t1 h2 m2 t2) along a column, where
+// the normal momenta are hv: planes 0 2 1 3 5 4.
+__device__ __forceinline__ int col_plane(int f) { return (f == 1 || f == 4) ? f + 1 : (f == 2 || f == 5) ? f - 1 : f; }
+
+// Columns (the y-sweep's lines): a block takes TCOLS adjacent columns and 61
+// cells of each, one wave per column.  The block first copies the tile's cells
+// and output adjoints (rows of TCOLS consecutive doubles) into LDS, each wave
+// then reads its column there by lane, and the cell sums go back through LDS
+// so that the stores, too, run along rows.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_edges_col(AdjView V,
+                                                                                                double* lam_in,
+                                                                                                double* Bbar) {
+  __shared__ double tile[13 * TROWS * TPAD];
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  const int n = V.n;
+  const int nseg = (n + 4 + 60) / 61;
+  const int ncb = (V.nlines + TCOLS - 1) / TCOLS;
+  // blocks reach the eight XCDs in turn: XCD x takes the x-th band of the
+  // tiles, so the column groups that share cache lines meet in one L2
+  const int per = (int)(gridDim.x >> 3);
+  const int g = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  const int cb = g % ncb, seg = g / ncb;
+  if (seg >= nseg) return;  // whole blocks
+  const int i0 = TCOLS * cb, k0 = 61 * seg - 4;
+  const long long pl = V.plane;
+  // all of a thread's loads are issued, from clamped in-bounds addresses,
+  // before its first LDS write; the values past the data are chosen after
+  constexpr int NIN = 13 * TROWS * TCOLS, KIN = (NIN + 255) / 256;
+  double vin[KIN];
+#pragma unroll
+  for (int u = 0; u < KIN; ++u) {
+    const int x = (int)threadIdx.x + 256 * u;
+    const int f = x < NIN ? x / (TROWS * TCOLS) : 12, r = (x / TCOLS) % TROWS, c = x % TCOLS;
+    const int k = k0 + r, i = i0 + c;
+    const int ii = i < V.nlines ? i : V.nlines - 1;
+    double v;
+    if (f < 7) {
+      const int kk = k < -2 ? -2 : (k > n + 1 ? n + 1 : k);
+      v = (f < 6 ? V.q + col_plane(f) * pl : V.B)[aidx(V, ii, kk)];
+    } else {
+      const int kk = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+      v = V.lam[col_plane(f - 7) * V.lplane + lidx(V, ii, kk)];
+    }
+    // cells exist on rows -2 .. n+1 (outside them a still, flat cell); the
+    // output adjoints are zero outside the updated cells 0 .. n-1
+    const bool in = f < 7 ? (k >= -2 && k <= n + 1) : (k >= 0 && k < n);
+    const double dflt = (f == 0 || f == 3) ? 1.0 : 0.0;
+    vin[u] = in ? v : dflt;
+  }
+#pragma unroll
+  for (int u = 0; u < KIN; ++u) {
+    const int x = (int)threadIdx.x + 256 * u;
+    if (x < NIN) tile[(x / (TROWS * TCOLS) * TROWS + (x / TCOLS) % TROWS) * TPAD + x % TCOLS] = vin[u];
+  }
+  __syncthreads();
+  const int line = i0 + w;
+  const int e = 61 * seg - 3 + lane;
+  const bool exists = line < V.nlines && e >= -1 && e <= n + 1;
+  const bool own = exists && lane >= 1 && lane <= 62;
+  const TileSrc src{tile, k0, w, n, V.P};
+  double ol[7], orr[7];
+  adj_edge_lane(src, V.P, V.nu, n, e, exists, V.status, own, ol, orr);
+  double l0[6];
+  src.lam(e, l0);
+  double out[7];
+  cell_sums(ol, orr, l0, e >= -1, e + 1 <= n + 1, out);
+  __syncthreads();  // the tile's inputs are read; its space takes the sums
+  // cell k = e = k0 + 2 + r (r = lane - 1) at [f][r][w]
+  if (lane >= 1 && lane <= 61) {
+#pragma unroll
+    for (int f = 0; f < 7; ++f) tile[(f * TROWS + lane - 1) * TPAD + w] = out[f];
+  }
+  __syncthreads();
+  constexpr int NOUT = 7 * 61 * TCOLS, KOUT = (NOUT + 255) / 256;
+#pragma unroll
+  for (int u = 0; u < KOUT; ++u) {
+    const int x = (int)threadIdx.x + 256 * u;
+    const int f = x / (61 * TCOLS), r = (x / TCOLS) % 61, c = x % TCOLS;
+    const int k = k0 + 2 + r, i = i0 + c;
+    if (x >= NOUT || i >= V.nlines || k < -2 || k > n + 1) continue;
+    const double v = tile[(f * TROWS + r) * TPAD + c];
+    if (f < 6) lam_in[col_plane(f) * pl + aidx(V, i, k)] = v;
+    else Bbar[aidx(V, i, k)] = v;
   }
 }
 

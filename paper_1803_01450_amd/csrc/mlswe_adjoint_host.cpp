@@ -5,20 +5,16 @@
 // ------------------------------------------------------------ adjoint
 static int ensure_adj(mlswe_ctx* c, ProblemH& P) {
   AdjBuf& A = P.adj;
-  if (A.lam1) return MLSWE_OK;
+  if (A.lamS) return MLSWE_OK;
   const LevelH& L = P.L[0];
   const size_t pb = sizeof(double) * (size_t)L.plane;
   int rc;
-  if ((rc = dalloc(c, (void**)&A.lam1, 6 * pb)) || (rc = dalloc(c, (void**)&A.lamS, 6 * pb)) ||
-      (rc = dalloc(c, (void**)&A.lamG, 6 * pb)) || (rc = dalloc(c, (void**)&A.cL, 7 * pb)) ||
-      (rc = dalloc(c, (void**)&A.cR, 7 * pb)) || (rc = dalloc(c, (void**)&A.Bbx, pb)) ||
+  if ((rc = dalloc(c, (void**)&A.lamS, 6 * pb)) ||
+      (rc = dalloc(c, (void**)&A.lamG, 6 * pb)) || (rc = dalloc(c, (void**)&A.Bbx, pb)) ||
       (rc = dalloc(c, (void**)&A.Bby, pb)) || (rc = dalloc(c, (void**)&A.status, sizeof(int))))
     return rc;
-  HIPCHK(c, hipMemsetAsync(A.lam1, 0, 6 * pb, c->stream));
   HIPCHK(c, hipMemsetAsync(A.lamS, 0, 6 * pb, c->stream));
   HIPCHK(c, hipMemsetAsync(A.lamG, 0, 6 * pb, c->stream));
-  HIPCHK(c, hipMemsetAsync(A.cL, 0, 7 * pb, c->stream));
-  HIPCHK(c, hipMemsetAsync(A.cR, 0, 7 * pb, c->stream));
   HIPCHK(c, hipMemsetAsync(A.Bbx, 0, pb, c->stream));
   HIPCHK(c, hipMemsetAsync(A.Bby, 0, pb, c->stream));
   HIPCHK(c, hipMemsetAsync(A.status, 0, sizeof(int), c->stream));
@@ -49,8 +45,11 @@ extern "C" int mlswe_run_fixed(mlswe_ctx* c, int p, int n, const double* dts) {
     if (!(dts[k] > 0.0) || !std::isfinite(dts[k])) return fail(c, MLSWE_EINVAL, "dt[%d] must be positive", k);
   // each step's dt travels as a kernel argument: no copy, no host wait
   for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, c->stream, c->ctl + P.ctl0, dts[k]);
-    if ((rc = substep(c, 0, p, p + 1, 0.0, false))) return rc;
+    c->dt_ctl = c->ctl + P.ctl0;  // stored by the step's fill launch
+    c->dt_value = dts[k];
+    rc = substep(c, 0, p, p + 1, 0.0, false);
+    c->dt_ctl = nullptr;
+    if (rc) return rc;
   }
   return MLSWE_OK;
 }
@@ -73,35 +72,44 @@ extern "C" int mlswe_adjoint_step(mlswe_ctx* c, int p, const double* q_n, const 
   }
   // forward recomputation: state, walls, x-sweep
   if ((rc = copy_state(c, L, L.cur, q_n, MLSWE_DEVICE, true, nullptr))) return rc;
-  hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, c->stream, c->ctl + P.ctl0, dt);
   if ((rc = build_launch(c, 0))) return rc;
-  if ((rc = launch_fill(c, 0, p, p + 1, 0.0))) return rc;
+  c->dt_ctl = c->ctl + P.ctl0;  // stored by the fill launch
+  c->dt_value = dt;
+  rc = launch_fill(c, 0, p, p + 1, 0.0);
+  c->dt_ctl = nullptr;
+  if (rc) return rc;
   LevelLaunch& LL = c->launch[0];
   int k0 = -1;
   for (int k = 0; k < LL.nptch; ++k)
     if (LL.patch_prob[k] == p) { k0 = k; break; }
   if (k0 < 0) return fail(c, MLSWE_ESTATE, "problem %d has no patch", p);
   if ((rc = launch_sweeps(c, 0, L.cur, LL.xr[k0].first, LL.xr[k0].second, 0, 0))) return rc;
-  // adjoint of the step's output into the level layout
-  hipLaunchKernelGGL(k_copy6, dim3(blocks((long long)L.nx * L.ny)), dim3(256), 0, c->stream, A.lam1, (long long)L.pitch,
-                     (long long)L.plane, const_cast<double*>(lam_np1), L.nx, L.ny, 0);
   AdjView V;
   std::memset(&V, 0, sizeof V);
-  V.B = L.B; V.cL = A.cL; V.cR = A.cR; V.plane = L.plane; V.P = P.P; V.status = A.status;
+  V.B = L.B; V.plane = L.plane; V.P = P.P; V.status = A.status;
   // y-sweep lines: columns, cells along rows
-  V.q = L.qs; V.lam = A.lam1;
+  // (the adjoint of the step's output is read where the caller holds it, [6][ny][nx])
+  V.q = L.qs; V.lam = lam_np1;
   V.lstride = 1; V.kstride = L.pitch; V.base = idx(L, 0, 0);
+  V.lplane = (long long)L.nx * L.ny; V.lbase = 0; V.llstride = 1; V.lkstride = L.nx;
   V.nlines = L.nx; V.n = L.ny; V.orient = 1; V.nu = dt / L.dy;
-  hipLaunchKernelGGL(k_adj_edges, dim3(blocks((long long)L.nx * (L.ny + 3))), dim3(256), 0, c->stream, V);
-  hipLaunchKernelGGL(k_adj_gather, dim3(blocks((long long)L.nx * (L.ny + 4))), dim3(256), 0, c->stream, V, A.lamS,
-                     A.Bby);
+  {
+    // a block per 4 columns and 61 cells (k_adj_edges_col), in eight XCD bands
+    const long long tiles = ((L.nx + 3) / 4) * (long long)((L.ny + 4 + 60) / 61);
+    hipLaunchKernelGGL(k_adj_edges_col, dim3((unsigned)(8 * ((tiles + 7) / 8))), dim3(256), 0, c->stream, V, A.lamS,
+                       A.Bby);
+  }
   // x-sweep lines: rows -2..ny+1 of the wall-filled state, cells along x
   V.q = L.q[L.cur]; V.lam = A.lamS;
   V.lstride = L.pitch; V.kstride = 1; V.base = idx(L, 0, -2);
+  V.lplane = L.plane; V.lbase = V.base; V.llstride = V.lstride; V.lkstride = V.kstride;
   V.nlines = L.ny + 4; V.n = L.nx; V.orient = 0; V.nu = dt / L.dx;
-  hipLaunchKernelGGL(k_adj_edges, dim3(blocks((long long)(L.ny + 4) * (L.nx + 3))), dim3(256), 0, c->stream, V);
-  hipLaunchKernelGGL(k_adj_gather, dim3(blocks((long long)(L.ny + 4) * (L.nx + 4))), dim3(256), 0, c->stream, V,
-                     A.lamG, A.Bbx);
+  {
+    // one wave per 61 cells of a row (k_adj_edges_row), four waves a block
+    const long long waves = (long long)(L.ny + 4) * ((L.nx + 4 + 60) / 61);
+    hipLaunchKernelGGL(k_adj_edges_row, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, c->stream, V, A.lamG,
+                       A.Bbx);
+  }
   AdjFold F;
   F.lam_g = A.lamG; F.Bbx = A.Bbx; F.Bby = A.Bby; F.lam_out = lam_n; F.Bbar = B_bar;
   F.pitch = L.pitch; F.plane = L.plane; F.nx = L.nx; F.ny = L.ny;

@@ -53,11 +53,8 @@ struct LevelH {
 
 // Device buffers of the adjoint step (level layout), allocated on first use.
 struct AdjBuf {
-  double* lam1 = nullptr;  // adjoint of the step's output
   double* lamS = nullptr;  // adjoint of the x-swept state
   double* lamG = nullptr;  // adjoint of the wall-filled state
-  double* cL = nullptr;    // per-edge contributions (7 planes)
-  double* cR = nullptr;
   double* Bbx = nullptr;
   double* Bby = nullptr;
   int* status = nullptr;        // device: set by the edge kernel on a non-wet edge (sticky)
@@ -182,6 +179,8 @@ struct mlswe_ctx {
   std::vector<GraphRec> graphs;
   long long graph_launches = 0, graph_captures = 0;
   long long host_waits = 0;  // waits of the host on the context's stream
+  LevelCtl* dt_ctl = nullptr;  // a time step for the next fill launch to store (fixed-grid calls)
+  double dt_value = 0.0;
   LevelCtl* ctl_bk = nullptr;
   Counters* cnt_bk = nullptr;
   int bk_cap = 0, cbk_cap = 0;

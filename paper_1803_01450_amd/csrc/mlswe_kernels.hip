@@ -79,8 +79,12 @@ __device__ __forceinline__ bool refine_cell_into(const FillPatch& F, int i, int 
 
 // pass 0: in-domain frame cells not covered by a patch of the level are refined
 // from the coarser level; pass 1: frame cells outside the domain mirror the
-// in-domain cells across the walls (normal momentum negated).
-__global__ __launch_bounds__(256) void k_ghost_fill(const FillPatch* __restrict__ fills, int pass, double theta) {
+// in-domain cells across the walls (normal momentum negated).  With dt_ctl
+// set, the launch also stores the level's time step (dt_ctl->dt = dt) for the
+// sweeps that follow it: a caller-given step costs no launch of its own.
+__global__ __launch_bounds__(256) void k_ghost_fill(const FillPatch* __restrict__ fills, int pass, double theta,
+                                                    LevelCtl* dt_ctl, double dt) {
+  if (dt_ctl && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) dt_ctl->dt = dt;
   const FillPatch& F = fills[blockIdx.y];
   const int ring = 4 * (F.bnx + 4) + 4 * F.bny;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;

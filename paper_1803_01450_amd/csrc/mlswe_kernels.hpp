@@ -161,8 +161,7 @@ struct AdjView {
   const double* q;
   const double* B;
   const double* lam;   // adjoint of the sweep's outputs (read at cells 0..n-1)
-  double* cL;          // 7 planes: contribution of edge e to its left cell, at e
-  double* cR;          // 7 planes: contribution of edge e to its right cell, at e
+  long long lplane, lbase, llstride, lkstride;  // its own indexing (level or dense layout)
   long long plane, lstride, kstride, base;
   int nlines, n, orient;
   double nu;
@@ -200,8 +199,8 @@ struct Gauge {
   int nx, ny, i0, j0, gn, qlevel;
 };
 
-__global__ void k_adj_edges(AdjView V);
-__global__ void k_adj_gather(AdjView V, double* lam_in, double* Bbar);
+__global__ void k_adj_edges_row(AdjView V, double* lam_in, double* Bbar);
+__global__ void k_adj_edges_col(AdjView V, double* lam_in, double* Bbar);
 __global__ void k_adj_fold(AdjFold F);
 __global__ void k_param_map(ParamMap M);
 __global__ void k_param_map_adj(ParamMap M, const double* __restrict__ lam0, double* eta1_bar, double* B_bar);
@@ -233,7 +232,8 @@ __global__ void k_sweep_x_fast(const PatchDev* __restrict__ patches, const XTile
 __global__ void k_sweep_y_fast(const PatchDev* __restrict__ patches, const YTile* __restrict__ tiles, int ntiles,
                                int sched, unsigned* ticket, TilePart* parts);
 __global__ void k_zero_u32(unsigned* p, int n);
-__global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass, double theta);
+__global__ void k_ghost_fill(const FillPatch* __restrict__ fills, int pass, double theta, LevelCtl* dt_ctl,
+                             double dt);
 __global__ void k_refine_new(const FillPatch* __restrict__ fills);
 __global__ void k_coarsen(const CoarsenPatch* __restrict__ cps);
 

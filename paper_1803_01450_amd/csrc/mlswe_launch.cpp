@@ -135,18 +135,25 @@ int build_launch(mlswe_ctx* c, int l) {
   // start worth half a row (x) or its halo worth 2.5 rows (y), values fitted to
   // sweep times of uniform grids, batches of uneven problems and their union
   // tiles.  Ties keep the taller tiles.
-  const int xc[4] = {32, 16, 8, 4}, yc[5] = {128, 64, 32, 16, 8};
+  // The last candidate (2 rows for x, 4 for y) serves small levels only: it
+  // is weighed when the one before it leaves some SIMD without a tile, so
+  // that a few waves do not each run a long serial chain of rows on an idle
+  // chip (on fuller levels its extra halo and start work would cost more).
+  const int xc[5] = {32, 16, 8, 4, 2}, yc[6] = {128, 64, 32, 16, 8, 4};
   auto pick = [&](int axis, int tuned, const std::function<void(int, std::vector<int>&)>& rows_of) {
     if (tuned > 0) return tuned;
     const int* cand = axis == 0 ? xc : yc;
-    const int nc = axis == 0 ? 4 : 5;
+    const int nc = axis == 0 ? 5 : 6;
     const long long slots = (axis == 0 ? 24LL : 16LL) * c->ncu;
     long long best = -1;
     int br = cand[0];
     std::vector<int> d;
+    size_t prev_tiles = 0;
     for (int k = 0; k < nc; ++k) {
       d.clear();
       rows_of(cand[k], d);
+      if (k == nc - 1 && (long long)prev_tiles >= 4LL * c->ncu) break;
+      prev_tiles = d.size();
       const long long m = tile_makespan(d, axis == 0 ? 2 : 10, slots);
       if (best < 0 || m < best) { best = m; br = cand[k]; }
     }
@@ -552,15 +559,29 @@ int launch_fill(mlswe_ctx* c, int l, int p0, int p1, double theta) {
       walls = walls || b.ilo < 2 || b.jlo < 2 || b.ilo + b.nx > L.nx - 2 || b.jlo + b.ny > L.ny - 2;
     }
   }
-  if (count == 0) return MLSWE_OK;
-  const FillPatch* f = LL.fp[fpar * 2 + cpar] + first;
-  if (l > 0) {
-    hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 0, theta);
-    HIPCHK(c, hipGetLastError());
+  // a time step handed over by the fixed-grid calls rides on the first fill
+  // launch (or gets a launch of its own when no fill runs)
+  LevelCtl* dt_ctl = c->dt_ctl;
+  const double dt = c->dt_value;
+  c->dt_ctl = nullptr;
+  if (count > 0) {
+    const FillPatch* f = LL.fp[fpar * 2 + cpar] + first;
+    if (l > 0) {
+      hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 0, theta,
+                         dt_ctl, dt);
+      HIPCHK(c, hipGetLastError());
+      dt_ctl = nullptr;
+    }
+    // the second pass only mirrors frame cells outside the domain
+    if (walls) {
+      hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 1, theta,
+                         dt_ctl, dt);
+      HIPCHK(c, hipGetLastError());
+      dt_ctl = nullptr;
+    }
   }
-  // the second pass only mirrors frame cells outside the domain
-  if (walls) {
-    hipLaunchKernelGGL(k_ghost_fill, dim3((maxring + 255) / 256, count), dim3(256), 0, c->stream, f, 1, theta);
+  if (dt_ctl) {
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(1), 0, c->stream, dt_ctl, dt);
     HIPCHK(c, hipGetLastError());
   }
   return MLSWE_OK;

@@ -181,7 +181,7 @@ int mlswe_destroy(mlswe_ctx* c) {
   if (!c) return MLSWE_EINVAL;
   (void)host_wait(c);
   for (ProblemH& P : c->probs) {
-    dfree(P.adj.lam1); dfree(P.adj.lamS); dfree(P.adj.lamG); dfree(P.adj.cL); dfree(P.adj.cR);
+    dfree(P.adj.lamS); dfree(P.adj.lamG);
     dfree(P.adj.Bbx); dfree(P.adj.Bby); dfree(P.adj.status);
     if (P.adj.status_host) (void)hipHostFree(P.adj.status_host);
     if (P.adj.status_ev) (void)hipEventDestroy(P.adj.status_ev);

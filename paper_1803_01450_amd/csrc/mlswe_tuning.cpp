@@ -115,9 +115,9 @@ extern "C" int mlswe_autotune(mlswe_ctx* c, const char* cache_path, int reps) {
   int rc = MLSWE_OK;
   for (int axis = 0; axis < 2 && !rc; ++axis) {
     // 0: the per-level choice made when the tiles are built
-    const int rows_x[5] = {0, 4, 8, 16, 32};
-    const int rows_y[6] = {0, 16, 32, 64, 128, 256};
-    const int nrows = axis == 0 ? 5 : 6;
+    const int rows_x[6] = {0, 2, 4, 8, 16, 32};
+    const int rows_y[8] = {0, 4, 8, 16, 32, 64, 128, 256};
+    const int nrows = axis == 0 ? 6 : 8;
     double best_ms = 1e300;
     for (int ri = 0; ri < nrows && !rc; ++ri)
       for (int si = 0; si < 5 && !rc; ++si) {

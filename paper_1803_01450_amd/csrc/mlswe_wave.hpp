@@ -72,6 +72,20 @@ __device__ __forceinline__ EdgeW shup_edge(const EdgeW& w) {
   return o;
 }
 
+__device__ __forceinline__ int shdn_i(int v) { return dpp_dn_i(v); }
+
+__device__ __forceinline__ EdgeW shdn_edge(const EdgeW& w) {
+  EdgeW o;
+#pragma unroll
+  for (int p = 0; p < 6; ++p) o.s[p] = shdn(w.s[p]);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) { o.A[p] = shdn(w.A[p]); o.C[p] = shdn(w.C[p]); }
+  o.v1 = shdn(w.v1); o.v2 = shdn(w.v2); o.z4 = shdn(w.z4); o.z5 = shdn(w.z5);
+  int m = shdn_i(w.mode1 | (w.mode2 << 4));
+  o.mode1 = m & 15; o.mode2 = m >> 4;
+  return o;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) { double t = __shfl_xor(v, o, 64); v = t > v ? t : v; }
