@@ -58,14 +58,20 @@ typedef struct mlswe_config {
                          cfl_max is undone and retaken with dt scaled by
                          cfl_desired / that number, at most this often; -1 = never
                          (the step then fails with MLSWE_ECFL), 0 = the default 8.
+                         Only the problems that failed are retaken: the other
+                         problems of a batched group keep their step (their
+                         launches in the retake do nothing).
                          mlswe_advance in MLSWE_BATCHED, MLSWE_GRAPH and
                          MLSWE_PER_PATCH checks once per window of up to 32
                          coarse steps (and before each regrid) with no host
                          wait in between: the first failing substep halts the
                          window on the device, and the run resumes from that
-                         step's retake, with results identical to a check
-                         after every step (which plain mode, dts_out, kernel
-                         timing, reflux and dynamic_rt keep) */
+                         step's retake (of every problem, as the halt stopped
+                         all of them part way), with results identical to a
+                         check after every step (which plain mode, dts_out,
+                         kernel timing, reflux and dynamic_rt keep); after a
+                         retake the windows restart from single checked steps
+                         and double with each clean window */
   int reflux;         /* 1: mass flux correction at coarse-fine edges (the paper has
                          none), within mlswe_advance (mlswe_step_level and
                          mlswe_coarsen called on their own leave it out): after a

@@ -189,8 +189,8 @@ int graph_step(mlswe_ctx* c, int p0, int p1) {
 }
 
 // Backup (to_bk) or restore of a group's coarse-step start: the patch interiors
-// of its finer levels and the control blocks and counters of every problem,
-// in one launch.
+// of its finer levels and the control blocks and counters of its problems, in
+// one launch (a problem whose skip flag is set is left as it is).
 int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt, bool mark) {
   // the list depends on the launch data (generation), the direction and the
   // buffer parity of every level: built and uploaded once per combination
@@ -211,8 +211,11 @@ int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt
   if (!hit) {
     std::vector<CopyBox> boxes;
     long long longest = 0;
+    // every box carries its problem's skip flag: a retake restores only the
+    // problems it takes again
+    const unsigned* sk = nullptr;
     auto add = [&](const double* from, double* to, long long pitch, long long plane, int nx, int ny, int nf) {
-      boxes.push_back(CopyBox{from, to, pitch, plane, nx, ny, nf, 0});
+      boxes.push_back(CopyBox{from, to, pitch, plane, nx, ny, nf, 0, sk});
       longest = std::max(longest, (long long)nx * ny * nf);
     };
     auto run = [&](double* live, double* saved, long long n) {
@@ -220,10 +223,19 @@ int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt
     };
     static_assert(sizeof(LevelCtl) % sizeof(double) == 0 && sizeof(Counters) % sizeof(double) == 0,
                   "copied as doubles");
-    run((double*)c->ctl, (double*)c->ctl_bk, (long long)nctl * (long long)(sizeof(LevelCtl) / sizeof(double)));
-    run((double*)c->cnt, (double*)c->cnt_bk, (long long)ncnt * (long long)(sizeof(Counters) / sizeof(double)));
+    (void)nctl;
+    (void)ncnt;
     for (int p = p0; p < p1; ++p) {
       ProblemH& P = c->probs[p];
+      sk = c->skip + p;
+      constexpr long long wc = (long long)(sizeof(LevelCtl) / sizeof(double));
+      constexpr long long wn = (long long)(sizeof(Counters) / sizeof(double));
+      run((double*)(c->ctl + P.ctl0), (double*)(c->ctl_bk + P.ctl0), P.nlev * wc);
+      run((double*)(c->cnt + P.cnt), (double*)(c->cnt_bk + P.cnt), wn);
+    }
+    for (int p = p0; p < p1; ++p) {
+      ProblemH& P = c->probs[p];
+      sk = c->skip + p;
       for (int l = 1; l < P.nlev; ++l) {
         LevelH& L = P.L[l];
         for (const Box& b : L.boxes) {
@@ -326,9 +338,11 @@ int read_controls(mlswe_ctx* c, int nctl, bool want_halt, const LevelCtl** h, co
 // From the control blocks after a step: each problem's largest substep Courant
 // number; a problem above cfl_max gets dt scaled by cfl_desired / that number
 // for its retake, the others keep theirs.  MLSWE_ENAN on a non-finite state.
-int judge(mlswe_ctx* c, int p0, int p1, const LevelCtl* h, std::vector<double>& dt0, bool* any) {
+int judge(mlswe_ctx* c, int p0, int p1, const LevelCtl* h, std::vector<double>& dt0, bool* any,
+          std::vector<unsigned char>* failing) {
   *any = false;
   dt0.assign((size_t)(p1 - p0), 0.0);
+  if (failing) failing->assign((size_t)(p1 - p0), 0);
   for (int p = p0; p < p1; ++p) {
     const ProblemH& P = c->probs[p];
     double cm = 0.0;
@@ -342,6 +356,7 @@ int judge(mlswe_ctx* c, int p0, int p1, const LevelCtl* h, std::vector<double>& 
     if (nan) return fail(c, MLSWE_ENAN, "non-finite state or Courant number in problem %d", p);
     if (cm > c->cfg.cfl_max) {
       *any = true;
+      if (failing) (*failing)[p - p0] = 1;
       dt0[p - p0] = dtp * (c->cfg.cfl_desired / cm);
     } else {
       dt0[p - p0] = dtp;
@@ -361,39 +376,57 @@ void accept_step(mlswe_ctx* c, int p0, int p1, const LevelCtl* h) {
   }
 }
 
-// Retakes a rejected coarse step of the group: host bookkeeping back to the
-// step's start m, patch interiors, controls and counters from the backup, dt0
-// for every problem, the subcycled recursion again; checked after each
-// attempt until it passes or max_retries retakes are spent.
+// Retakes a rejected coarse step: the problems marked in rerun (those whose
+// Courant number exceeded cfl_max, or the whole group when a deferred window
+// stopped its step part way) are put back to the step's start m (patch
+// interiors, controls and counters from the backup) and stepped again with
+// dt0, while every other problem of the group is left alone through its skip
+// flag (its launches do nothing, its buffers keep the accepted step, and the
+// host bookkeeping replays the same parity flips and counts); failing marks
+// the problems whose step is counted as rejected.  Checked after each attempt
+// until it passes or max_retries retakes are spent.
 int retake(mlswe_ctx* c, int p0, int p1, bool together, const StepMark& m, std::vector<double> dt0, int nctl,
-           int ncnt) {
+           int ncnt, std::vector<unsigned char> rerun, std::vector<unsigned char> failing) {
   int rc;
   const int np = p1 - p0;
+  // the skip flags are cleared whatever the outcome
+  struct Clear {
+    mlswe_ctx* c;
+    int p0, np;
+    ~Clear() { hipLaunchKernelGGL(k_set_skip, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->skip + p0, nullptr, np); }
+  } clear{c, p0, np};
   for (int attempt = 1;; ++attempt) {
     if (attempt > c->cfg.max_retries) return fail(c, MLSWE_ECFL, "Courant number above %g", c->cfg.cfl_max);
     size_t k = 0;
     for (int p = p0; p < p1; ++p) {
       ProblemH& P = c->probs[p];
-      P.rejected++;
+      if (failing[p - p0]) P.rejected++;
       for (int l = 0; l < P.nlev; ++l, ++k) {
         P.L[l].cur = m.cur[k];
         P.updates[l] = m.upd[k];
       }
     }
+    if ((rc = ensure(c, &c->fail_d, &c->fail_cap, np))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->fail_d, rerun.data(), (size_t)np, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_set_skip, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->skip + p0, c->fail_d, np);
     if ((rc = copy_step_start(c, p0, p1, false, nctl, ncnt, false))) return rc;
     if ((rc = ensure(c, &c->dt0_d, &c->dt0_cap, np))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->dt0_d, dt0.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(k_set_dt0, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, c->dt0_d, np);
+    hipLaunchKernelGGL(k_set_dt0, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, c->dt0_d, np,
+                       c->skip + p0);
     HIPCHK(c, hipGetLastError());
     if ((rc = adv(c, 0, p0, p1, 0.0, together))) return rc;
     const LevelCtl* h = nullptr;
     if ((rc = read_controls(c, nctl, false, &h, nullptr))) return rc;
     bool any = false;
-    if ((rc = judge(c, p0, p1, h, dt0, &any))) return rc;
+    std::vector<unsigned char> again;
+    if ((rc = judge(c, p0, p1, h, dt0, &any, &again))) return rc;
     if (!any) {
       accept_step(c, p0, p1, h);
       return MLSWE_OK;
     }
+    failing = again;
+    rerun = again;
   }
 }
 
@@ -411,8 +444,9 @@ void counts(const mlswe_ctx* c, int* nctl, int* ncnt) {
 // unchanged.  Frames and uncovered cells of the finer levels are refilled or
 // unused before they are read again, so the backup leaves them out.  The check
 // waits for the step (one host round trip per coarse step).
-int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
+int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode, bool* retaken) {
   int rc;
+  if (retaken) *retaken = false;
   const bool together = mode == MLSWE_BATCHED || mode == MLSWE_GRAPH;
   if (c->cfg.max_retries <= 0) return run_step(c, p0, p1, mode);
   int nctl, ncnt;
@@ -424,13 +458,15 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode) {
   const LevelCtl* h = nullptr;
   if ((rc = read_controls(c, nctl, false, &h, nullptr))) return rc;
   std::vector<double> dt0;
+  std::vector<unsigned char> failing;
   bool any = false;
-  if ((rc = judge(c, p0, p1, h, dt0, &any))) return rc;
+  if ((rc = judge(c, p0, p1, h, dt0, &any, &failing))) return rc;
   if (!any) {
     accept_step(c, p0, p1, h);
     return MLSWE_OK;
   }
-  return retake(c, p0, p1, together, m, dt0, nctl, ncnt);
+  if (retaken) *retaken = true;
+  return retake(c, p0, p1, together, m, dt0, nctl, ncnt, failing, failing);
 }
 
 // Deferred checks: the steps of a window run back to back with no host wait.
@@ -467,7 +503,7 @@ int disarm(mlswe_ctx* c) {
 
 // kept: how many of the window's steps stand once it is checked (all, or up to
 // and including the retaken first failure).
-int verify_window(mlswe_ctx* c, int mode, std::vector<StepMark>& win, int* kept) {
+int verify_window(mlswe_ctx* c, int mode, std::vector<StepMark>& win, int* kept, bool* retook) {
   int rc;
   const int np = (int)c->probs.size();
   const bool together = mode == MLSWE_BATCHED || mode == MLSWE_GRAPH;
@@ -481,7 +517,9 @@ int verify_window(mlswe_ctx* c, int mode, std::vector<StepMark>& win, int* kept)
   if ((rc = disarm(c))) return rc;
   std::vector<double> dt0;
   bool any = false;
-  if ((rc = judge(c, 0, np, h, dt0, &any))) return rc;
+  std::vector<unsigned char> failing;
+  if ((rc = judge(c, 0, np, h, dt0, &any, &failing))) return rc;
+  *retook = halted;
   if (!halted) {
     if (any) return fail(c, MLSWE_ESTATE, "deferred check: a failing step did not halt its window");
     accept_step(c, 0, np, h);
@@ -490,7 +528,9 @@ int verify_window(mlswe_ctx* c, int mode, std::vector<StepMark>& win, int* kept)
   }
   if (!any || f < 0 || f >= (int)win.size())
     return fail(c, MLSWE_ESTATE, "deferred check: halted window without a failing step");
-  if ((rc = retake(c, 0, np, together, win[f], dt0, nctl, ncnt))) return rc;
+  // the halt stopped every problem's step part way: all of them are taken again
+  std::vector<unsigned char> all((size_t)np, 1);
+  if ((rc = retake(c, 0, np, together, win[f], dt0, nctl, ncnt, all, failing))) return rc;
   *kept = f + 1;
   return MLSWE_OK;
 }
@@ -526,7 +566,11 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
   // ratio's speeds) and the flux correction keep the per-step check
   const bool defer = together && c->cfg.max_retries > 0 && !dts_out && !c->timing && !c->cfg.reflux &&
                      !c->cfg.dynamic_rt;
+  // window length: 32 coarse steps, down to single checked steps after a
+  // retake (a halted window takes every problem again, a checked step only
+  // the failing ones), then doubling after each clean window
   constexpr int WINDOW = 32;
+  int W = WINDOW;
   std::vector<StepMark> win;
   struct Guard {
     mlswe_ctx* c;
@@ -545,21 +589,28 @@ int mlswe_advance(mlswe_ctx* c, int nsteps, int regrid_every, const double* tau,
     }
     if (c->cfg.dynamic_rt && (rc = choose_time_ratios(c))) return rc;
     if ((rc = build_pdt(c))) return rc;
-    if (defer) {
+    if (defer && (W > 1 || !win.empty())) {
       if ((rc = deferred_step(c, mode, win))) return rc;
       ++n;
-      if ((int)win.size() >= WINDOW || n == nsteps || (regrid_every > 0 && n % regrid_every == 0)) {
+      if ((int)win.size() >= W || n == nsteps || (regrid_every > 0 && n % regrid_every == 0)) {
         int kept = 0;
-        if ((rc = verify_window(c, mode, win, &kept))) return rc;
+        bool retook = false;
+        if ((rc = verify_window(c, mode, win, &kept, &retook))) return rc;
+        const bool clean = !retook;
         n -= (int)win.size() - kept;
         win.clear();
+        W = clean ? std::min(WINDOW, 2 * W) : 1;
       }
       continue;
     }
+    bool retaken = false;
     for (int gi = 0; gi < ngroups; ++gi) {
       const int p0 = together ? 0 : gi, p1 = together ? np : gi + 1;
-      if ((rc = step_with_retry(c, p0, p1, mode))) return rc;
+      bool r = false;
+      if ((rc = step_with_retry(c, p0, p1, mode, &r))) return rc;
+      retaken = retaken || r;
     }
+    if (defer) W = retaken ? 1 : 2;
     if (dts_out || c->timing) {
       if ((rc = collect_events(c))) return rc;
     }

@@ -179,6 +179,10 @@ struct mlswe_ctx {
   std::vector<GraphRec> graphs;
   long long graph_launches = 0, graph_captures = 0;
   long long host_waits = 0;  // waits of the host on the context's stream
+  unsigned* skip = nullptr;  // per problem: set while a retake leaves it alone
+  int skip_cap = 0;
+  unsigned char* fail_d = nullptr;  // per problem: taken again by a retake
+  int fail_cap = 0;
   LevelCtl* dt_ctl = nullptr;  // a time step for the next fill launch to store (fixed-grid calls)
   double dt_value = 0.0;
   LevelCtl* ctl_bk = nullptr;
@@ -275,7 +279,7 @@ int build_all(mlswe_ctx* c);
 int coarse_step(mlswe_ctx* c, int p0, int p1, bool batched);
 int graph_step(mlswe_ctx* c, int p0, int p1);
 int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt, bool mark);
-int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode);
+int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode, bool* retaken = nullptr);
 
 // grow-only device array
 template <class T>

@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256) void k_ghost_fill(const FillPatch* __restrict_
                                                     LevelCtl* dt_ctl, double dt) {
   if (dt_ctl && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) dt_ctl->dt = dt;
   const FillPatch& F = fills[blockIdx.y];
+  if (F.skip && *F.skip) return;
   const int ring = 4 * (F.bnx + 4) + 4 * F.bny;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= ring) return;
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(256) void k_refine_new(const FillPatch* __restrict_
 // (row-major sum times 1/r^2) for all six fields, then the dry-state fix-up.
 __global__ __launch_bounds__(256) void k_coarsen(const CoarsenPatch* __restrict__ cps) {
   const CoarsenPatch& C = cps[blockIdx.y];
-  if (C.halt[HALT_SET]) return;
+  if (C.halt[HALT_SET] || *C.skip) return;
   const int r = C.r;
   const int cnx = C.bnx / r, cny = C.bny / r;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -295,10 +296,11 @@ __device__ __forceinline__ void after_tail(LevelCtl* ctls, Counters* cnts, const
 // combines the slices in slice order.
 __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos,
                                                         const TilePart* parts, double cflmax, SliceRed* red,
-                                                        unsigned* halt) {
+                                                        unsigned* halt, const unsigned* skip) {
   __shared__ double red_d[4][16];
   __shared__ unsigned long long red_u[4][16];
   const LevelInfo I = infos[blockIdx.x];
+  if (skip[I.prob]) return;  // a problem a retake leaves alone
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int ns = (int)gridDim.y, sl = (int)blockIdx.y;
   double sx = 0.0, sy = 0.0, c1 = 0.0, c2 = 0.0;
@@ -357,9 +359,10 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
 // One thread per problem: its ns slice results combined in slice order, then
 // the end of the reduction.
 __global__ void k_after_combine(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, int n, int ns,
-                                const SliceRed* __restrict__ red, double cflmax, unsigned* halt) {
+                                const SliceRed* __restrict__ red, double cflmax, unsigned* halt,
+                                const unsigned* skip) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || skip[infos[i].prob]) return;
   const SliceRed* R = red + (size_t)i * ns;
   double sx = R[0].sx, sy = R[0].sy, c1 = R[0].c1, c2 = R[0].c2;
   unsigned long long h = R[0].h, nc = R[0].nc, rp = R[0].rp, nf = R[0].nf;
@@ -447,9 +450,10 @@ __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int npr
 
 // Retake of a rejected coarse step: the given coarse dt, the levels' substeps,
 // cleared speeds and Courant maximum.
-__global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const double* __restrict__ dt0, int nprob) {
+__global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const double* __restrict__ dt0, int nprob,
+                          const unsigned* skip) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprob) return;
+  if (p >= nprob || skip[p]) return;
   const ProbDt& D = pd[p];
   double dt = dt0[p];
   for (int l = 0; l < D.nlev; ++l) {
@@ -461,6 +465,11 @@ __global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const d
     C.cmax = 0.0;
   }
   ctls[D.ctl0].t += dt0[p];
+}
+
+__global__ void k_set_skip(unsigned* skip, const unsigned char* __restrict__ fail, int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) skip[p] = fail ? (fail[p] ? 0u : 1u) : 0u;
 }
 
 __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob) {
@@ -524,6 +533,7 @@ __global__ __launch_bounds__(64) void k_reflux_coarse(const RefluxCell* __restri
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 4LL * n) return;
   const RefluxCell& R = rcs[t >> 2];
+  if (*R.skip) return;
   const int d = (int)(t & 3);
   if (!((R.dirs >> d) & 1)) return;
   const long long o = cidx(R.cpitch, R.i, R.j);
@@ -552,6 +562,7 @@ __global__ __launch_bounds__(64) void k_reflux_fine(const RefluxCell* __restrict
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 64LL * n) return;
   const RefluxCell& R = rcs[t >> 6];
+  if (*R.skip) return;
   const int d = (int)((t >> 4) & 3), k = (int)(t & 15);
   const int r = R.r;
   if (!((R.dirs >> d) & 1) || k >= r) return;
@@ -583,6 +594,7 @@ __global__ __launch_bounds__(64) void k_reflux_fsum(const RefluxCell* __restrict
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const RefluxCell& R = rcs[t];
+  if (*R.skip) return;
   for (int d = 0; d < 4; ++d) {
     if (!((R.dirs >> d) & 1)) continue;
     for (int m = 0; m < 2; ++m) {
@@ -599,6 +611,7 @@ __global__ __launch_bounds__(64) void k_reflux_apply(const RefluxCell* __restric
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const RefluxCell& R = rcs[t];
+  if (*R.skip) return;
   const long long o = cidx(R.cpitch, R.i, R.j);
   const double dt = R.cctl->dt;
   const double inv = 1.0 / double(R.r * rt);  // r fine faces in each of rt substeps
@@ -660,6 +673,7 @@ __global__ __launch_bounds__(256) void k_copy_boxes(const CopyBox* __restrict__ 
     if (mark && halt[HALT_ARMED] && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) halt[HALT_MARKS] += 1u;
   }
   const CopyBox C = boxes[blockIdx.y];
+  if (C.skip && *C.skip) return;
   const unsigned nx = (unsigned)C.nx, ny = (unsigned)C.ny;
   const unsigned n = nx * ny * (unsigned)C.nf;
   for (unsigned k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {

@@ -52,6 +52,7 @@ struct PatchDev {
   int sig_on;        // accumulate the branch signature into cnt->sig
   const unsigned char* mask;  // coverage of the level (bits below)
   const unsigned* halt;       // the context's halt words (HALT_*)
+  const unsigned* skip;       // the problem's skip flag (set: a retake of other problems)
 };
 
 // Coverage byte of a level cell: interior of some patch, and whether the cell
@@ -85,6 +86,7 @@ struct FillPatch {
   int r;
   int coarse_none;            // level 0: walls only
   PhysParams P;
+  const unsigned* skip;       // the problem's skip flag (null: never skipped)
 };
 
 struct CoarsenPatch {
@@ -94,6 +96,7 @@ struct CoarsenPatch {
   int ilo, jlo, bnx, bny, r;
   PhysParams P;
   const unsigned* halt;
+  const unsigned* skip;
 };
 
 struct FlagLevel {
@@ -131,7 +134,7 @@ struct TilePart {
 // One problem on one level: its control block and counters, spacings, and the
 // ranges of its x- and y-tile partials in the level's partial array.
 struct LevelInfo {
-  int ctl, cnt;
+  int ctl, cnt, prob;
   double dx, dy;
   int x0, nx, y0, ny;
 };
@@ -256,6 +259,7 @@ struct RefluxCell {
   int i, j, dirs, r;
   double cdx, cdy, fdx, fdy;
   PhysParams P;
+  const unsigned* skip;
 };
 __global__ void k_reflux_coarse(const RefluxCell* __restrict__ rc, int n, int parity);
 __global__ void k_reflux_fine(const RefluxCell* __restrict__ rc, int n, int parity);
@@ -275,9 +279,10 @@ struct SliceRed {
 };
 constexpr int AFTER_MAX_SLICES = 32;
 __global__ void k_after_substep(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, const TilePart* parts,
-                                double cflmax, SliceRed* red, unsigned* halt);
+                                double cflmax, SliceRed* red, unsigned* halt, const unsigned* skip);
 __global__ void k_after_combine(LevelCtl* ctls, Counters* cnts, const LevelInfo* infos, int n, int ns,
-                                const SliceRed* __restrict__ red, double cflmax, unsigned* halt);
+                                const SliceRed* __restrict__ red, double cflmax, unsigned* halt,
+                                const unsigned* skip);
 __global__ void k_initial_speed(const SpeedLevel* __restrict__ sl);
 __global__ void k_next_dt(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob, double cfl, int initial,
                           const unsigned* halt);
@@ -293,6 +298,7 @@ struct CopyBox {
   double* dst;
   long long pitch, plane;
   int nx, ny, nf, pad;
+  const unsigned* skip;  // the owning problem's skip flag (null: always copied)
 };
 __global__ void k_copy_boxes(const CopyBox* __restrict__ boxes, unsigned* halt, int mark);
 __global__ void k_set_halt(unsigned* halt, unsigned armed);
@@ -313,6 +319,10 @@ struct MaskBox {
 __global__ void k_mask_boxes(const MaskBox* __restrict__ boxes);
 __global__ void k_copy6(double* lv, long long pitch, long long plane, double* cq, int nx, int ny, int dir);
 __global__ void k_reset_acc(LevelCtl* ctls, const ProbDt* __restrict__ pd, int nprob);
-__global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const double* __restrict__ dt0, int nprob);
+__global__ void k_set_dt0(LevelCtl* ctls, const ProbDt* __restrict__ pd, const double* __restrict__ dt0, int nprob,
+                          const unsigned* skip);
+// Skip flags of problems 0..n-1: set where fail[p] is 0 (the problems a retake
+// leaves alone), cleared where it is 1; fail null clears them all.
+__global__ void k_set_skip(unsigned* skip, const unsigned char* __restrict__ fail, int n);
 
 }  // namespace mlswe

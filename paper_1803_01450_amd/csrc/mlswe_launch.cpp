@@ -112,6 +112,7 @@ int build_reflux(mlswe_ctx* c, int l, std::vector<RefluxCell>& out) {
             R.i = Oi; R.j = Oj; R.dirs = 0; R.r = r;
             R.cdx = Lc.dx; R.cdy = Lc.dy; R.fdx = Lf.dx; R.fdy = Lf.dy;
             R.P = P.P;
+            R.skip = c->skip + p;
             at[o] = (int)out.size();
             out.push_back(R);
           }
@@ -240,7 +241,7 @@ int build_launch(mlswe_ctx* c, int l) {
     LevelH& L = P.L[l];
     LL.li_first[pi] = (int)li.size();
     LevelInfo info;
-    info.ctl = P.ctl0 + l; info.cnt = P.cnt; info.dx = L.dx; info.dy = L.dy;
+    info.ctl = P.ctl0 + l; info.cnt = P.cnt; info.prob = (int)pi; info.dx = L.dx; info.dy = L.dy;
     info.x0 = (int)xt.size(); info.nx = 0; info.y0 = (int)yt.size(); info.ny = 0;  // y0: offset added below
     li.push_back(info);
     if (L.boxes.empty()) continue;
@@ -259,6 +260,7 @@ int build_launch(mlswe_ctx* c, int l) {
         d.sig_on = c->sig_on;
         d.mask = L.mask;
         d.halt = c->halt;
+        d.skip = c->skip + pi;
         pd[par].push_back(d);
       }
       LL.patch_prob.push_back((int)pi);
@@ -286,8 +288,10 @@ int build_launch(mlswe_ctx* c, int l) {
       f.nx = L.nx; f.ny = L.ny;
       f.ilo = b.ilo; f.jlo = b.jlo; f.bnx = b.nx; f.bny = b.ny;
       f.P = P.P;
+      f.skip = c->skip + pi;
       CoarsenPatch cc;
       std::memset(&cc, 0, sizeof cc);
+      cc.skip = c->skip + pi;
       const LevelH* Cl = l > 0 ? &P.L[l - 1] : nullptr;
       if (Cl) {
         f.Bc = Cl->B;
@@ -604,11 +608,11 @@ int launch_after(mlswe_ctx* c, int l, int p0, int p1, int runs) {
   const int slices = std::min(AFTER_MAX_SLICES, std::max(1, LL.max_info_tiles / 8192));
   const LevelInfo* li = LL.li + (size_t)runs * LL.nli + first;
   hipLaunchKernelGGL(k_after_substep, dim3(n, slices), dim3(big ? 1024 : 64), 0, c->stream, c->ctl, c->cnt, li,
-                     LL.parts, c->cfg.cfl_max, LL.red, c->halt);
+                     LL.parts, c->cfg.cfl_max, LL.red, c->halt, c->skip);
   if (slices > 1) {
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL(k_after_combine, dim3((n + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->cnt, li, n, slices,
-                       LL.red, c->cfg.cfl_max, c->halt);
+                       LL.red, c->cfg.cfl_max, c->halt, c->skip);
   }
   HIPCHK(c, hipGetLastError());
   return MLSWE_OK;

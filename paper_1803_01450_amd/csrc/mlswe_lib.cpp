@@ -199,7 +199,7 @@ int mlswe_destroy(mlswe_ctx* c) {
     dfree(LL.rfx); dfree(LL.rfx_reg);
   }
   dfree(c->ctl); dfree(c->cnt); dfree(c->pdt); dfree(c->spd); dfree(c->dt_stage);
-  dfree(c->tickets); dfree(c->halt); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d);
+  dfree(c->tickets); dfree(c->halt); dfree(c->skip); dfree(c->fail_d); dfree(c->ctl_bk); dfree(c->cnt_bk); dfree(c->dt0_d);
   dfree(c->bsegs_d); dfree(c->mboxes_d); dfree(c->rfills_d); dfree(c->flv_d);
   for (auto& bl : c->box_lists) dfree(bl.d);
   dfree(c->ftl_d); dfree(c->tbits_d); dfree(c->lrep_d);
@@ -274,6 +274,14 @@ int mlswe_problem_define(mlswe_ctx* c, int* p_out, double r, int nx0, int ny0, d
     int rc;
     if ((rc = dalloc(c, (void**)&nc, sizeof(LevelCtl) * ncap))) return rc;
     if ((rc = dalloc(c, (void**)&ncn, sizeof(Counters) * ccap))) return rc;
+    if (ccap > c->skip_cap) {
+      unsigned* ns = nullptr;
+      if ((rc = dalloc(c, (void**)&ns, sizeof(unsigned) * ccap))) return rc;
+      HIPCHK(c, hipMemsetAsync(ns, 0, sizeof(unsigned) * ccap, c->stream));
+      dfree(c->skip);
+      c->skip = ns;
+      c->skip_cap = ccap;
+    }
     HIPCHK(c, hipMemsetAsync(nc, 0, sizeof(LevelCtl) * ncap, c->stream));
     HIPCHK(c, hipMemsetAsync(ncn, 0, sizeof(Counters) * ccap, c->stream));
     if (c->ctl) HIPCHK(c, hipMemcpyAsync(nc, c->ctl, sizeof(LevelCtl) * nctl, hipMemcpyDeviceToDevice, c->stream));
