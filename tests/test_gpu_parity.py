@@ -351,6 +351,46 @@ def test_deferred_check_retakes_like_per_step_check(mode):
     A.close(); B.close()
 
 
+@pytest.mark.parametrize("want_dts", [True, False])
+def test_retake_takes_only_failing_problems(want_dts):
+    """A batch in which one problem's step fails the Courant check: checked
+    after every step (want_dts) only that problem is retaken and the others
+    keep their step; in deferred windows the halted step is retaken for all.
+    Either way every problem ends bit for bit as when run alone, and each
+    counts only its own rejections."""
+    say("case: per-problem retake, want_dts", want_dts)
+    specs = [(301, 152, 2e-5), (400, 96, 2e-5), (401, 96, 2e-5)]
+
+    def build(which):
+        S = solver()
+        for k in which:
+            seed, n, tau = specs[k]
+            c = inputs.batch_problem(seed, n)
+            p = S.define(n, n, c["dx"], c["dx"], c["r"], (2,))
+            S.set_bathymetry(p, np.kron(c["B"], np.ones((2, 2))))
+            S.set_state(p, 0, c["q"])
+        return S
+
+    taus = [[s[2], 0.0] for s in specs]
+    G = build(range(3))
+    G.advance(22, 10, taus, mode=1, want_dts=want_dts)
+    rej = [G.counters(p)["rejected"] for p in range(3)]
+    say("rejected in the batch", rej)
+    assert rej[0] >= 1
+    for k in range(3):
+        A = build([k])
+        A.advance(22, 10, [taus[k]], mode=1, want_dts=want_dts)
+        assert A.counters(0)["rejected"] == rej[k], k
+        assert A.counters(0)["t"] == G.counters(k)["t"], k
+        for l in range(2):
+            x, y = G.state(k, l), A.state(0, l)
+            assert np.array_equal(np.isnan(x), np.isnan(y))
+            m = ~np.isnan(x)
+            assert np.array_equal(x[m], y[m]), (k, l)
+        A.close()
+    G.close()
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_coarse_steps_without_host_waits(mode):
     """Between regrids a batched (1) or graph (2) advance with retakes waits for
