@@ -191,7 +191,7 @@ int graph_step(mlswe_ctx* c, int p0, int p1) {
 // Backup (to_bk) or restore of a group's coarse-step start: the patch interiors
 // of its finer levels and the control blocks and counters of its problems, in
 // one launch (a problem whose skip flag is set is left as it is).
-int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt, bool mark) {
+int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, bool mark) {
   // the list depends on the launch data (generation), the direction and the
   // buffer parity of every level: built and uploaded once per combination
   std::vector<char> cur;
@@ -223,8 +223,6 @@ int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt
     };
     static_assert(sizeof(LevelCtl) % sizeof(double) == 0 && sizeof(Counters) % sizeof(double) == 0,
                   "copied as doubles");
-    (void)nctl;
-    (void)ncnt;
     for (int p = p0; p < p1; ++p) {
       ProblemH& P = c->probs[p];
       sk = c->skip + p;
@@ -409,7 +407,7 @@ int retake(mlswe_ctx* c, int p0, int p1, bool together, const StepMark& m, std::
     if ((rc = ensure(c, &c->fail_d, &c->fail_cap, np))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->fail_d, rerun.data(), (size_t)np, hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_set_skip, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->skip + p0, c->fail_d, np);
-    if ((rc = copy_step_start(c, p0, p1, false, nctl, ncnt, false))) return rc;
+    if ((rc = copy_step_start(c, p0, p1, false, false))) return rc;
     if ((rc = ensure(c, &c->dt0_d, &c->dt0_cap, np))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->dt0_d, dt0.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_set_dt0, dim3((np + 63) / 64), dim3(64), 0, c->stream, c->ctl, c->pdt + p0, c->dt0_d, np,
@@ -437,13 +435,13 @@ void counts(const mlswe_ctx* c, int* nctl, int* ncnt) {
 }
 
 // A coarse step of problems [p0, p1) with rejection: when the largest substep
-// Courant number of a problem exceeds cfl_max, every problem of the group is
-// put back (fine-level patch interiors, controls, counters, host bookkeeping;
-// level 0 keeps its input buffer through a step) and the step is retaken, the
-// failing problems with dt scaled by cfl_desired / that number, the others
-// unchanged.  Frames and uncovered cells of the finer levels are refilled or
-// unused before they are read again, so the backup leaves them out.  The check
-// waits for the step (one host round trip per coarse step).
+// Courant number of a problem exceeds cfl_max, that problem is put back
+// (fine-level patch interiors, controls, counters; level 0 keeps its input
+// buffer through a step) and retaken with dt scaled by cfl_desired / that
+// number, while the group's other problems keep their step (retake).  Frames
+// and uncovered cells of the finer levels are refilled or unused before they
+// are read again, so the backup leaves them out.  The check waits for the step
+// (one host round trip per coarse step); retaken reports whether a retake ran.
 int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode, bool* retaken) {
   int rc;
   if (retaken) *retaken = false;
@@ -453,7 +451,7 @@ int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode, bool* retaken) {
   counts(c, &nctl, &ncnt);
   StepMark m;
   if ((rc = mark_step(c, p0, p1, nctl, ncnt, m))) return rc;
-  if ((rc = copy_step_start(c, p0, p1, true, nctl, ncnt, false))) return rc;
+  if ((rc = copy_step_start(c, p0, p1, true, false))) return rc;
   if ((rc = run_step(c, p0, p1, mode))) return rc;
   const LevelCtl* h = nullptr;
   if ((rc = read_controls(c, nctl, false, &h, nullptr))) return rc;
@@ -489,7 +487,7 @@ int deferred_step(mlswe_ctx* c, int mode, std::vector<StepMark>& win) {
   }
   win.emplace_back();
   if ((rc = mark_step(c, 0, np, nctl, ncnt, win.back()))) return rc;
-  if ((rc = copy_step_start(c, 0, np, true, nctl, ncnt, true))) return rc;
+  if ((rc = copy_step_start(c, 0, np, true, true))) return rc;
   return run_step(c, 0, np, mode);
 }
 

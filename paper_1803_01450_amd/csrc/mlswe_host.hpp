@@ -278,7 +278,7 @@ int choose_time_ratios(mlswe_ctx* c);
 int build_all(mlswe_ctx* c);
 int coarse_step(mlswe_ctx* c, int p0, int p1, bool batched);
 int graph_step(mlswe_ctx* c, int p0, int p1);
-int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, int nctl, int ncnt, bool mark);
+int copy_step_start(mlswe_ctx* c, int p0, int p1, bool to_bk, bool mark);
 int step_with_retry(mlswe_ctx* c, int p0, int p1, int mode, bool* retaken = nullptr);
 
 // grow-only device array
