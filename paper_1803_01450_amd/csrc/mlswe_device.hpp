@@ -63,9 +63,43 @@ __device__ __forceinline__ double mdiv(double a, double b) {
 #define MDIV(a, b) mdiv(a, b)
 #define MSQRT(x) msqrt(x)
 #else
-#define MRCP(x) (1.0 / (x))
+// Correctly rounded reciprocal and square root without the operand scaling of
+// the general sequences.  The hardware's divide and square-root sequences scale
+// operands near the ends of the exponent range and patch zeros, infinities and
+// NaNs afterwards; between 2^-767 and 2^1000 that scaling is the identity and
+// the patch never applies, so the refinement steps below (two Newton steps on
+// the reciprocal seed, then one correction by the exact residual, after
+// Markstein; Goldschmidt's coupled iteration for the root, then two residual
+// corrections) give the correctly rounded result, bit for bit that of 1/x and
+// sqrt(x).  Operands outside that range take the general operation.
+__device__ __forceinline__ bool plain_range(double a) { return a >= 0x1p-767 && a <= 0x1p+1000; }
+__device__ __forceinline__ double rcp_cr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(e, r, r);
+  if (__builtin_expect(!plain_range(__builtin_fabs(x)), 0)) r = 1.0 / x;
+  return r;
+}
+__device__ __forceinline__ double sqrt_cr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = y * 0.5;
+  const double r = __builtin_fma(-h, s, 0.5);
+  s = __builtin_fma(s, r, s);
+  double d = __builtin_fma(-s, s, x);
+  h = __builtin_fma(h, r, h);
+  s = __builtin_fma(d, h, s);
+  d = __builtin_fma(-s, s, x);
+  s = __builtin_fma(d, h, s);
+  if (__builtin_expect(!plain_range(x), 0)) s = __builtin_sqrt(x);
+  return s;
+}
+#define MRCP(x) rcp_cr(x)
 #define MDIV(a, b) ((a) / (b))
-#define MSQRT(x) __builtin_sqrt(x)
+#define MSQRT(x) sqrt_cr(x)
 #endif
 
 #define FMA(a, b, c) __builtin_fma(a, b, c)
