@@ -261,32 +261,65 @@ __global__ __launch_bounds__(256) void k_flag_tiles(const FlagTiles* __restrict_
 // as the bit patterns of non-negative doubles.  Block size: a multiple of 64,
 // at most 1024.
 // The end of a (problem, level)'s substep reduction: the Courant check,
-// status bits, speeds and counters from the reduced partials.
-__device__ __forceinline__ void after_tail(LevelCtl* ctls, Counters* cnts, const LevelInfo& I, double sx, double sy,
-                                           double c1, double c2, unsigned long long h, unsigned long long nc,
-                                           unsigned long long rp, unsigned long long nf, double cflmax,
-                                           unsigned* halt) {
+// status bits, speeds and counters from the reduced partials.  The words it
+// reads are loaded together first (tail_load, issued before the partials are
+// reduced) so that the reduction's end waits on one round trip to memory, not
+// on one per read-modify-write.
+struct TailIn {
+  unsigned set, armed;
+  double dt, cmax;
+  int status;
+  unsigned long long acc0, acc1, hyp, nclip, repair;
+  double clip1, clip2;
+};
+
+__device__ __forceinline__ TailIn tail_load(const LevelCtl* ctls, const Counters* cnts, const LevelInfo& I,
+                                            const unsigned* halt) {
+  TailIn t;
+  t.set = halt[HALT_SET];
+  t.armed = halt[HALT_ARMED];
+  const LevelCtl& C = ctls[I.ctl];
+  t.dt = C.dt;
+  t.cmax = C.cmax;
+  t.status = C.status;
+  t.acc0 = C.acc_smax[0];
+  t.acc1 = C.acc_smax[1];
+  const Counters& K = cnts[I.cnt];
+  t.hyp = K.hyp;
+  t.nclip = K.nclip;
+  t.repair = K.repair;
+  t.clip1 = K.clip1;
+  t.clip2 = K.clip2;
+  return t;
+}
+
+__device__ __forceinline__ void after_tail(LevelCtl* ctls, Counters* cnts, const LevelInfo& I, const TailIn& t,
+                                           double sx, double sy, double c1, double c2, unsigned long long h,
+                                           unsigned long long nc, unsigned long long rp, unsigned long long nf,
+                                           double cflmax, unsigned* halt) {
   // a halted window keeps the failing substep's control block and counters
-  if (halt[HALT_SET]) return;
+  if (t.set) return;
   LevelCtl& C = ctls[I.ctl];
   const double ax = sx / I.dx, ay = sy / I.dy;
-  const double courant = C.dt * (ax > ay ? ax : ay);
-  if (halt[HALT_ARMED] && (!(courant <= cflmax) || nf)) halt[HALT_SET] = 1u;
-  if (courant > C.cmax || courant != courant) C.cmax = courant;
-  if (!(courant <= cflmax)) C.status |= STATUS_CFL;
-  if (nf) C.status |= STATUS_NAN;
+  const double courant = t.dt * (ax > ay ? ax : ay);
+  if (t.armed && (!(courant <= cflmax) || nf)) halt[HALT_SET] = 1u;
+  if (courant > t.cmax || courant != courant) C.cmax = courant;
+  int st = t.status;
+  if (!(courant <= cflmax)) st |= STATUS_CFL;
+  if (nf) st |= STATUS_NAN;
+  C.status = st;
   const unsigned long long bx = (unsigned long long)__double_as_longlong(sx);
   const unsigned long long by = (unsigned long long)__double_as_longlong(sy);
   C.last_smax[0] = bx;
   C.last_smax[1] = by;
-  if (bx > C.acc_smax[0]) C.acc_smax[0] = bx;
-  if (by > C.acc_smax[1]) C.acc_smax[1] = by;
+  if (bx > t.acc0) C.acc_smax[0] = bx;
+  if (by > t.acc1) C.acc_smax[1] = by;
   Counters& K = cnts[I.cnt];
-  K.hyp += h;
-  K.nclip += nc;
-  K.repair += rp;
-  if (c1 != 0.0) K.clip1 += c1;
-  if (c2 != 0.0) K.clip2 += c2;
+  K.hyp = t.hyp + h;
+  K.nclip = t.nclip + nc;
+  K.repair = t.repair + rp;
+  if (c1 != 0.0) K.clip1 = t.clip1 + c1;
+  if (c2 != 0.0) K.clip2 = t.clip2 + c2;
 }
 
 // Block (x, y) of a grid of (problems, slices) reduces slice y of problem x's
@@ -300,9 +333,12 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
   __shared__ double red_d[4][16];
   __shared__ unsigned long long red_u[4][16];
   const LevelInfo I = infos[blockIdx.x];
-  if (skip[I.prob]) return;  // a problem a retake leaves alone
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int ns = (int)gridDim.y, sl = (int)blockIdx.y;
+  // the skip flag, the tail's words and the partials are all requested before
+  // the first wait; a problem a retake leaves alone is dropped at the end
+  const unsigned sk = skip[I.prob];
+  const TailIn tin = tail_load(ctls, cnts, I, halt);
   double sx = 0.0, sy = 0.0, c1 = 0.0, c2 = 0.0;
   unsigned long long h = 0, nc = 0, rp = 0, nf = 0;
   const int ntot = I.nx + I.ny, step = blockDim.x;
@@ -349,11 +385,12 @@ __global__ __launch_bounds__(1024) void k_after_substep(LevelCtl* ctls, Counters
     c1 += red_d[2][w]; c2 += red_d[3][w];
     h += red_u[0][w]; nc += red_u[1][w]; rp += red_u[2][w]; nf += red_u[3][w];
   }
+  if (sk) return;  // a problem a retake leaves alone
   if (ns > 1) {
     red[(size_t)blockIdx.x * ns + sl] = SliceRed{sx, sy, c1, c2, h, nc, rp, nf};
     return;
   }
-  after_tail(ctls, cnts, I, sx, sy, c1, c2, h, nc, rp, nf, cflmax, halt);
+  after_tail(ctls, cnts, I, tin, sx, sy, c1, c2, h, nc, rp, nf, cflmax, halt);
 }
 
 // One thread per problem: its ns slice results combined in slice order, then
@@ -362,7 +399,10 @@ __global__ void k_after_combine(LevelCtl* ctls, Counters* cnts, const LevelInfo*
                                 const SliceRed* __restrict__ red, double cflmax, unsigned* halt,
                                 const unsigned* skip) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || skip[infos[i].prob]) return;
+  if (i >= n) return;
+  const LevelInfo I = infos[i];
+  const unsigned sk = skip[I.prob];
+  const TailIn tin = tail_load(ctls, cnts, I, halt);
   const SliceRed* R = red + (size_t)i * ns;
   double sx = R[0].sx, sy = R[0].sy, c1 = R[0].c1, c2 = R[0].c2;
   unsigned long long h = R[0].h, nc = R[0].nc, rp = R[0].rp, nf = R[0].nf;
@@ -372,7 +412,8 @@ __global__ void k_after_combine(LevelCtl* ctls, Counters* cnts, const LevelInfo*
     c1 += R[k].c1; c2 += R[k].c2;
     h += R[k].h; nc += R[k].nc; rp += R[k].rp; nf += R[k].nf;
   }
-  after_tail(ctls, cnts, infos[i], sx, sy, c1, c2, h, nc, rp, nf, cflmax, halt);
+  if (sk) return;
+  after_tail(ctls, cnts, I, tin, sx, sy, c1, c2, h, nc, rp, nf, cflmax, halt);
 }
 
 // Largest initial signal speed max(|u|,|v|) + sqrt(g (h1 + h2)) over covered cells.
