@@ -6,6 +6,10 @@ namespace mlswe {
 
 constexpr int XOFF = 8;         // column offset of interior column 0 within a row
 constexpr int XTILE_COLS = 60;  // interior columns per x-sweep wave (64 lanes - 4 halo)
+// Waves per block of the one-wave-per-tile sweep kernels.  The waves share
+// nothing, and a block's LDS is released only when all its waves are done, so
+// smaller blocks let a finished tile's slot take the next tile at once.
+constexpr int LEAN_WAVES = 1;
 constexpr int STATUS_CFL = 1;
 constexpr int STATUS_NAN = 2;
 

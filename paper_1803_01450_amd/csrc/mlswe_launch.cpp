@@ -505,15 +505,18 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
     const int g = std::max(1, mult) * c->ncu;
     return std::min(need, g);
   };
+  // the lean kernels: LEAN_WAVES waves (tiles) per block
+  const dim3 lean_block(64 * LEAN_WAVES);
+  auto lean_grid = [&](int ntiles) { return dim3((unsigned)(((ntiles + LEAN_WAVES - 1) / LEAN_WAVES + 7) / 8 * 8)); };
   if ((sx == 2 && nxt > 0) || (sy == 2 && nyt > 0))
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->tickets, 2);
   if (nxt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
     if (rx)
-      hipLaunchKernelGGL(c->tune.fast ? k_sweep_xr_fast : k_sweep_xr, dim3(grid_of(nxt, 0, 0)), dim3(256), 0,
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_xr_fast : k_sweep_xr, lean_grid(nxt), lean_block, 0,
                          c->stream, LL.pd[parity], LL.xt + xt0, nxt, LL.parts + xt0);
     else if (sx == 0 && !c->sig_on)  // one wave per tile, no signature: the lean kernels
-      hipLaunchKernelGGL(c->tune.fast ? k_sweep_x1_fast : k_sweep_x1, dim3(grid_of(nxt, 0, 0)), dim3(256), 0,
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_x1_fast : k_sweep_x1, lean_grid(nxt), lean_block, 0,
                          c->stream, LL.pd[parity], LL.xt + xt0, nxt, LL.parts + xt0);
     else
       hipLaunchKernelGGL(c->tune.fast ? k_sweep_x_fast : k_sweep_x, dim3(grid_of(nxt, sx, c->tune.grid_x)), dim3(256),
@@ -527,10 +530,10 @@ int launch_sweeps(mlswe_ctx* c, int l, int parity, int xt0, int nxt, int yt0, in
   if (nyt > 0) {
     if (c->timing && (rc = ev_begin(c, &e0))) return rc;
     if (ry)
-      hipLaunchKernelGGL(c->tune.fast ? k_sweep_yr_fast : k_sweep_yr, dim3(grid_of(nyt, 0, 0)), dim3(256), 0,
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_yr_fast : k_sweep_yr, lean_grid(nyt), lean_block, 0,
                          c->stream, LL.pd[parity], LL.yt + yt0, nyt, LL.parts + LL.nxt + yt0);
     else if (sy == 0 && !c->sig_on)
-      hipLaunchKernelGGL(c->tune.fast ? k_sweep_y1_fast : k_sweep_y1, dim3(grid_of(nyt, 0, 0)), dim3(256), 0,
+      hipLaunchKernelGGL(c->tune.fast ? k_sweep_y1_fast : k_sweep_y1, lean_grid(nyt), lean_block, 0,
                          c->stream, LL.pd[parity], LL.yt + yt0, nyt, LL.parts + LL.nxt + yt0);
     else
       hipLaunchKernelGGL(c->tune.fast ? k_sweep_y_fast : k_sweep_y, dim3(grid_of(nyt, sy, c->tune.grid_y)), dim3(256),
