@@ -374,7 +374,10 @@ __device__ __forceinline__ double corr_coef(const EdgeW& W, int p, double dd, do
   double th = MDIV(dn, on ? dd : 1.0);
   double phi = mc_limiter(th);
   double sg = sv > 0.0 ? 0.5 : -0.5;
-  double as = sv < 0.0 ? 0.0 - sv : sv;
+  // |s| by the sign-clearing operand modifier: it differs from the select
+  // form (-s when s < 0, else s) only at s = -0 (where 1 - nu |s| is 1 either
+  // way) and in a NaN's sign bit
+  double as = __builtin_fabs(sv);
   return on ? (sg * (1.0 - nu * as)) * phi : 0.0;
 }
 

@@ -49,14 +49,18 @@ __device__ __forceinline__ double shdn(double v) {
 }
 __device__ __forceinline__ int shup_i(int v) { return dpp_up_i(v); }
 
-__device__ __forceinline__ CellX shup_cell(const CellX& c) {
+// The surfaces and wet flags are formed again from the moved depths and
+// bathymetry, by the same expressions as load_cell (cheaper than moving them).
+__device__ __forceinline__ CellX shup_cell(const PhysParams& P, const CellX& c) {
   CellX o;
   o.h1 = shup(c.h1); o.m1 = shup(c.m1); o.t1 = shup(c.t1);
   o.h2 = shup(c.h2); o.m2 = shup(c.m2); o.t2 = shup(c.t2); o.B = shup(c.B);
   o.u1 = shup(c.u1); o.w1 = shup(c.w1); o.u2 = shup(c.u2); o.w2 = shup(c.w2);
-  o.s1 = shup(c.s1); o.s2 = shup(c.s2); o.e1 = shup(c.e1); o.e2 = shup(c.e2);
-  int f = shup_i((c.wet1 ? 1 : 0) | (c.wet2 ? 2 : 0));
-  o.wet1 = (f & 1) != 0; o.wet2 = (f & 2) != 0;
+  o.s1 = shup(c.s1); o.s2 = shup(c.s2);
+  o.e2 = o.B + o.h2;
+  o.e1 = o.e2 + o.h1;
+  o.wet1 = o.h1 >= P.hdry;
+  o.wet2 = o.h2 >= P.hdry;
   return o;
 }
 
