@@ -208,6 +208,11 @@ struct mlswe_ctx {
   size_t pin_cap = 0;
   ByteSeg* bsegs_d = nullptr;    // regrid descriptor lists
   int bsegs_cap = 0;
+  // host sides of the regrid's descriptor copies: kept until the next regrid
+  // level, whose flag readback waits for the stream before they are rebuilt
+  std::vector<ByteSeg> rg_segs;
+  std::vector<MaskBox> rg_boxes;
+  std::vector<FillPatch> rg_fills;
   MaskBox* mboxes_d = nullptr;
   int mboxes_cap = 0;
   FillPatch* rfills_d = nullptr;

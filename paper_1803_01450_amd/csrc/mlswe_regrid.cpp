@@ -259,8 +259,10 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
       nbs[k] = cluster_tiles(F.nx, F.ny, c->pin + off[k]);
     }
     std::vector<ByteSeg> keep, clear;
-    std::vector<MaskBox> mb;
-    std::vector<FillPatch> fills;
+    std::vector<MaskBox>& mb = c->rg_boxes;
+    std::vector<FillPatch>& fills = c->rg_fills;
+    mb.clear();
+    fills.clear();
     int maxn = 0, maxbox = 0;
     for (size_t k = 0; k < who.size(); ++k) {
       ProblemH& P = c->probs[who[k]];
@@ -290,7 +292,8 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
     }
     // device: old coverage kept, masks cleared and set, new cells refined
     if ((rc = ensure(c, &c->bsegs_d, &c->bsegs_cap, (int)(2 * keep.size())))) return rc;
-    std::vector<ByteSeg> both(keep);
+    std::vector<ByteSeg>& both = c->rg_segs;
+    both.assign(keep.begin(), keep.end());
     both.insert(both.end(), clear.begin(), clear.end());
     HIPCHK(c, hipMemcpyAsync(c->bsegs_d, both.data(), sizeof(ByteSeg) * both.size(), hipMemcpyHostToDevice, c->stream));
     const unsigned gb = (unsigned)std::min(64, (maxbox + 255) / 256);
@@ -309,9 +312,8 @@ int regrid_group(mlswe_ctx* c, int p0, int p1, const double* tau_all, int nbuf) 
                          c->rfills_d);
     }
     HIPCHK(c, hipGetLastError());
-    // the descriptor lists above are host vectors read by the copies: wait
-    // before they go out of scope (one wait per level of the regrid)
-    HIPCHK(c, host_wait(c));
+    // no wait here: the copies' host sides live in the context until the next
+    // level's flag readback has drained the stream
   }
   return MLSWE_OK;
 }
