@@ -117,7 +117,9 @@ def bench_batch(nprob, steps, stream, modes=("plain", "per_patch", "batched", "g
             S.autotune(None, reps=1)
         S.advance(2, 10, tau, mode=mode)   # initial dt, first regrid, graph capture
         sec, upd = timed_advance(S, nsteps, 10, tau, mode)
-        res = {"seconds": sec, "coarse_steps": nsteps, "cell_updates": upd, "rate": upd / sec}
+        # the multilevel step's rate against the HBM roof at 104 B per cell update
+        res = {"seconds": sec, "coarse_steps": nsteps, "cell_updates": upd, "rate": upd / sec,
+               "hbm_frac": round(upd / sec * BYTES_PER_CELL / HBM_PEAK, 4)}
         if breakdown:
             out["tuning"] = S.tuning()
             out["phases_ms_per_coarse_step"] = phase_breakdown(S, 20, 10, tau, mode)
@@ -173,6 +175,7 @@ def bench_amr(steps, stream, modes=("plain", "batched", "graph", "reflux", "dynr
         sec, upd = timed_advance(S, nsteps, 4, tau, mode)
         fine = [int(b[2]) * int(b[3]) for b in S.patches(p, 2)]
         res = {"seconds": sec, "coarse_steps": nsteps, "cell_updates": upd, "rate": upd / sec,
+               "hbm_frac": round(upd / sec * BYTES_PER_CELL / HBM_PEAK, 4),
                "finest_patches": len(fine), "finest_cells": int(sum(fine)),
                "time_ratios": [int(v) for v in S.time_ratios(p)]}
         if breakdown:
