@@ -57,6 +57,19 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_test_lib(src: str, out: str, verbose: bool = False) -> str:
+    """A test-only shared library from one HIP source that includes the
+    library's device headers (exact-build flags)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [hipcc] + FLAGS + EXACT + ["-I" + CSRC, "-shared", "-x", "hip", src, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     print(LIB)
